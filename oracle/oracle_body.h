@@ -1,0 +1,417 @@
+/*
+ * Body of the CPU oracle, instantiated once per real type by oracle.c with
+ *   R      the real type (double or long double),
+ *   FN(n)  the name mangler (n##_d or n##_ld).
+ * <tgmath.h> makes sqrt/fabs resolve to the variant of R.
+ *
+ * Every query is written as its plain definition (see oracle.c's header):
+ * membership tests, Euclidean distances to the profile's edges, and the
+ * intersection of the flight line with the solid as a set of intervals.
+ */
+
+/* ---------------------------------------------------------------- Contains
+ * Closed-set membership test ("inside/outside checks", section 3.1).      */
+static int FN(contains)(int kind, const double *par, R x, R y, R z)
+{
+    if (kind == OR_BOX)
+        return fabs(x) <= (R)par[0] && fabs(y) <= (R)par[1] && fabs(z) <= (R)par[2];
+    if (kind == OR_TUBE) {
+        R r = sqrt(x * x + y * y);
+        return fabs(z) <= (R)par[2] && r >= (R)par[0] && r <= (R)par[1];
+    }
+    if (kind == OR_CONE) {
+        R dz = par[0];
+        if (fabs(z) > dz) return 0;
+        R f = (z + dz) / (2 * dz);                    /* 0 at -dz, 1 at +dz */
+        R rin = (R)par[1] + ((R)par[3] - (R)par[1]) * f;
+        R rout = (R)par[2] + ((R)par[4] - (R)par[2]) * f;
+        R r = sqrt(x * x + y * y);
+        return r >= rin && r <= rout;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------ Safety
+ * Euclidean distance from p to the boundary of the shape, "the minimum
+ * distance to any boundary" (section 3.1).                                 */
+
+/* Distance from (u, v) to the segment (u0, v0)-(u1, v1) in a plane. */
+static R FN(seg_dist)(R u, R v, R u0, R v0, R u1, R v1)
+{
+    R eu = u1 - u0, ev = v1 - v0;
+    R wu = u - u0, wv = v - v0;
+    R ee = eu * eu + ev * ev;
+    R t = 0;
+    if (ee > 0) {
+        t = (wu * eu + wv * ev) / ee;
+        if (t < 0) t = 0;
+        if (t > 1) t = 1;
+    }
+    R du = wu - t * eu, dv = wv - t * ev;
+    return sqrt(du * du + dv * dv);
+}
+
+static R FN(safety)(int kind, const double *par, R x, R y, R z)
+{
+    if (kind == OR_BOX) {
+        R ax = fabs(x), ay = fabs(y), az = fabs(z);
+        R dx = par[0], dy = par[1], dz = par[2];
+        if (FN(contains)(kind, par, x, y, z)) {
+            /* inside: nearest face */
+            R s = dx - ax;
+            if (dy - ay < s) s = dy - ay;
+            if (dz - az < s) s = dz - az;
+            return s;
+        }
+        /* outside: distance to the solid (equal to the distance to its
+         * surface), per-axis excess */
+        R ex = ax > dx ? ax - dx : 0, ey = ay > dy ? ay - dy : 0, ez = az > dz ? az - dz : 0;
+        return sqrt(ex * ex + ey * ey + ez * ez);
+    }
+    /* Tube and cone are solids of revolution: the nearest boundary point
+     * lies in p's own half-plane, so the distance is the planar distance
+     * from (r, z) to the edges of the profile quadrilateral
+     *   A(rin1, -dz) B(rout1, -dz) C(rout2, +dz) D(rin2, +dz).
+     * An edge on the axis (r = 0) bounds no surface and is skipped. */
+    R rin1, rout1, rin2, rout2, dz;
+    if (kind == OR_TUBE) {
+        rin1 = rin2 = par[0];
+        rout1 = rout2 = par[1];
+        dz = par[2];
+    } else if (kind == OR_CONE) {
+        dz = par[0];
+        rin1 = par[1]; rout1 = par[2];
+        rin2 = par[3]; rout2 = par[4];
+    } else {
+        return -1;
+    }
+    R r = sqrt(x * x + y * y);
+    R best = FN(seg_dist)(r, z, rin1, -dz, rout1, -dz);              /* bottom AB */
+    R s = FN(seg_dist)(r, z, rout1, -dz, rout2, dz);                  /* outer  BC */
+    if (s < best) best = s;
+    s = FN(seg_dist)(r, z, rout2, dz, rin2, dz);                      /* top    CD */
+    if (s < best) best = s;
+    if (!(rin1 == 0 && rin2 == 0)) {
+        s = FN(seg_dist)(r, z, rin2, dz, rin1, -dz);                  /* inner  DA */
+        if (s < best) best = s;
+    }
+    return best;
+}
+
+/* ------------------------------------------------ line-solid intersection
+ * The flight line p + t d meets a solid in a set of closed t-intervals.    */
+typedef struct { R lo, hi; } FN(ival);
+
+/* {t : |z0 + t uz| <= h}. Returns 0 if empty. */
+static int FN(slab)(R z0, R uz, R h, R *lo, R *hi)
+{
+    if (uz == 0) {
+        if (fabs(z0) <= h) { *lo = -INFINITY; *hi = INFINITY; return 1; }
+        return 0;
+    }
+    R t1 = (-h - z0) / uz, t2 = (h - z0) / uz;
+    *lo = t1 < t2 ? t1 : t2;
+    *hi = t1 < t2 ? t2 : t1;
+    return 1;
+}
+
+/* Is the line point at t inside the closed nappe solid
+ * N(a, b) = { sqrt(x^2 + y^2) <= a + b z } ? */
+static int FN(in_nappe)(R a, R b, const R *p, const R *d, R t)
+{
+    R x = p[0] + t * d[0], y = p[1] + t * d[1], z = p[2] + t * d[2];
+    return sqrt(x * x + y * y) <= a + b * z;
+}
+
+/* Line intersected with the convex solid N(a, b): a single closed interval
+ * (maybe unbounded) or empty (returns 0). On the boundary of N the squared
+ * form f(t) = (a + b z(t))^2 - (x(t)^2 + y(t)^2) vanishes, so the line's
+ * crossings are among the real roots of this quadratic; membership is then
+ * decided by testing one interior point of every piece between roots (this
+ * test also rejects the mirror nappe a + b z < 0). */
+static int FN(line_nappe)(R a, R b, const R *p, const R *d, R *lo, R *hi)
+{
+    R w0 = a + b * p[2];
+    R wz = b * d[2];
+    R qa = wz * wz - (d[0] * d[0] + d[1] * d[1]);
+    R qb = 2 * (w0 * wz - (p[0] * d[0] + p[1] * d[1]));
+    R qc = w0 * w0 - (p[0] * p[0] + p[1] * p[1]);
+    R roots[2];
+    int nr = 0;
+    if (qa == 0) {
+        if (qb != 0) roots[nr++] = -qc / qb;
+    } else {
+        R disc = qb * qb - 4 * qa * qc;
+        if (disc == 0) {
+            roots[nr++] = -qb / (2 * qa);
+        } else if (disc > 0) {
+            R sq = sqrt(disc);
+            R q = -(qb + (qb >= 0 ? sq : -sq)) / 2;
+            R r1 = q / qa, r2 = qc / q;
+            roots[0] = r1 < r2 ? r1 : r2;
+            roots[1] = r1 < r2 ? r2 : r1;
+            nr = 2;
+        }
+    }
+    if (nr == 0) {
+        if (FN(in_nappe)(a, b, p, d, 0)) { *lo = -INFINITY; *hi = INFINITY; return 1; }
+        return 0;
+    }
+    /* Pieces between consecutive roots, each with one interior sample; a
+     * root on its own is a piece too (a touching point). */
+    R plo[5], phi[5], smp[5];
+    int np = 0;
+    R first = roots[0], last = roots[nr - 1];
+    plo[np] = -INFINITY; phi[np] = first; smp[np] = first - (1 + fabs(first)); np++;
+    plo[np] = first; phi[np] = first; smp[np] = first; np++;
+    if (nr == 2) {
+        plo[np] = first; phi[np] = last; smp[np] = first + (last - first) / 2; np++;
+        plo[np] = last; phi[np] = last; smp[np] = last; np++;
+    }
+    plo[np] = last; phi[np] = INFINITY; smp[np] = last + (1 + fabs(last)); np++;
+    int found = 0;
+    for (int i = 0; i < np; ++i) {
+        if (!FN(in_nappe)(a, b, p, d, smp[i])) continue;
+        if (!found) { *lo = plo[i]; *hi = phi[i]; found = 1; }
+        else {
+            if (plo[i] < *lo) *lo = plo[i];
+            if (phi[i] > *hi) *hi = phi[i];
+        }
+    }
+    return found;
+}
+
+/* Intersect [lo, hi] with [a, b]; returns 0 if empty. */
+static int FN(cap)(R *lo, R *hi, R a, R b)
+{
+    if (a > *lo) *lo = a;
+    if (b < *hi) *hi = b;
+    return *lo <= *hi;
+}
+
+/* Line intersected with the shape: up to two closed intervals, ascending.
+ * Box: the three slabs intersected (Kay-Kajiya).
+ * Tube and cone: (z-slab  and  outer nappe solid)  minus  the open inner
+ * nappe solid {r < rin(z)}, which is empty when both inner radii are 0.   */
+static int FN(line_shape)(int kind, const double *par, const R *p, const R *d, FN(ival) *out)
+{
+    R lo, hi, a, b;
+    if (kind == OR_BOX) {
+        lo = -INFINITY; hi = INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            if (!FN(slab)(p[i], d[i], (R)par[i], &a, &b)) return 0;
+            if (!FN(cap)(&lo, &hi, a, b)) return 0;
+        }
+        out[0].lo = lo; out[0].hi = hi;
+        return 1;
+    }
+    R dz, ao, bo, ai, bi;
+    int hole;
+    if (kind == OR_TUBE) {
+        dz = par[2];
+        ao = par[1]; bo = 0;
+        ai = par[0]; bi = 0;
+        hole = par[0] != 0;
+    } else if (kind == OR_CONE) {
+        dz = par[0];
+        /* radius at z is linear: r(z) = a + b z with r(-dz) = r1, r(dz) = r2 */
+        ao = ((R)par[2] + (R)par[4]) / 2; bo = ((R)par[4] - (R)par[2]) / (2 * dz);
+        ai = ((R)par[1] + (R)par[3]) / 2; bi = ((R)par[3] - (R)par[1]) / (2 * dz);
+        hole = !(par[1] == 0 && par[3] == 0);
+    } else {
+        return 0;
+    }
+    if (!FN(slab)(p[2], d[2], dz, &lo, &hi)) return 0;
+    if (!FN(line_nappe)(ao, bo, p, d, &a, &b)) return 0;
+    if (!FN(cap)(&lo, &hi, a, b)) return 0;
+    if (!hole || !FN(line_nappe)(ai, bi, p, d, &a, &b)) {
+        out[0].lo = lo; out[0].hi = hi;
+        return 1;
+    }
+    /* [lo, hi] minus the open interval (a, b) */
+    int n = 0;
+    if (lo <= a) { out[n].lo = lo; out[n].hi = hi < a ? hi : a; n++; }
+    if (hi >= b) { out[n].lo = lo > b ? lo : b; out[n].hi = hi; n++; }
+    return n;
+}
+
+/* -------------------------------------------- DistFromOutside / Inside
+ * Distance along the line of flight to enter the shape / to leave it
+ * (section 3.1). A point already inside has DistFromOutside 0; a point
+ * outside has DistFromInside 0. A line that never enters gives OR_BIG.  */
+static R FN(dist_out)(int kind, const double *par, const R *p, const R *d)
+{
+    if (FN(contains)(kind, par, p[0], p[1], p[2])) return 0;
+    FN(ival) iv[2];
+    int n = FN(line_shape)(kind, par, p, d, iv);
+    R best = OR_BIG;
+    for (int i = 0; i < n; ++i) {
+        if (iv[i].hi < 0) continue;
+        R t = iv[i].lo > 0 ? iv[i].lo : 0;
+        if (t < best) best = t;
+    }
+    return best;
+}
+
+static R FN(dist_in)(int kind, const double *par, const R *p, const R *d)
+{
+    if (!FN(contains)(kind, par, p[0], p[1], p[2])) return 0;
+    FN(ival) iv[2];
+    int n = FN(line_shape)(kind, par, p, d, iv);
+    for (int i = 0; i < n; ++i)
+        if (iv[i].lo <= 0 && iv[i].hi >= 0) return iv[i].hi < OR_BIG ? iv[i].hi : OR_BIG;
+    return 0;
+}
+
+/* --------------------------------------------------------------- exports */
+void FN(or_shape_query)(int kind, const double *par, int query, int64_t n,
+                        const double *x, const double *y, const double *z,
+                        const double *ux, const double *uy, const double *uz,
+                        double *out_val, uint8_t *out_in)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        R p[3] = { x[i], y[i], z[i] };
+        if (query == OR_CONTAINS) {
+            out_in[i] = (uint8_t)FN(contains)(kind, par, p[0], p[1], p[2]);
+        } else if (query == OR_SAFETY) {
+            out_val[i] = (double)FN(safety)(kind, par, p[0], p[1], p[2]);
+        } else {
+            R d[3] = { ux[i], uy[i], uz[i] };
+            out_val[i] = (double)(query == OR_DIST_IN ? FN(dist_in)(kind, par, p, d)
+                                                      : FN(dist_out)(kind, par, p, d));
+        }
+    }
+}
+
+/* ------------------------------------------------------------ Navigator
+ * Fig. 1: the step to the next boundary is the smaller of the mother's
+ * distFromInside and, over the daughters, distFromOutside taken in each
+ * daughter's own frame; the hit volume is the one attaining it (-1 for the
+ * mother). Daughter k places its frame at q -> R_k q + T_k + delta_k, so a
+ * mother-frame point p maps back to R_k^T (p - T_k - delta_k).
+ * Ties: mother first, then the lowest daughter index (strict <).
+ * Also returns the gap between the two smallest candidates.              */
+typedef struct {
+    int mother_kind;
+    const double *mother_par;     /* 5 */
+    int nd;
+    const int32_t *kinds;         /* nd */
+    const double *pars;           /* nd x 5 */
+    const double *rots;           /* nd x 9, row-major R */
+    const double *trs;            /* nd x 3 */
+} FN(vol);
+
+static R FN(navigate1)(const FN(vol) *v, const R *p, const R *d, const R *offs,
+                       int32_t *hit, R *gap)
+{
+    R best = FN(dist_in)(v->mother_kind, v->mother_par, p, d);
+    R second = OR_BIG * 2;
+    int32_t h = -1;
+    for (int k = 0; k < v->nd; ++k) {
+        const double *rm = v->rots + 9 * k;
+        R w[3];
+        for (int i = 0; i < 3; ++i)
+            w[i] = p[i] - (R)v->trs[3 * k + i] - (offs ? offs[3 * k + i] : 0);
+        R pl[3], dl[3];
+        for (int j = 0; j < 3; ++j) {           /* (R^T w)_j = sum_i R_ij w_i */
+            pl[j] = (R)rm[0 + j] * w[0] + (R)rm[3 + j] * w[1] + (R)rm[6 + j] * w[2];
+            dl[j] = (R)rm[0 + j] * d[0] + (R)rm[3 + j] * d[1] + (R)rm[6 + j] * d[2];
+        }
+        R s = FN(dist_out)(v->kinds[k], v->pars + 5 * k, pl, dl);
+        if (s < best) { second = best; best = s; h = k; }
+        else if (s < second) second = s;
+    }
+    *hit = h;
+    if (gap) *gap = second - best;
+    return best;
+}
+
+void FN(or_navigate)(int mother_kind, const double *mother_par, int nd,
+                     const int32_t *kinds, const double *pars, const double *rots,
+                     const double *trs, const double *offsets, int64_t n,
+                     const double *x, const double *y, const double *z,
+                     const double *ux, const double *uy, const double *uz,
+                     double *step, int32_t *hit, double *gap)
+{
+    FN(vol) v = { mother_kind, mother_par, nd, kinds, pars, rots, trs };
+    R offs[3 * OR_MAX_DAUGHTERS];
+    if (offsets)
+        for (int i = 0; i < 3 * nd; ++i) offs[i] = offsets[i];
+    for (int64_t i = 0; i < n; ++i) {
+        R p[3] = { x[i], y[i], z[i] }, d[3] = { ux[i], uy[i], uz[i] };
+        R g;
+        step[i] = (double)FN(navigate1)(&v, p, d, offsets ? offs : 0, hit + i, &g);
+        if (gap) gap[i] = (double)g;
+    }
+}
+
+/* --------------------------------------------- adjoint reference (FD)
+ * Central finite differences of phi = gs * s + gh . (o + s d), with s the
+ * navigator step, with respect to the origin o, the direction d and the
+ * offset delta of the hit daughter. A track is flagged non-smooth (mask 0)
+ * when the runner-up gap is below min_gap, when any perturbation changes the
+ * hit volume, when the forward and backward one-sided differences disagree
+ * by more than kink_tol (a kink within the stencil), or when the central
+ * differences at h and 2h disagree by more than 3 * fd_tol (the central
+ * difference's own error is about a third of that disagreement).          */
+static R FN(phi)(const FN(vol) *v, const R *o, const R *d, const R *offs, R gs, const R *gh,
+                 int32_t *hit)
+{
+    R s = FN(navigate1)(v, o, d, offs, hit, 0);
+    return gs * s + gh[0] * (o[0] + s * d[0]) + gh[1] * (o[1] + s * d[1]) + gh[2] * (o[2] + s * d[2]);
+}
+
+void FN(or_navigate_fd)(int mother_kind, const double *mother_par, int nd,
+                        const int32_t *kinds, const double *pars, const double *rots,
+                        const double *trs, const double *offsets, int64_t n,
+                        const double *x, const double *y, const double *z,
+                        const double *ux, const double *uy, const double *uz,
+                        const double *gstep, const double *ghit, double h,
+                        double min_gap, double kink_tol, double fd_tol,
+                        double *g_o, double *g_d, double *g_off, int32_t *hit_out,
+                        uint8_t *mask)
+{
+    FN(vol) v = { mother_kind, mother_par, nd, kinds, pars, rots, trs };
+    R offs[3 * OR_MAX_DAUGHTERS];
+    for (int i = 0; i < 3 * nd; ++i) offs[i] = offsets ? offsets[i] : 0;
+    for (int64_t i = 0; i < n; ++i) {
+        R o[3] = { x[i], y[i], z[i] }, d[3] = { ux[i], uy[i], uz[i] };
+        R gh[3] = { ghit ? ghit[i] : 0, ghit ? ghit[n + i] : 0, ghit ? ghit[2 * n + i] : 0 };
+        R gs = gstep ? gstep[i] : 0;
+        int32_t h0;
+        R gap;
+        FN(navigate1)(&v, o, d, offs, &h0, &gap);
+        hit_out[i] = h0;
+        int ok = gap >= min_gap;
+        R phi0 = FN(phi)(&v, o, d, offs, gs, gh, &h0);
+        R grad[9] = { 0 };
+        int ndof = h0 >= 0 ? 9 : 6;
+        for (int j = 0; j < ndof; ++j) {
+            R val[4];
+            const R mult[4] = { 1, -1, 2, -2 };
+            for (int m = 0; m < 4; ++m) {
+                R oo[3] = { o[0], o[1], o[2] }, dd[3] = { d[0], d[1], d[2] };
+                R *target = j < 3 ? &oo[j] : j < 6 ? &dd[j - 3] : &offs[3 * h0 + (j - 6)];
+                R keep = *target;
+                *target = keep + mult[m] * (R)h;
+                int32_t hh;
+                val[m] = FN(phi)(&v, oo, dd, offs, gs, gh, &hh);
+                *target = keep;
+                if (hh != h0) ok = 0;
+            }
+            R c1 = (val[0] - val[1]) / (2 * (R)h);
+            R c2 = (val[2] - val[3]) / (4 * (R)h);
+            R dp = (val[0] - phi0) / (R)h, dm = (phi0 - val[1]) / (R)h;
+            R scale = fabs(c1) > 1 ? fabs(c1) : 1;
+            if (fabs(dp - dm) > kink_tol * scale) ok = 0;
+            if (fabs(c1 - c2) > 3 * fd_tol * scale) ok = 0;
+            grad[j] = c1;
+        }
+        for (int j = 0; j < 3; ++j) {
+            g_o[j * n + i] = (double)grad[j];
+            g_d[j * n + i] = (double)grad[3 + j];
+            g_off[j * n + i] = (double)grad[6 + j];
+        }
+        mask[i] = (uint8_t)ok;
+    }
+}

@@ -1,0 +1,312 @@
+"""Seeded synthetic workloads: shapes, logical volumes and track baskets.
+
+This module only *draws* inputs. It evaluates none of the shape queries and
+none of the navigator: no Contains, Safety or distance is computed here. Both
+the CPU oracle and the HIP path read the exact arrays it returns.
+
+Everything is drawn from ``numpy.random.default_rng(seed)`` (PCG64), so a
+(workload, seed) pair names one byte-identical input.
+
+Layouts
+-------
+* Tracks: one C-contiguous float64 array of shape (6, n). Rows are
+  x, y, z, ux, uy, uz, i.e. six SoA component arrays. This is the "basket"
+  container of the paper (section 2): the particles of one logical volume,
+  contiguous in memory.
+* Shape: ``(kind, par)`` with ``par`` five float64 values, ROOT-style
+  half-lengths centred on the origin with z as the axis:
+  BOX (dx, dy, dz), TUBE (rmin, rmax, dz), CONE (dz, rmin1, rmax1, rmin2,
+  rmax2), where the "1" radii sit at z = -dz and the "2" radii at z = +dz.
+* Volume: a mother shape and daughters placed by a rotation R (row-major 3x3)
+  and a translation T, so that a daughter-frame point q sits at R q + T in
+  the mother frame (the navigator of section 3, Fig. 1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BOX, TUBE, CONE = 0, 1, 2
+KIND_NAMES = {BOX: "box", TUBE: "tube", CONE: "cone"}
+
+# Shape-suite shapes (parameter order as above).
+SUITE_SHAPES = {
+    BOX: np.array([10.0, 20.0, 30.0, 0.0, 0.0]),
+    TUBE: np.array([5.0, 15.0, 20.0, 0.0, 0.0]),
+    CONE: np.array([20.0, 0.0, 10.0, 5.0, 20.0]),
+}
+
+MOTHER_HALF = 200.0
+
+
+def isotropic(rng: np.random.Generator, n: int):
+    """Unit directions with cos(theta) ~ U[-1, 1] and phi ~ U[0, 2 pi)."""
+    ct = rng.uniform(-1.0, 1.0, n)
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    return st * np.cos(ph), st * np.sin(ph), ct
+
+
+def pack_tracks(x, y, z, ux, uy, uz) -> np.ndarray:
+    return np.ascontiguousarray(np.stack([x, y, z, ux, uy, uz]).astype(np.float64))
+
+
+@dataclass
+class Volume:
+    """A logical volume: mother shape plus placed daughters."""
+
+    mother_kind: int
+    mother_par: np.ndarray                     # (5,)
+    kinds: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))   # (nd,)
+    pars: np.ndarray = field(default_factory=lambda: np.zeros((0, 5)))       # (nd, 5)
+    rots: np.ndarray = field(default_factory=lambda: np.zeros((0, 9)))       # (nd, 9) row-major R
+    trs: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))        # (nd, 3) T
+    bound_r: np.ndarray = field(default_factory=lambda: np.zeros(0))         # (nd,) generator-side bounding radius
+
+    @property
+    def nd(self) -> int:
+        return int(self.kinds.shape[0])
+
+    def normalized(self) -> "Volume":
+        return Volume(int(self.mother_kind),
+                      np.ascontiguousarray(self.mother_par, np.float64).reshape(5),
+                      np.ascontiguousarray(self.kinds, np.int32).reshape(-1),
+                      np.ascontiguousarray(self.pars, np.float64).reshape(-1, 5),
+                      np.ascontiguousarray(self.rots, np.float64).reshape(-1, 9),
+                      np.ascontiguousarray(self.trs, np.float64).reshape(-1, 3),
+                      np.ascontiguousarray(self.bound_r, np.float64).reshape(-1))
+
+
+# ----------------------------------------------------------------------------
+# Shape-suite inputs
+# ----------------------------------------------------------------------------
+
+def box_c0(seed: int = 1000, n: int = 1024):
+    """Box (10, 20, 30): origins uniform in the cube of half-size 60,
+    isotropic directions. Returns (kind, par, tracks)."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-60.0, 60.0, (3, n))
+    u = isotropic(rng, n)
+    return BOX, SUITE_SHAPES[BOX].copy(), pack_tracks(p[0], p[1], p[2], *u)
+
+
+def _sample_in_shape(rng, kind, par, n):
+    """Points uniformly distributed in the shape's volume, by construction
+    (not by a membership test)."""
+    if kind == BOX:
+        return [rng.uniform(-par[i], par[i], n) for i in range(3)]
+    if kind == TUBE:
+        rmin, rmax, dz = par[0], par[1], par[2]
+        z = rng.uniform(-dz, dz, n)
+        r = np.sqrt(rng.uniform(rmin * rmin, rmax * rmax, n))
+        ph = rng.uniform(0.0, 2.0 * np.pi, n)
+        return [r * np.cos(ph), r * np.sin(ph), z]
+    if kind == CONE:
+        dz, rmin1, rmax1, rmin2, rmax2 = par
+        # Radii vary linearly between the end faces; the cross-section area
+        # pi (ro^2 - ri^2) sets the z density. Sample z by acceptance against
+        # the bound max(rmax1, rmax2)^2, then r^2 uniform in the annulus.
+        zs = []
+        need = n
+        bound = max(rmax1, rmax2) ** 2
+        while need > 0:
+            m = 2 * need + 64
+            z = rng.uniform(-dz, dz, m)
+            f = (z + dz) / (2.0 * dz)
+            ro = rmax1 + (rmax2 - rmax1) * f
+            ri = rmin1 + (rmin2 - rmin1) * f
+            acc = rng.uniform(0.0, bound, m) < (ro * ro - ri * ri)
+            zs.append(z[acc][:need])
+            need -= zs[-1].size
+        z = np.concatenate(zs)
+        f = (z + dz) / (2.0 * dz)
+        ro = rmax1 + (rmax2 - rmax1) * f
+        ri = rmin1 + (rmin2 - rmin1) * f
+        r = np.sqrt(rng.uniform(ri * ri, ro * ro))
+        ph = rng.uniform(0.0, 2.0 * np.pi, n)
+        return [r * np.cos(ph), r * np.sin(ph), z]
+    raise ValueError(kind)
+
+
+def shape_suite_c1(kind: int, n: int = 1 << 20, seed: int | None = None):
+    """Shape-suite workload for one shape: half the origins drawn inside the
+    shape, half uniform in the cube of half-size 50 around it (that half is
+    not filtered, so a few percent of it also lands inside), randomly
+    interleaved, isotropic directions. Returns (kind, par, tracks)."""
+    if seed is None:
+        seed = 1100 + kind
+    rng = np.random.default_rng(seed)
+    par = SUITE_SHAPES[kind].copy()
+    n_in = n // 2
+    n_out = n - n_in
+    pin = _sample_in_shape(rng, kind, par, n_in)
+    pout = rng.uniform(-50.0, 50.0, (3, n_out))
+    p = np.concatenate([np.stack(pin), pout], axis=1)
+    perm = rng.permutation(n)
+    p = p[:, perm]
+    u = isotropic(rng, n)
+    return kind, par, pack_tracks(p[0], p[1], p[2], *u)
+
+
+# ----------------------------------------------------------------------------
+# Detector volumes
+# ----------------------------------------------------------------------------
+
+def euler_zxz(phi, theta, psi) -> np.ndarray:
+    """R = Rz(phi) Rx(theta) Rz(psi), row-major 9 values."""
+    def rz(a):
+        c, s = np.cos(a), np.sin(a)
+        return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+    def rx(a):
+        c, s = np.cos(a), np.sin(a)
+        return np.array([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]])
+
+    return (rz(phi) @ rx(theta) @ rz(psi)).reshape(9)
+
+
+def _draw_daughter(rng, kind):
+    """Sizes uniform in [5, 20]; inner radii U[0, 0.75] * outer, set to 0
+    with probability 1/4. Returns (par, bounding radius about the centre)."""
+    if kind == BOX:
+        d = rng.uniform(5.0, 20.0, 3)
+        return np.array([d[0], d[1], d[2], 0.0, 0.0]), float(np.sqrt((d * d).sum()))
+
+    def inner(rmax):
+        r = rng.uniform(0.0, 0.75) * rmax
+        return 0.0 if rng.uniform() < 0.25 else r
+
+    if kind == TUBE:
+        rmax = rng.uniform(5.0, 20.0)
+        dz = rng.uniform(5.0, 20.0)
+        rmin = inner(rmax)
+        return np.array([rmin, rmax, dz, 0.0, 0.0]), float(np.hypot(rmax, dz))
+    if kind == CONE:
+        dz = rng.uniform(5.0, 20.0)
+        rmax1 = rng.uniform(5.0, 20.0)
+        rmax2 = rng.uniform(5.0, 20.0)
+        rmin1 = inner(rmax1)
+        rmin2 = inner(rmax2)
+        return (np.array([dz, rmin1, rmax1, rmin2, rmax2]),
+                float(np.hypot(max(rmax1, rmax2), dz)))
+    raise ValueError(kind)
+
+
+def _place_daughters(rng, centres, cell_half):
+    nd = len(centres)
+    kinds = np.array([i % 3 for i in range(nd)], np.int32)
+    pars = np.zeros((nd, 5))
+    rots = np.zeros((nd, 9))
+    trs = np.zeros((nd, 3))
+    bound = np.zeros(nd)
+    for i in range(nd):
+        par, rb = _draw_daughter(rng, int(kinds[i]))
+        ang = rng.uniform(0.0, 1.0, 3) * np.array([2 * np.pi, np.pi, 2 * np.pi])
+        jit = cell_half - rb
+        assert jit > 0.0
+        pars[i] = par
+        rots[i] = euler_zxz(*ang)
+        trs[i] = np.asarray(centres[i], float) + rng.uniform(-jit, jit, 3)
+        bound[i] = rb
+    return kinds, pars, rots, trs, bound
+
+
+def toy_detector_volume(seed: int = 1200) -> Volume:
+    """Mother box (200, 200, 200) holding 32 daughters on a 4 x 4 x 2 grid of
+    cells (x, y centres at +-50, +-150; z centres at +-100). Daughter i has
+    kind i mod 3, a ZXZ rotation with uniformly drawn Euler angles and a
+    jittered cell-centre translation. Each daughter's bounding sphere stays
+    inside its 100-wide cell, so daughters cannot overlap."""
+    rng = np.random.default_rng(seed)
+    cs = [-150.0, -50.0, 50.0, 150.0]
+    centres = [(x, y, z) for z in (-100.0, 100.0) for y in cs for x in cs]
+    kinds, pars, rots, trs, bound = _place_daughters(rng, centres, 50.0)
+    return Volume(BOX, np.array([MOTHER_HALF] * 3 + [0.0, 0.0]), kinds, pars, rots, trs, bound)
+
+
+def grid_volume(rng, nd: int) -> Volume:
+    """Mother box (200)^3 with nd daughters in distinct, randomly chosen cells
+    of a 4 x 4 x 4 grid of 100-wide cells, drawn as in the toy detector."""
+    cs = [-150.0, -50.0, 50.0, 150.0]
+    cells = [(x, y, z) for z in cs for y in cs for x in cs]
+    pick = rng.choice(len(cells), size=nd, replace=False)
+    centres = [cells[i] for i in pick]
+    kinds, pars, rots, trs, bound = _place_daughters(rng, centres, 50.0)
+    return Volume(BOX, np.array([MOTHER_HALF] * 3 + [0.0, 0.0]), kinds, pars, rots, trs, bound)
+
+
+def tracks_in_mother(rng, vol: Volume, n: int) -> np.ndarray:
+    """n tracks uniform in the box mother, outside every daughter: an origin
+    is redrawn when it falls in a daughter's bounding sphere (the sphere the
+    placement above keeps inside the daughter's cell). Isotropic directions."""
+    h = vol.mother_par[:3]
+    out = np.empty((3, 0))
+    need = n
+    while need > 0:
+        m = int(need * 1.15) + 1024
+        p = rng.uniform(-1.0, 1.0, (3, m)) * h[:, None]
+        ok = np.ones(m, bool)
+        for k in range(vol.nd):
+            d = p - vol.trs[k][:, None]
+            ok &= (d * d).sum(axis=0) > vol.bound_r[k] ** 2
+        p = p[:, ok][:, :need]
+        out = np.concatenate([out, p], axis=1)
+        need = n - out.shape[1]
+    u = isotropic(rng, n)
+    return pack_tracks(out[0], out[1], out[2], *u)
+
+
+def toy_detector_c2(seed: int = 1200, n: int = 1 << 22):
+    """Toy-detector navigator workload: the 32-daughter volume and n tracks.
+    Returns (volume, tracks)."""
+    vol = toy_detector_volume(seed)
+    rng = np.random.default_rng(seed + 1)
+    return vol, tracks_in_mother(rng, vol, n)
+
+
+@dataclass
+class BatchedWorkload:
+    volumes: list            # list[Volume]
+    basket_volume: np.ndarray  # (nb,) int32
+    basket_offset: np.ndarray  # (nb,) int64, into the track pool
+    basket_n: np.ndarray       # (nb,) int64
+    tracks: np.ndarray         # (6, sum n) pool
+
+
+def batched_c3(seed: int = 1300, nvol: int = 64, nb: int = 512,
+               nmin: int = 32, nmax: int = 65536, scale: float = 1.0) -> BatchedWorkload:
+    """Batched workload: nvol volumes (mother box (200)^3, 1..64 daughters
+    each, uniform), nb baskets with volume = b mod nvol and size
+    floor(nmin * (nmax / nmin)^u), u ~ U[0, 1) (log-uniform). The track pool
+    is the concatenation of the baskets. ``scale`` shrinks every basket
+    (at least one track) for small test cases."""
+    rng = np.random.default_rng(seed)
+    vols = []
+    for _ in range(nvol):
+        nd = int(rng.integers(1, 65))
+        vols.append(grid_volume(rng, nd))
+    u = rng.uniform(0.0, 1.0, nb)
+    sizes = np.floor(nmin * (nmax / nmin) ** u).astype(np.int64)
+    if scale != 1.0:
+        sizes = np.maximum(1, np.floor(sizes * scale).astype(np.int64))
+    bvol = (np.arange(nb) % nvol).astype(np.int32)
+    offs = np.zeros(nb, np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    parts = []
+    for b in range(nb):
+        parts.append(tracks_in_mother(rng, vols[bvol[b]], int(sizes[b])))
+    pool = np.ascontiguousarray(np.concatenate(parts, axis=1))
+    return BatchedWorkload(vols, bvol, offs, sizes, pool)
+
+
+def adjoint_c4(seed: int = 1400, n: int = 1 << 20, detector_seed: int = 1200):
+    """Adjoint workload: the toy detector (same geometry as the navigator
+    workload), n tracks, and target points uniform in the mother.
+    Returns (volume, tracks, targets (3, n))."""
+    vol = toy_detector_volume(detector_seed)
+    rng = np.random.default_rng(seed)
+    tracks = tracks_in_mother(rng, vol, n)
+    rng_t = np.random.default_rng(seed + 1)
+    targets = np.ascontiguousarray(rng_t.uniform(-MOTHER_HALF, MOTHER_HALF, (3, n)))
+    return vol, tracks, targets
