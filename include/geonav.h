@@ -1,0 +1,183 @@
+/*
+ * geonav — basket-wide geometry queries and the simple vector navigator on
+ * AMD MI355X (gfx950), after "Vectorising the detector geometry to optimize
+ * particle transport" (Apostolakis, Brun, Carminati, Gheata, Wenzel).
+ *
+ * C ABI of libgeonav.so. All functions return an int status (GEO_OK or a
+ * negative GEO_ERR_*); no C++ exception crosses this boundary. Computation is
+ * FP64 throughout.
+ *
+ * Memory and ownership
+ *   - Track arrays and output arrays are DEVICE pointers owned by the caller,
+ *     8-byte aligned (4 for int32 outputs, 1 for uint8), not aliasing each
+ *     other. Every call is asynchronous on the given stream; the caller keeps
+ *     the buffers alive until the stream has passed the call.
+ *   - Descriptor structs (geo_shape, geo_volume_desc, geo_basket arrays) are
+ *     HOST memory, read during the call only.
+ *   - A geo_geometry handle owns device copies of its volumes.
+ *
+ * Conventions (section 3.1 names the shapes and queries; the parameter
+ * conventions below follow ROOT-style half-lengths, centred on the origin,
+ * z as the symmetry axis):
+ *   GEO_BOX  par = {dx, dy, dz}                          |x|<=dx, |y|<=dy, |z|<=dz
+ *   GEO_TUBE par = {rmin, rmax, dz}                      rmin<=r<=rmax, |z|<=dz
+ *   GEO_CONE par = {dz, rmin1, rmax1, rmin2, rmax2}      radii "1" at z=-dz and
+ *            "2" at z=+dz, varying linearly in z
+ *   Shapes are closed sets. Directions are not renormalised: distances are
+ *   the ray parameter t of p + t*d (the length when |d| = 1).
+ *   A line that never reaches the boundary gives GEO_BIG.
+ */
+#ifndef GEONAV_H
+#define GEONAV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEO_BIG 1e30
+#define GEO_MAX_DAUGHTERS 1024
+
+enum { GEO_BOX = 0, GEO_TUBE = 1, GEO_CONE = 2 };
+
+/* Queries of section 3.1: inside/outside check, minimum distance to any
+ * boundary, distance along the line of flight to leave / to enter. */
+enum { GEO_CONTAINS = 0, GEO_SAFETY = 1, GEO_DIST_IN = 2, GEO_DIST_OUT = 3 };
+
+enum {
+    GEO_OK = 0,
+    GEO_ERR_INVALID_ARG = -1, /* bad pointer, size, kind, query, volume, shape or alignment */
+    GEO_ERR_HIP = -2,         /* a HIP runtime call failed; geo_strerror gives its message */
+    GEO_ERR_NOMEM = -3        /* a device or pinned host allocation failed */
+};
+
+/* A basket (section 2): the tracks of one logical volume as six SoA device
+ * arrays of length n (origin x, y, z and direction ux, uy, uz). */
+typedef struct {
+    const double *x, *y, *z, *ux, *uy, *uz;
+    int64_t n;
+} geo_tracks;
+
+typedef struct {
+    int32_t kind; /* GEO_BOX, GEO_TUBE or GEO_CONE */
+    int32_t _pad;
+    double par[5];
+} geo_shape;
+
+/* Placement of a daughter in its mother (the coordinate transformations of
+ * section 3.1): a daughter-frame point q is at rot * q + tr in the mother
+ * frame. rot is row-major and must be a proper rotation (orthonormal to
+ * 1e-12, determinant +1). */
+typedef struct {
+    double rot[9];
+    double tr[3];
+} geo_placement;
+
+/* A logical volume (Fig. 1): a mother shape and its placed daughters. */
+typedef struct {
+    geo_shape mother;
+    int32_t ndaughters; /* 0 .. GEO_MAX_DAUGHTERS */
+    int32_t _pad;
+    const geo_shape *daughters;      /* host, ndaughters */
+    const geo_placement *placements; /* host, ndaughters */
+} geo_volume_desc;
+
+/* A basket of the batched call: n tracks of volume `volume` starting at
+ * `offset` in the shared track pool. */
+typedef struct {
+    int32_t volume;
+    int32_t _pad;
+    int64_t offset;
+    int64_t n;
+} geo_basket;
+
+typedef struct geo_geometry geo_geometry;
+
+/* Copy nvol volumes to the current device and return a handle.
+ * Validation: kinds known, parameters finite, box half-lengths > 0,
+ * 0 <= rmin <= rmax with rmax > 0 (cone: at both ends, rmax1 + rmax2 > 0),
+ * dz > 0, rotations proper to 1e-12. Errors: GEO_ERR_INVALID_ARG,
+ * GEO_ERR_NOMEM, GEO_ERR_HIP; *out is NULL on error. */
+int geo_geometry_create(const geo_volume_desc *volumes, int32_t nvol, geo_geometry **out);
+
+/* Release the handle and its device memory. Synchronises the device first.
+ * NULL is a no-op. */
+int geo_geometry_destroy(geo_geometry *g);
+
+/* Shape queries of section 3.1 over a whole basket: one launch evaluates
+ * `query` for the shape `s` (host struct, in its own frame) at every track.
+ * out: uint8_t[n] (GEO_CONTAINS: 1 inside, 0 outside) or double[n]
+ * (GEO_SAFETY: Euclidean distance to the surface; GEO_DIST_IN: distance to
+ * leave, 0 for a point outside; GEO_DIST_OUT: distance to enter, 0 for a
+ * point inside). Contains and Safety ignore ux, uy, uz (they may be NULL).
+ * n == 0 is a no-op. */
+int geo_shape_query(const geo_shape *s, int32_t query, geo_tracks t, void *out, hipStream_t stream);
+
+/* The simple navigator of section 3 (Fig. 1b) over one basket of `volume`:
+ *   step[i] = min( DistFromInside_mother(p_i, d_i),
+ *                  min_k DistFromOutside_k(R_k^T (p_i - T_k - delta_k), R_k^T d_i) )
+ *   hit[i]  = -1 if the mother attains it, else the daughter index k;
+ *            ties go to the mother, then to the lowest k.
+ * offsets: device double[ndaughters * 3] (delta_k, x/y/z per daughter) or
+ * NULL for zero. hitpt: device double[3 * n] (SoA rows x, y, z of
+ * p + step * d) or NULL. Tracks should start inside the mother and outside
+ * every daughter (section 3.2's benchmark protocol); a track inside daughter
+ * k gets step 0 (hit = the first such k), a track outside the mother gets
+ * step 0 and hit -1. */
+int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                        double *step, int32_t *hit, double *hitpt, hipStream_t stream);
+
+/* Many baskets of possibly different volumes in ONE persistent launch
+ * (replayed from a cached HIP graph). baskets: host array of nb entries
+ * indexing into the shared pool `all`; step and hit are indexed like the
+ * pool (entry offset + j for track j of a basket); pool entries not covered
+ * by any basket are left untouched. Results are bit-identical to
+ * geo_navigate_basket on each basket with offsets = NULL.
+ * The handle keeps per-call state (tile list, graph): calls on one handle
+ * must not run concurrently from several host threads; stream order is
+ * respected. */
+int geo_navigate_batched(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
+                         double *step, int32_t *hit, hipStream_t stream);
+
+/* Adjoint of the navigator for one basket (recomputes the forward pass, then
+ * differentiates the surface that determined each step, by the implicit-
+ * function theorem on that surface). With upstream gradients gstep (double[n]
+ * or NULL = 0) for the step and ghit (double[3 * n] SoA or NULL = 0) for the
+ * hit point h = p + step * d, it writes
+ *   g_o   (double[3 * n] SoA, or NULL to skip): d/dp of sum_i gstep_i s_i + ghit_i . h_i
+ *   g_d   (double[3 * n] SoA, or NULL to skip): d/dd of the same
+ *   g_off (double[ndaughters * 3], or NULL to skip): d/d delta_k summed over
+ *         the basket; overwritten, deterministic (fixed reduction order).
+ * Tracks whose step is 0 (outside the mother or inside a daughter) or that
+ * never reach a boundary contribute 0. At a non-smooth point (an edge, a tie
+ * between volumes) the gradient of the surface the forward pass picked is
+ * used. Calls on one handle share a partial-sum buffer: they must be
+ * stream-ordered (no concurrent backward calls on one handle). */
+int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                          const double *gstep, const double *ghit, double *g_o, double *g_d,
+                          double *g_off, hipStream_t stream);
+
+/* Time the candidate launch shapes of the batched kernel (tile size, waves
+ * per SIMD) on these baskets and keep the fastest in the handle; also records
+ * it in the JSON cache named by the GEONAV_AUTOTUNE_CACHE environment
+ * variable, if set. Writes step/hit scratch internally; synchronises the
+ * stream. */
+int geo_autotune(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
+                 hipStream_t stream);
+
+/* The batched launch shape currently used by the handle. */
+int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd);
+/* Force a launch shape (tracks_per_lane in {1, 2, 4}, waves_per_simd 1..8). */
+int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd);
+
+/* Message for a status code; for the most recent failure on the calling
+ * thread it includes that failure's detail. Never NULL. */
+const char *geo_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEONAV_H */

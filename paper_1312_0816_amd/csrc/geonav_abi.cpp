@@ -1,0 +1,688 @@
+// C ABI of libgeonav: argument validation, the geometry handle (device copies
+// of the volumes with host-derived shape constants), the batched scheduler
+// (cost-sorted baskets, device-side tile expansion, a cached HIP graph), the
+// launch-shape autotuner and error reporting.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "geonav.h"
+#include "geonav_internal.hpp"
+
+using namespace gn;
+
+namespace {
+
+thread_local std::string g_last_msg;
+thread_local int g_last_code = 0;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_msg = buf;
+    g_last_code = code;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(GEO_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GN_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+bool finite5(const double *p) {
+    for (int i = 0; i < 5; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Validate a shape and derive its device record.
+int make_shape(const geo_shape &s, ShapeRec &out, double *bound_r, const char *what) {
+    std::memset(&out, 0, sizeof out);
+    if (!finite5(s.par)) return fail(GEO_ERR_INVALID_ARG, "%s: non-finite shape parameter", what);
+    const double *p = s.par;
+    out.kind = s.kind;
+    switch (s.kind) {
+        case GEO_BOX:
+            if (!(p[0] > 0 && p[1] > 0 && p[2] > 0))
+                return fail(GEO_ERR_INVALID_ARG, "%s: box half-lengths must be > 0", what);
+            out.c[0] = p[0];
+            out.c[1] = p[1];
+            out.c[2] = p[2];
+            if (bound_r) *bound_r = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+            return GEO_OK;
+        case GEO_TUBE:
+            if (!(p[0] >= 0 && p[1] > 0 && p[0] <= p[1] && p[2] > 0))
+                return fail(GEO_ERR_INVALID_ARG, "%s: tube needs 0 <= rmin <= rmax, rmax > 0, dz > 0",
+                            what);
+            out.hole = p[0] > 0 ? 1 : 0;
+            out.c[0] = p[0];
+            out.c[1] = p[1];
+            out.c[2] = p[2];
+            out.c[3] = p[0] * p[0];
+            out.c[4] = p[1] * p[1];
+            if (bound_r) *bound_r = std::sqrt(p[1] * p[1] + p[2] * p[2]);
+            return GEO_OK;
+        case GEO_CONE: {
+            const double dz = p[0], rmin1 = p[1], rmax1 = p[2], rmin2 = p[3], rmax2 = p[4];
+            if (!(dz > 0 && rmin1 >= 0 && rmin2 >= 0 && rmin1 <= rmax1 && rmin2 <= rmax2 &&
+                  rmax1 + rmax2 > 0))
+                return fail(GEO_ERR_INVALID_ARG,
+                            "%s: cone needs dz > 0, 0 <= rmin <= rmax at both ends, rmax1 + rmax2 > 0",
+                            what);
+            out.hole = (rmin1 > 0 || rmin2 > 0) ? 1 : 0;
+            const double bo = (rmax2 - rmax1) / (2 * dz), bi = (rmin2 - rmin1) / (2 * dz);
+            out.c[0] = dz;
+            out.c[1] = 0.5 * (rmax1 + rmax2);
+            out.c[2] = bo;
+            out.c[3] = 0.5 * (rmin1 + rmin2);
+            out.c[4] = bi;
+            out.c[5] = rmin1;
+            out.c[6] = rmax1;
+            out.c[7] = rmin2;
+            out.c[8] = rmax2;
+            out.c[9] = rmin1 * rmin1;
+            out.c[10] = rmax1 * rmax1;
+            out.c[11] = rmin2 * rmin2;
+            out.c[12] = rmax2 * rmax2;
+            out.c[13] = 1.0 / std::sqrt(1.0 + bo * bo);
+            out.c[14] = 1.0 / std::sqrt(1.0 + bi * bi);
+            out.c[15] = 1.0 / ((rmax2 - rmax1) * (rmax2 - rmax1) + 4 * dz * dz);
+            out.c[16] = 1.0 / ((rmin2 - rmin1) * (rmin2 - rmin1) + 4 * dz * dz);
+            if (bound_r) {
+                const double rm = std::max(rmax1, rmax2);
+                *bound_r = std::sqrt(rm * rm + dz * dz);
+            }
+            return GEO_OK;
+        }
+        default:
+            return fail(GEO_ERR_INVALID_ARG, "%s: unknown shape kind %d", what, s.kind);
+    }
+}
+
+int check_rotation(const double *r, const char *what) {
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(r[i])) return fail(GEO_ERR_INVALID_ARG, "%s: non-finite rotation", what);
+    double worst = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += r[3 * k + i] * r[3 * k + j];
+            worst = std::max(worst, std::fabs(s - (i == j ? 1.0 : 0.0)));
+        }
+    const double det = r[0] * (r[4] * r[8] - r[5] * r[7]) - r[1] * (r[3] * r[8] - r[5] * r[6]) +
+                       r[2] * (r[3] * r[7] - r[4] * r[6]);
+    if (worst > 1e-12 || det <= 0)
+        return fail(GEO_ERR_INVALID_ARG, "%s: rotation not proper orthonormal (|R^T R - I| = %g, det = %g)",
+                    what, worst, det);
+    return GEO_OK;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_tracks(const geo_tracks &t, bool need_dir, const char *what) {
+    if (t.n < 0) return fail(GEO_ERR_INVALID_ARG, "%s: n < 0", what);
+    if (t.n == 0) return GEO_OK;
+    const double *ps[6] = {t.x, t.y, t.z, t.ux, t.uy, t.uz};
+    for (int i = 0; i < (need_dir ? 6 : 3); ++i) {
+        if (!ps[i]) return fail(GEO_ERR_INVALID_ARG, "%s: NULL track array with n > 0", what);
+        if (!aligned(ps[i], 8)) return fail(GEO_ERR_INVALID_ARG, "%s: track array not 8-byte aligned", what);
+    }
+    return GEO_OK;
+}
+
+int check_out(const void *p, size_t align, const char *what) {
+    if (!p) return fail(GEO_ERR_INVALID_ARG, "%s is NULL", what);
+    if (!aligned(p, align)) return fail(GEO_ERR_INVALID_ARG, "%s is misaligned", what);
+    return GEO_OK;
+}
+
+int check_opt(const void *p, size_t align, const char *what) {
+    if (p && !aligned(p, align)) return fail(GEO_ERR_INVALID_ARG, "%s is misaligned", what);
+    return GEO_OK;
+}
+
+TracksDev to_dev(const geo_tracks &t) { return TracksDev{t.x, t.y, t.z, t.ux, t.uy, t.uz, t.n}; }
+
+}  // namespace
+
+// ------------------------------------------------------------ the handle
+struct geo_geometry {
+    int device = 0;
+    int num_cus = 0;
+    std::string device_name;
+    int nvol = 0;
+    int max_nd = 0;
+    std::vector<VolumeRec> h_vols;
+    VolumeRec *d_vols = nullptr;
+    DaughterRec *d_dau = nullptr;
+    // adjoint partial sums: kBackwardMaxBlocks x 3 x max_nd
+    double *d_partial = nullptr;
+    // batched state
+    int tracks_per_lane = 2;
+    int waves_per_simd = 4;
+    BasketRec *h_baskets = nullptr;  // pinned staging: nb baskets then nb + 1 tile starts
+    size_t h_cap = 0;                // bytes
+    void *d_bstage = nullptr;        // device copy of the staging block
+    size_t d_bcap = 0;
+    Tile *d_tiles = nullptr;
+    int64_t tiles_cap = 0;
+    unsigned int *d_cursor = nullptr;
+    hipEvent_t staged = nullptr;     // the last upload from h_baskets has completed
+    bool staged_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node_build = nullptr, node_nav = nullptr;
+    int graph_U = 0, graph_grid = 0;
+    std::vector<BasketRec> sorted;   // reused host scratch
+};
+
+namespace {
+
+void destroy_graph(geo_geometry *g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->exec = nullptr;
+    g->graph = nullptr;
+    g->node_build = g->node_nav = nullptr;
+    g->graph_U = g->graph_grid = 0;
+}
+
+int check_device(const geo_geometry *g) {
+    int dev = -1;
+    GN_HIP(hipGetDevice(&dev));
+    if (dev != g->device)
+        return fail(GEO_ERR_INVALID_ARG, "geometry lives on device %d but device %d is current", g->device,
+                    dev);
+    return GEO_OK;
+}
+
+}  // namespace
+
+// Entry points keep the C linkage of their declarations in geonav.h.
+
+const char *geo_strerror(int status) {
+    if (status != GEO_OK && status == g_last_code && !g_last_msg.empty()) return g_last_msg.c_str();
+    switch (status) {
+        case GEO_OK: return "success";
+        case GEO_ERR_INVALID_ARG: return "invalid argument";
+        case GEO_ERR_HIP: return "HIP runtime error";
+        case GEO_ERR_NOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **out) {
+    if (!out) return fail(GEO_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nvol <= 0 || !v) return fail(GEO_ERR_INVALID_ARG, "need nvol > 0 volumes");
+    std::vector<VolumeRec> vols(nvol);
+    std::vector<DaughterRec> dau;
+    int max_nd = 0;
+    for (int iv = 0; iv < nvol; ++iv) {
+        const geo_volume_desc &d = v[iv];
+        VolumeRec &r = vols[iv];
+        std::memset(&r, 0, sizeof r);
+        char what[64];
+        snprintf(what, sizeof what, "volume %d mother", iv);
+        int rc = make_shape(d.mother, r.mother, nullptr, what);
+        if (rc) return rc;
+        if (d.ndaughters < 0 || d.ndaughters > GEO_MAX_DAUGHTERS)
+            return fail(GEO_ERR_INVALID_ARG, "volume %d: ndaughters %d outside 0..%d", iv, d.ndaughters,
+                        GEO_MAX_DAUGHTERS);
+        if (d.ndaughters > 0 && (!d.daughters || !d.placements))
+            return fail(GEO_ERR_INVALID_ARG, "volume %d: NULL daughter arrays", iv);
+        r.nd = d.ndaughters;
+        r.first = (int32_t)dau.size();
+        max_nd = std::max(max_nd, r.nd);
+        for (int k = 0; k < d.ndaughters; ++k) {
+            DaughterRec dr;
+            std::memset(&dr, 0, sizeof dr);
+            snprintf(what, sizeof what, "volume %d daughter %d", iv, k);
+            rc = make_shape(d.daughters[k], dr.shape, &dr.bound_r, what);
+            if (rc) return rc;
+            rc = check_rotation(d.placements[k].rot, what);
+            if (rc) return rc;
+            for (int i = 0; i < 3; ++i)
+                if (!std::isfinite(d.placements[k].tr[i]))
+                    return fail(GEO_ERR_INVALID_ARG, "%s: non-finite translation", what);
+            std::memcpy(dr.rot, d.placements[k].rot, sizeof dr.rot);
+            std::memcpy(dr.tr, d.placements[k].tr, sizeof dr.tr);
+            dau.push_back(dr);
+        }
+    }
+    geo_geometry *g = new (std::nothrow) geo_geometry();
+    if (!g) return fail(GEO_ERR_NOMEM, "host allocation failed");
+    auto cleanup = [&](int rc) {
+        geo_geometry_destroy(g);
+        return rc;
+    };
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, g->device);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDeviceProperties"));
+    g->num_cus = prop.multiProcessorCount;
+    g->device_name = prop.gcnArchName;
+    g->nvol = nvol;
+    g->max_nd = max_nd;
+    g->h_vols = vols;
+    if (hipMalloc(&g->d_vols, sizeof(VolumeRec) * nvol) != hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of volumes failed"));
+    if (!dau.empty() && hipMalloc(&g->d_dau, sizeof(DaughterRec) * dau.size()) != hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of daughters failed"));
+    if (max_nd > 0 &&
+        hipMalloc(&g->d_partial, sizeof(double) * 3 * (size_t)max_nd * kBackwardMaxBlocks) != hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of adjoint partials failed"));
+    if (hipMalloc(&g->d_cursor, sizeof(unsigned int)) != hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of the cursor failed"));
+    e = hipMemcpy(g->d_vols, vols.data(), sizeof(VolumeRec) * nvol, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy volumes"));
+    if (!dau.empty()) {
+        e = hipMemcpy(g->d_dau, dau.data(), sizeof(DaughterRec) * dau.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy daughters"));
+    }
+    e = hipEventCreateWithFlags(&g->staged, hipEventDisableTiming);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventCreate"));
+    *out = g;
+    return GEO_OK;
+}
+
+int geo_geometry_destroy(geo_geometry *g) {
+    if (!g) return GEO_OK;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != g->device) (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    destroy_graph(g);
+    if (g->staged) (void)hipEventDestroy(g->staged);
+    (void)hipFree(g->d_vols);
+    (void)hipFree(g->d_dau);
+    (void)hipFree(g->d_partial);
+    (void)hipFree(g->d_tiles);
+    (void)hipFree(g->d_bstage);
+    (void)hipFree(g->d_cursor);
+    if (g->h_baskets) (void)hipHostFree(g->h_baskets);
+    if (dev >= 0 && dev != g->device) (void)hipSetDevice(dev);
+    delete g;
+    return GEO_OK;
+}
+
+int geo_shape_query(const geo_shape *s, int32_t query, geo_tracks t, void *out, hipStream_t stream) {
+    if (!s) return fail(GEO_ERR_INVALID_ARG, "shape is NULL");
+    if (query < GEO_CONTAINS || query > GEO_DIST_OUT) return fail(GEO_ERR_INVALID_ARG, "unknown query %d", query);
+    ShapeRec rec;
+    int rc = make_shape(*s, rec, nullptr, "shape");
+    if (rc) return rc;
+    rc = check_tracks(t, query >= GEO_DIST_IN, "tracks");
+    if (rc) return rc;
+    if (t.n == 0) return GEO_OK;
+    rc = check_out(out, query == GEO_CONTAINS ? 1 : 8, "out");
+    if (rc) return rc;
+    hipError_t e = launch_shape_query(rec, query, to_dev(t), out, stream);
+    if (e != hipSuccess) return hip_fail(e, "shape query launch");
+    return GEO_OK;
+}
+
+int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                        double *step, int32_t *hit, double *hitpt, hipStream_t stream) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (volume < 0 || volume >= g->nvol) return fail(GEO_ERR_INVALID_ARG, "volume %d out of range", volume);
+    int rc = check_tracks(t, true, "tracks");
+    if (rc) return rc;
+    if (t.n == 0) return GEO_OK;
+    if ((rc = check_out(step, 8, "step")) || (rc = check_out(hit, 4, "hit")) ||
+        (rc = check_opt(hitpt, 8, "hitpt")) || (rc = check_opt(offsets, 8, "offsets")))
+        return rc;
+    if ((rc = check_device(g))) return rc;
+    const int first = g->h_vols[volume].first;
+    hipError_t e = launch_nav_basket(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr, to_dev(t),
+                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, step, hit, hitpt, stream);
+    if (e != hipSuccess) return hip_fail(e, "navigator launch");
+    return GEO_OK;
+}
+
+int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                          const double *gstep, const double *ghit, double *g_o, double *g_d, double *g_off,
+                          hipStream_t stream) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (volume < 0 || volume >= g->nvol) return fail(GEO_ERR_INVALID_ARG, "volume %d out of range", volume);
+    int rc = check_tracks(t, true, "tracks");
+    if (rc) return rc;
+    if ((rc = check_opt(offsets, 8, "offsets")) || (rc = check_opt(gstep, 8, "gstep")) ||
+        (rc = check_opt(ghit, 8, "ghit")) || (rc = check_opt(g_o, 8, "g_o")) ||
+        (rc = check_opt(g_d, 8, "g_d")) || (rc = check_opt(g_off, 8, "g_off")))
+        return rc;
+    const int nd = g->h_vols[volume].nd;
+    if (t.n == 0 && !(g_off && nd > 0)) return GEO_OK;
+    if ((rc = check_device(g))) return rc;
+    const int first = g->h_vols[volume].first;
+    hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr, nd, to_dev(t),
+                                   nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, g->d_partial,
+                                   nd > 0 ? g_off : nullptr, stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return GEO_OK;
+}
+
+// ------------------------------------------------------------- batched
+namespace {
+
+int ensure_capacity(geo_geometry *g, int nb, int64_t ntiles, hipStream_t stream) {
+    const size_t need = sizeof(BasketRec) * (size_t)nb + sizeof(int64_t) * (size_t)(nb + 1);
+    if (need > g->h_cap) {
+        if (g->staged_pending) GN_HIP(hipEventSynchronize(g->staged));
+        g->staged_pending = false;
+        if (g->h_baskets) (void)hipHostFree(g->h_baskets);
+        g->h_baskets = nullptr;
+        const size_t cap = std::max(need, (size_t)(1 << 16));
+        if (hipHostMalloc(reinterpret_cast<void **>(&g->h_baskets), cap, hipHostMallocDefault) != hipSuccess)
+            return fail(GEO_ERR_NOMEM, "pinned staging allocation failed");
+        g->h_cap = cap;
+    }
+    const bool grow_stage = need > g->d_bcap;
+    const bool grow_tiles = ntiles > g->tiles_cap;
+    if (grow_stage || grow_tiles) {
+        // buffers may still be in use by a previous graph launch on this stream
+        GN_HIP(hipStreamSynchronize(stream));
+        GN_HIP(hipDeviceSynchronize());
+        destroy_graph(g);
+        if (grow_stage) {
+            (void)hipFree(g->d_bstage);
+            g->d_bstage = nullptr;
+            const size_t cap = std::max(need, (size_t)(1 << 16));
+            if (hipMalloc(&g->d_bstage, cap) != hipSuccess) return fail(GEO_ERR_NOMEM, "device staging allocation failed");
+            g->d_bcap = cap;
+        }
+        if (grow_tiles) {
+            (void)hipFree(g->d_tiles);
+            g->d_tiles = nullptr;
+            const int64_t cap = std::max<int64_t>(ntiles + ntiles / 4, 4096);
+            if (hipMalloc(&g->d_tiles, sizeof(Tile) * (size_t)cap) != hipSuccess)
+                return fail(GEO_ERR_NOMEM, "device tile allocation failed");
+            g->tiles_cap = cap;
+        }
+    }
+    return GEO_OK;
+}
+
+int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_tracks &all, double *step,
+                   int32_t *hit, hipStream_t stream) {
+    const int U = g->tracks_per_lane;
+    const int tile_n = 64 * U;
+    // cost-sorted basket list (per-track cost ~ daughters + mother), stable
+    std::vector<BasketRec> &s = g->sorted;
+    s.clear();
+    for (int i = 0; i < nb; ++i)
+        if (b[i].n > 0) s.push_back(BasketRec{b[i].volume, 0, b[i].offset, b[i].n});
+    std::stable_sort(s.begin(), s.end(), [&](const BasketRec &a, const BasketRec &c) {
+        return g->h_vols[a.volume].nd > g->h_vols[c.volume].nd;
+    });
+    const int ns = (int)s.size();
+    if (ns == 0) return GEO_OK;
+    int64_t ntiles = 0;
+    for (const BasketRec &r : s) ntiles += (r.n + tile_n - 1) / tile_n;
+    if (ntiles > 0x7fffffff) return fail(GEO_ERR_INVALID_ARG, "too many tiles");
+    int rc = ensure_capacity(g, ns, ntiles, stream);
+    if (rc) return rc;
+    // stage baskets and tile starts in pinned memory, once the previous
+    // upload from it has completed
+    if (g->staged_pending) GN_HIP(hipEventSynchronize(g->staged));
+    BasketRec *hb = g->h_baskets;
+    int64_t *hs = reinterpret_cast<int64_t *>(hb + ns);
+    int64_t acc = 0;
+    for (int i = 0; i < ns; ++i) {
+        hb[i] = s[i];
+        hs[i] = acc;
+        acc += (s[i].n + tile_n - 1) / tile_n;
+    }
+    hs[ns] = acc;
+    const size_t bytes = sizeof(BasketRec) * (size_t)ns + sizeof(int64_t) * (size_t)(ns + 1);
+    GN_HIP(hipMemcpyAsync(g->d_bstage, hb, bytes, hipMemcpyHostToDevice, stream));
+    GN_HIP(hipEventRecord(g->staged, stream));
+    g->staged_pending = true;
+
+    BuildTilesArgs ba;
+    ba.baskets = reinterpret_cast<const BasketRec *>(g->d_bstage);
+    ba.tile_start = reinterpret_cast<const int64_t *>(reinterpret_cast<const BasketRec *>(g->d_bstage) + ns);
+    ba.nb = ns;
+    ba.tile_n = tile_n;
+    ba.tiles = g->d_tiles;
+    ba.cursor = g->d_cursor;
+    PersistentArgs pa;
+    pa.vols = g->d_vols;
+    pa.dau = g->d_dau;
+    pa.tiles = g->d_tiles;
+    pa.ntiles = (int32_t)ntiles;
+    pa.cursor = g->d_cursor;
+    pa.t = to_dev(all);
+    pa.step = step;
+    pa.hit = hit;
+
+    const int grid = persistent_grid(g->waves_per_simd, g->num_cus);
+    void *bargs[] = {&ba};
+    void *pargs[] = {&pa};
+    hipKernelNodeParams kb = {};
+    kb.func = const_cast<void *>(build_tiles_kernel());
+    kb.gridDim = dim3(kBuildTilesBlocks);
+    kb.blockDim = dim3(kBlock);
+    kb.kernelParams = bargs;
+    hipKernelNodeParams kn = {};
+    kn.func = const_cast<void *>(persistent_kernel(U));
+    kn.gridDim = dim3(grid);
+    kn.blockDim = dim3(kBlock);
+    kn.kernelParams = pargs;
+    if (!g->exec || g->graph_U != U || g->graph_grid != grid) {
+        destroy_graph(g);
+        GN_HIP(hipGraphCreate(&g->graph, 0));
+        GN_HIP(hipGraphAddKernelNode(&g->node_build, g->graph, nullptr, 0, &kb));
+        GN_HIP(hipGraphAddKernelNode(&g->node_nav, g->graph, &g->node_build, 1, &kn));
+        GN_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        g->graph_U = U;
+        g->graph_grid = grid;
+    } else {
+        GN_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->node_build, &kb));
+        GN_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->node_nav, &kn));
+    }
+    GN_HIP(hipGraphLaunch(g->exec, stream));
+    return GEO_OK;
+}
+
+int validate_batched(const geo_geometry *g, const geo_basket *b, int32_t nb, const geo_tracks &all,
+                     double *step, int32_t *hit, bool check_outputs) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (nb < 0) return fail(GEO_ERR_INVALID_ARG, "nb < 0");
+    if (nb > 0 && !b) return fail(GEO_ERR_INVALID_ARG, "baskets is NULL");
+    int rc = check_tracks(all, true, "track pool");
+    if (rc) return rc;
+    int64_t total = 0;
+    for (int i = 0; i < nb; ++i) {
+        if (b[i].volume < 0 || b[i].volume >= g->nvol)
+            return fail(GEO_ERR_INVALID_ARG, "basket %d: volume %d out of range", i, b[i].volume);
+        if (b[i].n < 0 || b[i].offset < 0 || b[i].offset > all.n || b[i].n > all.n - b[i].offset)
+            return fail(GEO_ERR_INVALID_ARG, "basket %d: [%lld, +%lld) outside the pool of %lld", i,
+                        (long long)b[i].offset, (long long)b[i].n, (long long)all.n);
+        total += b[i].n;
+    }
+    if (total > 0 && check_outputs) {
+        if ((rc = check_out(step, 8, "step")) || (rc = check_out(hit, 4, "hit"))) return rc;
+    }
+    return GEO_OK;
+}
+
+}  // namespace
+
+int geo_navigate_batched(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks all, double *step,
+                         int32_t *hit, hipStream_t stream) {
+    int rc = validate_batched(g, b, nb, all, step, hit, true);
+    if (rc) return rc;
+    if (nb == 0 || all.n == 0) return GEO_OK;
+    if ((rc = check_device(g))) return rc;
+    return launch_batched(g, b, nb, all, step, hit, stream);
+}
+
+int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd) {
+    if (!g || !tracks_per_lane || !waves_per_simd) return fail(GEO_ERR_INVALID_ARG, "NULL argument");
+    *tracks_per_lane = g->tracks_per_lane;
+    *waves_per_simd = g->waves_per_simd;
+    return GEO_OK;
+}
+
+int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (!(tracks_per_lane == 1 || tracks_per_lane == 2 || tracks_per_lane == 4))
+        return fail(GEO_ERR_INVALID_ARG, "tracks_per_lane must be 1, 2 or 4");
+    if (waves_per_simd < 1 || waves_per_simd > 8) return fail(GEO_ERR_INVALID_ARG, "waves_per_simd must be 1..8");
+    g->tracks_per_lane = tracks_per_lane;
+    g->waves_per_simd = waves_per_simd;
+    return GEO_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+namespace {
+
+std::string tune_key(const geo_geometry *g, const geo_basket *b, int nb) {
+    int64_t total = 0;
+    double work = 0;
+    for (int i = 0; i < nb; ++i) {
+        total += b[i].n;
+        work += (double)b[i].n * (g->h_vols[b[i].volume].nd + 1);
+    }
+    // bucket by powers of two of the basket count, track count and mean cost
+    auto lg = [](double v) { return v > 1 ? (int)std::floor(std::log2(v)) : 0; };
+    std::ostringstream os;
+    os << g->device_name << "/cu" << g->num_cus << "/nb" << lg(nb) << "/n" << lg((double)total) << "/c"
+       << lg(total > 0 ? work / total : 1);
+    return os.str();
+}
+
+// The cache is a flat JSON object: {"key": [tracks_per_lane, waves_per_simd], ...}
+std::vector<std::pair<std::string, std::pair<int, int>>> read_cache(const char *path) {
+    std::vector<std::pair<std::string, std::pair<int, int>>> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t pos = 0;
+    while (true) {
+        size_t q0 = s.find('"', pos);
+        if (q0 == std::string::npos) break;
+        size_t q1 = s.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        size_t lb = s.find('[', q1);
+        size_t rb = s.find(']', lb == std::string::npos ? q1 : lb);
+        if (lb == std::string::npos || rb == std::string::npos) break;
+        int u = 0, w = 0;
+        if (std::sscanf(s.c_str() + lb, "[%d , %d]", &u, &w) == 2 ||
+            std::sscanf(s.c_str() + lb, "[%d,%d]", &u, &w) == 2)
+            out.push_back({s.substr(q0 + 1, q1 - q0 - 1), {u, w}});
+        pos = rb + 1;
+    }
+    return out;
+}
+
+void write_cache(const char *path, const std::vector<std::pair<std::string, std::pair<int, int>>> &ent) {
+    std::string tmp = std::string(path) + ".tmp";
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n";
+    for (size_t i = 0; i < ent.size(); ++i)
+        f << "  \"" << ent[i].first << "\": [" << ent[i].second.first << ", " << ent[i].second.second << "]"
+          << (i + 1 < ent.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks all, hipStream_t stream) {
+    int rc = validate_batched(g, b, nb, all, nullptr, nullptr, false);
+    if (rc) return rc;
+    if (nb == 0 || all.n == 0) return GEO_OK;
+    if ((rc = check_device(g))) return rc;
+    const char *path = std::getenv("GEONAV_AUTOTUNE_CACHE");
+    const std::string key = tune_key(g, b, nb);
+    auto cache = path ? read_cache(path) : decltype(read_cache("")){};
+    for (auto &e : cache)
+        if (e.first == key && geo_set_launch_config(g, e.second.first, e.second.second) == GEO_OK) return GEO_OK;
+
+    double *step = nullptr;
+    int32_t *hit = nullptr;
+    if (hipMalloc(&step, sizeof(double) * (size_t)all.n) != hipSuccess ||
+        hipMalloc(&hit, sizeof(int32_t) * (size_t)all.n) != hipSuccess) {
+        (void)hipFree(step);
+        return fail(GEO_ERR_NOMEM, "autotune scratch allocation failed");
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int Us[] = {1, 2, 4};
+    const int Ws[] = {1, 2, 4, 8};
+    int bestU = g->tracks_per_lane, bestW = g->waves_per_simd;
+    float best = 1e30f;
+    rc = GEO_OK;
+    for (int U : Us) {
+        for (int W : Ws) {
+            g->tracks_per_lane = U;
+            g->waves_per_simd = W;
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 4 && rc == GEO_OK; ++rep) {
+                (void)hipEventRecord(e0, stream);
+                rc = launch_batched(g, b, nb, all, step, hit, stream);
+                (void)hipEventRecord(e1, stream);
+                if (rc) break;
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(GEO_ERR_HIP, "autotune timing failed");
+                    break;
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) tmin = std::min(tmin, ms);  // first run warms up
+            }
+            if (rc) break;
+            if (tmin < best) {
+                best = tmin;
+                bestU = U;
+                bestW = W;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipStreamSynchronize(stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(step);
+    (void)hipFree(hit);
+    g->tracks_per_lane = bestU;
+    g->waves_per_simd = bestW;
+    if (rc) return rc;
+    if (path) {
+        bool found = false;
+        for (auto &e : cache)
+            if (e.first == key) {
+                e.second = {bestU, bestW};
+                found = true;
+            }
+        if (!found) cache.push_back({key, {bestU, bestW}});
+        write_cache(path, cache);
+    }
+    return GEO_OK;
+}
+

@@ -1,0 +1,457 @@
+// Device-side records and per-lane shape algorithms of libgeonav (gfx950, FP64).
+//
+// One lane evaluates one track. Every algorithm is branch-free over lanes:
+// all candidate surfaces of a shape are evaluated and the valid smallest one
+// is kept with selects, so a wavefront never diverges inside a shape. The
+// only branches are on the shape kind and the hole flag, which are uniform
+// across a wavefront (the navigator walks the daughters in lockstep).
+//
+// Each distance query is a minimum over per-surface candidates (faces,
+// z-planes, the outer and inner cylinder/cone nappes): for DistFromOutside
+// a candidate is a point where the line enters the solid through that
+// surface; for DistFromInside it is the first crossing of that surface's
+// constraint. Quadric roots use the cancellation-free pair of formulas
+// (numerator and denominator chosen by the sign of B), one division each.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gn {
+
+constexpr double kBig = 1e30;
+enum : int32_t { kBox = 0, kTube = 1, kCone = 2 };
+
+// Shape with host-derived constants.
+//   BOX  c0..2 = dx, dy, dz
+//   TUBE c0 = rmin, c1 = rmax, c2 = dz, c3 = rmin^2, c4 = rmax^2
+//   CONE c0 = dz, radius r(z) = a + b z: c1 = a_out, c2 = b_out, c3 = a_in, c4 = b_in,
+//        c5..8 = rmin1, rmax1, rmin2, rmax2, c9..12 = their squares,
+//        c13 = 1/sqrt(1 + b_out^2), c14 = 1/sqrt(1 + b_in^2),
+//        c15 = 1/|outer edge|^2, c16 = 1/|inner edge|^2 (profile edges in (r, z))
+struct alignas(16) ShapeRec {
+    int32_t kind;
+    int32_t hole;  // tube/cone: an inner surface exists (not both inner radii 0)
+    double c[19];
+};
+static_assert(sizeof(ShapeRec) == 160, "ShapeRec layout");
+
+// A placed daughter: mother-frame point = R * local + T.
+struct alignas(16) DaughterRec {
+    double rot[9];   // R, row-major
+    double tr[3];    // T
+    double bound_r;  // radius of a sphere about the local origin holding the shape
+    double pad[3];
+    ShapeRec shape;
+};
+static_assert(sizeof(DaughterRec) == 288, "DaughterRec layout");
+
+struct alignas(16) VolumeRec {
+    ShapeRec mother;
+    int32_t nd;     // number of daughters
+    int32_t first;  // index of daughter 0 in the daughter table
+    int32_t pad[6];
+};
+static_assert(sizeof(VolumeRec) == 192, "VolumeRec layout");
+
+struct TracksDev {
+    const double *x, *y, *z, *ux, *uy, *uz;
+    int64_t n;
+};
+
+// Work unit of the batched kernel: `count` tracks of volume `volume` at
+// pool index `offset`.
+struct Tile {
+    int32_t volume;
+    int32_t count;
+    int64_t offset;
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double sq(double a) { return a * a; }
+
+// Candidate update: keep the smallest valid t; on equal t the earlier
+// candidate (lower surface id) stays.
+__device__ __forceinline__ void take(bool ok, double t, int id, double &best, int &sid) {
+    const bool better = ok && (t < best);
+    best = better ? t : best;
+    sid = better ? id : sid;
+}
+
+// Roots of f(t) = A t^2 + 2 B t + C, with s = sqrt(B^2 - A C).
+// Root where f goes from + to - (A t + B = -s): (-B - s) / A = C / (s - B).
+__device__ __forceinline__ double root_down(double A, double B, double C, double s) {
+    const bool neg = B <= 0.0;
+    const double num = neg ? C : -(B + s);
+    const double den = neg ? (s - B) : A;
+    return num / den;
+}
+// Root where f goes from - to + (A t + B = +s): (-B + s) / A = -C / (s + B).
+__device__ __forceinline__ double root_up(double A, double B, double C, double s) {
+    const bool pos = B >= 0.0;
+    const double num = pos ? -C : (s - B);
+    const double den = pos ? (s + B) : A;
+    return num / den;
+}
+
+// ---------------------------------------------------------------------- box
+__device__ __forceinline__ bool box_contains(const double *c, double x, double y, double z) {
+    return fabs(x) <= c[0] && fabs(y) <= c[1] && fabs(z) <= c[2];
+}
+
+__device__ __forceinline__ double box_safety(const double *c, double x, double y, double z) {
+    const double ex = fabs(x) - c[0], ey = fabs(y) - c[1], ez = fabs(z) - c[2];
+    const double m = fmax(ex, fmax(ey, ez));
+    const double ox = fmax(ex, 0.0), oy = fmax(ey, 0.0), oz = fmax(ez, 0.0);
+    const double out = sqrt(ox * ox + oy * oy + oz * oz);
+    return m <= 0.0 ? -m : out;
+}
+
+// Entering face a: the point is beyond the slab (|p_a| > D_a) and moves
+// towards it; the entry point must lie within the other two slabs.
+__device__ __forceinline__ double box_dist_out(const double *c, double x, double y, double z,
+                                               double ux, double uy, double uz, int &sid) {
+    const double ax = fabs(x) - c[0], ay = fabs(y) - c[1], az = fabs(z) - c[2];
+    const bool inside = ax <= 0.0 && ay <= 0.0 && az <= 0.0;
+    double best = kBig;
+    sid = -1;
+    {
+        const double t = ax / fabs(ux);
+        const bool ok = ax > 0.0 && x * ux < 0.0 && fabs(fma(t, uy, y)) <= c[1] &&
+                        fabs(fma(t, uz, z)) <= c[2];
+        take(ok, t, 0, best, sid);
+    }
+    {
+        const double t = ay / fabs(uy);
+        const bool ok = ay > 0.0 && y * uy < 0.0 && fabs(fma(t, ux, x)) <= c[0] &&
+                        fabs(fma(t, uz, z)) <= c[2];
+        take(ok, t, 1, best, sid);
+    }
+    {
+        const double t = az / fabs(uz);
+        const bool ok = az > 0.0 && z * uz < 0.0 && fabs(fma(t, ux, x)) <= c[0] &&
+                        fabs(fma(t, uy, y)) <= c[1];
+        take(ok, t, 2, best, sid);
+    }
+    return inside ? 0.0 : best;
+}
+
+// Leaving: the first face the line reaches on each axis.
+__device__ __forceinline__ double box_dist_in(const double *c, double x, double y, double z,
+                                              double ux, double uy, double uz, int &sid) {
+    const bool inside = box_contains(c, x, y, z);
+    double best = kBig;
+    sid = -1;
+    take(ux != 0.0, (c[0] - (ux > 0.0 ? x : -x)) / fabs(ux), 0, best, sid);
+    take(uy != 0.0, (c[1] - (uy > 0.0 ? y : -y)) / fabs(uy), 1, best, sid);
+    take(uz != 0.0, (c[2] - (uz > 0.0 ? z : -z)) / fabs(uz), 2, best, sid);
+    return inside ? best : 0.0;
+}
+
+// --------------------------------------------------------------------- tube
+// Surfaces: 0 = z planes, 1 = outer cylinder, 2 = inner cylinder.
+__device__ __forceinline__ bool tube_contains(const double *c, double x, double y, double z) {
+    const double rsq = x * x + y * y;
+    return fabs(z) <= c[2] && rsq <= c[4] && rsq >= c[3];
+}
+
+// (r, z) profile is the rectangle [rmin, rmax] x [-dz, dz]; without a hole
+// the axis bounds no surface.
+__device__ __forceinline__ double tube_safety(const double *c, int hole, double x, double y,
+                                              double z) {
+    const double r = sqrt(x * x + y * y);
+    const double eo = r - c[1];
+    const double ei = hole ? c[0] - r : -kBig;
+    const double ez = fabs(z) - c[2];
+    const double er = fmax(eo, ei);
+    const double m = fmax(er, ez);
+    const double orr = fmax(er, 0.0), oz = fmax(ez, 0.0);
+    const double out = sqrt(orr * orr + oz * oz);
+    return m <= 0.0 ? -m : out;
+}
+
+__device__ __forceinline__ double tube_dist_out(const double *c, int hole, double x, double y,
+                                                double z, double ux, double uy, double uz,
+                                                int &sid) {
+    const double dz = c[2];
+    const double rsq = x * x + y * y;
+    const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3];
+    double best = kBig;
+    sid = -1;
+    {   // z planes: from beyond the slab, moving towards it, landing on the annulus
+        const double az = fabs(z) - dz;
+        const double t = az / fabs(uz);
+        const double xh = fma(t, ux, x), yh = fma(t, uy, y);
+        const double r2 = xh * xh + yh * yh;
+        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= c[3] && r2 <= c[4];
+        take(ok, t, 0, best, sid);
+    }
+    const double A = ux * ux + uy * uy;
+    const double B = x * ux + y * uy;
+    {   // outer cylinder, entered from r > rmax
+        const double C = rsq - c[4];
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = C / (s - B);
+        const bool ok = C > 0.0 && B < 0.0 && disc >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        take(ok, t, 1, best, sid);
+    }
+    if (hole) {  // inner cylinder, left from inside the hole into the material
+        const double C = rsq - c[3];
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_up(A, B, C, s);
+        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        take(ok, t, 2, best, sid);
+    }
+    return inside ? 0.0 : best;
+}
+
+__device__ __forceinline__ double tube_dist_in(const double *c, int hole, double x, double y,
+                                               double z, double ux, double uy, double uz,
+                                               int &sid) {
+    const double dz = c[2];
+    const double rsq = x * x + y * y;
+    const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3];
+    double best = kBig;
+    sid = -1;
+    take(uz != 0.0, (dz - (uz > 0.0 ? z : -z)) / fabs(uz), 0, best, sid);
+    const double A = ux * ux + uy * uy;
+    const double B = x * ux + y * uy;
+    {   // leave the outer cylinder
+        const double C = rsq - c[4];
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_up(A, B, C, s);
+        take(disc >= 0.0 && t >= 0.0, t, 1, best, sid);
+    }
+    if (hole) {  // enter the hole's cylinder
+        const double C = rsq - c[3];
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_down(A, B, C, s);
+        take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
+    }
+    return inside ? best : 0.0;
+}
+
+// --------------------------------------------------------------------- cone
+// Surfaces: 0 = z planes, 1 = outer nappe r = a_out + b_out z,
+// 2 = inner nappe r = a_in + b_in z. On a nappe, f = r^2 - (a + b z)^2 along
+// the line is the quadratic A t^2 + 2 B t + C with
+//   A = ux^2 + uy^2 - (b uz)^2, B = x ux + y uy - b uz w, C = x^2 + y^2 - w^2,
+// w = a + b z. Its roots include the mirror nappe (a + b z < 0); a root on the
+// mirror lies outside |z| <= dz (the radii are >= 0 on the slab), so the slab
+// test at the root rejects it for entries, and for exits the z plane comes
+// first.
+__device__ __forceinline__ bool cone_contains(const double *c, int hole, double x, double y,
+                                              double z) {
+    const double rsq = x * x + y * y;
+    const double wo = fma(c[2], z, c[1]);
+    const double wi = fma(c[4], z, c[3]);
+    return fabs(z) <= c[0] && rsq <= wo * wo && (!hole || rsq >= wi * wi);
+}
+
+__device__ __forceinline__ double seg_d2(double r, double z, double r0, double z0, double er,
+                                         double ez, double inv_ee) {
+    const double wr = r - r0, wz = z - z0;
+    const double t = fmin(fmax((wr * er + wz * ez) * inv_ee, 0.0), 1.0);
+    return sq(wr - t * er) + sq(wz - t * ez);
+}
+
+// Profile: trapezoid with corners (rmin1, -dz) (rmax1, -dz) (rmax2, dz)
+// (rmin2, dz). Inside it is convex, so the distance is the smallest distance
+// to the edges' lines; outside it is the smallest distance to the segments.
+__device__ __forceinline__ double cone_safety(const double *c, int hole, double x, double y,
+                                              double z) {
+    const double dz = c[0];
+    const double r = sqrt(x * x + y * y);
+    const double wo = fma(c[2], z, c[1]);
+    const double wi = fma(c[4], z, c[3]);
+    const bool inside = fabs(z) <= dz && r <= wo && (!hole || r >= wi);
+    double din = fmin(dz - fabs(z), (wo - r) * c[13]);
+    din = hole ? fmin(din, (r - wi) * c[14]) : din;
+    // outside: bottom and top edges, outer and inner slanted edges
+    const double rb = fmin(fmax(r, c[5]), c[6]);
+    const double rt = fmin(fmax(r, c[7]), c[8]);
+    double d2 = fmin(sq(r - rb) + sq(z + dz), sq(r - rt) + sq(z - dz));
+    d2 = fmin(d2, seg_d2(r, z, c[6], -dz, c[8] - c[6], 2.0 * dz, c[15]));
+    const double di2 = seg_d2(r, z, c[5], -dz, c[7] - c[5], 2.0 * dz, c[16]);
+    d2 = hole ? fmin(d2, di2) : d2;
+    return inside ? din : sqrt(d2);
+}
+
+__device__ __forceinline__ double cone_dist_out(const double *c, int hole, double x, double y,
+                                                double z, double ux, double uy, double uz,
+                                                int &sid) {
+    const double dz = c[0];
+    const double rsq = x * x + y * y;
+    const double wo = fma(c[2], z, c[1]);
+    const double wi = fma(c[4], z, c[3]);
+    const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi);
+    double best = kBig;
+    sid = -1;
+    {   // z planes: the face's annulus depends on which end is hit
+        const double az = fabs(z) - dz;
+        const double t = az / fabs(uz);
+        const double xh = fma(t, ux, x), yh = fma(t, uy, y);
+        const double r2 = xh * xh + yh * yh;
+        const bool top = z > 0.0;
+        const double lo2 = top ? c[11] : c[9];
+        const double hi2 = top ? c[12] : c[10];
+        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= lo2 && r2 <= hi2;
+        take(ok, t, 0, best, sid);
+    }
+    const double A0 = ux * ux + uy * uy;
+    const double B0 = x * ux + y * uy;
+    {   // outer nappe: entered where f goes from + to -
+        const double v = c[2] * uz;
+        const double A = A0 - v * v, B = B0 - v * wo, C = rsq - wo * wo;
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_down(A, B, C, s);
+        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        take(ok, t, 1, best, sid);
+    }
+    if (hole) {  // inner nappe: left from the hole where f goes from - to +
+        const double v = c[4] * uz;
+        const double A = A0 - v * v, B = B0 - v * wi, C = rsq - wi * wi;
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_up(A, B, C, s);
+        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        take(ok, t, 2, best, sid);
+    }
+    return inside ? 0.0 : best;
+}
+
+__device__ __forceinline__ double cone_dist_in(const double *c, int hole, double x, double y,
+                                               double z, double ux, double uy, double uz,
+                                               int &sid) {
+    const double dz = c[0];
+    const double rsq = x * x + y * y;
+    const double wo = fma(c[2], z, c[1]);
+    const double wi = fma(c[4], z, c[3]);
+    const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi);
+    double best = kBig;
+    sid = -1;
+    take(uz != 0.0, (dz - (uz > 0.0 ? z : -z)) / fabs(uz), 0, best, sid);
+    const double A0 = ux * ux + uy * uy;
+    const double B0 = x * ux + y * uy;
+    {   // leave the outer nappe
+        const double v = c[2] * uz;
+        const double A = A0 - v * v, B = B0 - v * wo, C = rsq - wo * wo;
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_up(A, B, C, s);
+        take(disc >= 0.0 && t >= 0.0, t, 1, best, sid);
+    }
+    if (hole) {  // enter the inner nappe (the hole)
+        const double v = c[4] * uz;
+        const double A = A0 - v * v, B = B0 - v * wi, C = rsq - wi * wi;
+        const double disc = B * B - A * C;
+        const double s = sqrt(fmax(disc, 0.0));
+        const double t = root_down(A, B, C, s);
+        take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
+    }
+    return inside ? best : 0.0;
+}
+
+// ------------------------------------------------------ dispatch on kind
+// `kind` is uniform across the wavefront wherever these are called.
+__device__ __forceinline__ bool any_contains(const ShapeRec &s, double x, double y, double z) {
+    switch (s.kind) {
+        case kBox: return box_contains(s.c, x, y, z);
+        case kTube: return tube_contains(s.c, x, y, z);
+        default: return cone_contains(s.c, s.hole, x, y, z);
+    }
+}
+
+__device__ __forceinline__ double any_safety(const ShapeRec &s, double x, double y, double z) {
+    switch (s.kind) {
+        case kBox: return box_safety(s.c, x, y, z);
+        case kTube: return tube_safety(s.c, s.hole, x, y, z);
+        default: return cone_safety(s.c, s.hole, x, y, z);
+    }
+}
+
+__device__ __forceinline__ double any_dist_out(const ShapeRec &s, double x, double y, double z,
+                                               double ux, double uy, double uz, int &sid) {
+    switch (s.kind) {
+        case kBox: return box_dist_out(s.c, x, y, z, ux, uy, uz, sid);
+        case kTube: return tube_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+        default: return cone_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+    }
+}
+
+__device__ __forceinline__ double any_dist_in(const ShapeRec &s, double x, double y, double z,
+                                              double ux, double uy, double uz, int &sid) {
+    switch (s.kind) {
+        case kBox: return box_dist_in(s.c, x, y, z, ux, uy, uz, sid);
+        case kTube: return tube_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+        default: return cone_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+    }
+}
+
+// Outward-or-inward normal (any scale/sign) of surface `sid` at local point h.
+__device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, double hx, double hy,
+                                               double hz, double &nx, double &ny, double &nz) {
+    nx = ny = nz = 0.0;
+    if (s.kind == kBox) {
+        nx = sid == 0 ? 1.0 : 0.0;
+        ny = sid == 1 ? 1.0 : 0.0;
+        nz = sid == 2 ? 1.0 : 0.0;
+        return;
+    }
+    if (sid == 0) { nz = 1.0; return; }
+    if (sid < 0) return;
+    nx = hx;
+    ny = hy;
+    if (s.kind == kCone) {
+        const double a = sid == 1 ? s.c[1] : s.c[3];
+        const double b = sid == 1 ? s.c[2] : s.c[4];
+        nz = -b * fma(b, hz, a);
+    }
+}
+
+// ----------------------------------------------------------- navigator
+// Per-track navigator of Fig. 1b: the mother's DistFromInside, then each
+// daughter's DistFromOutside in its own frame, keeping the smallest (ties to
+// the mother, then the lowest index). Daughters are walked in lockstep by
+// the whole wavefront, so the daughter record and its kind are uniform
+// (scalar loads, scalar branch).
+template <bool HAS_OFFS, bool TRACK_SURF>
+__device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                          const double *__restrict__ offs, double x, double y,
+                                          double z, double ux, double uy, double uz, double &best,
+                                          int &hit, int &bsid) {
+    int sid;
+    best = any_dist_in(v.mother, x, y, z, ux, uy, uz, sid);
+    hit = -1;
+    bsid = sid;
+    const int nd = v.nd;
+    for (int k = 0; k < nd; ++k) {
+        const DaughterRec &D = dau[k];
+        double wx = x - D.tr[0], wy = y - D.tr[1], wz = z - D.tr[2];
+        if (HAS_OFFS) {
+            wx -= offs[3 * k + 0];
+            wy -= offs[3 * k + 1];
+            wz -= offs[3 * k + 2];
+        }
+        const double *R = D.rot;
+        // local = R^T w
+        const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+        const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+        const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+        const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
+        const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
+        const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
+        const double s = any_dist_out(D.shape, lx, ly, lz, lux, luy, luz, sid);
+        const bool better = s < best;
+        best = better ? s : best;
+        hit = better ? k : hit;
+        if (TRACK_SURF) bsid = better ? sid : bsid;
+    }
+}
+
+}  // namespace gn

@@ -1,0 +1,63 @@
+// Host-side interface between the C ABI (geonav_abi.cpp) and the kernel
+// launchers (geonav_kernels.hip). Not part of the public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "geonav_device.hpp"
+
+namespace gn {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
+constexpr int kBackwardMaxBlocks = 2048;
+
+hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, void *out,
+                              hipStream_t st);
+
+hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const TracksDev &t,
+                             const double *offs, double *step, int32_t *hit, double *hitpt,
+                             hipStream_t st);
+
+// Persistent batched navigator; `cursor` is reset by k_build_tiles, which
+// runs just before it in the same graph.
+struct PersistentArgs {
+    const VolumeRec *vols;
+    const DaughterRec *dau;
+    const Tile *tiles;
+    int32_t ntiles;
+    unsigned int *cursor;
+    TracksDev t;
+    double *step;
+    int32_t *hit;
+};
+
+// A basket as the device sees it (sorted by decreasing per-track cost).
+struct BasketRec {
+    int32_t volume;
+    int32_t pad;
+    int64_t offset;
+    int64_t n;
+};
+
+struct BuildTilesArgs {
+    const BasketRec *baskets;
+    const int64_t *tile_start;  // nb + 1 prefix offsets into tiles
+    int32_t nb;
+    int32_t tile_n;             // tracks per tile (64 * tracks per lane)
+    Tile *tiles;
+    unsigned int *cursor;
+};
+
+constexpr int kBuildTilesBlocks = 256;
+
+// Kernel function handles for graph kernel nodes.
+const void *persistent_kernel(int tracks_per_lane);
+const void *build_tiles_kernel();
+int persistent_grid(int waves_per_simd, int num_cus);
+
+hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
+                           const TracksDev &t, const double *offs, const double *gstep,
+                           const double *ghit, double *g_o, double *g_d, double *partial,
+                           double *g_off, hipStream_t st);
+
+}  // namespace gn

@@ -1,0 +1,331 @@
+// Kernels of libgeonav for gfx950 and their launchers.
+//
+//  k_shape_query     one query of one shape over a basket (section 3.1);
+//                    streaming, one lane per track, HBM-bound.
+//  k_nav_basket      the simple navigator (section 3, Fig. 1b) over one
+//                    basket; FP64-ALU-bound (every lane walks every daughter).
+//  k_nav_persistent  the same per-track navigator over many baskets of many
+//                    volumes in one launch: wavefronts pull tiles of one
+//                    volume from a global cursor (largest cost first).
+//  k_nav_backward    adjoint of the navigator (recompute + implicit-function
+//                    gradient of the surface that set the step) with
+//                    per-workgroup partial sums of the offset gradient;
+//  k_reduce_partials fixed-order reduction of those partials.
+#include "geonav_internal.hpp"
+
+namespace gn {
+
+// ------------------------------------------------------------ shape queries
+template <int KIND, int Q>
+__global__ __launch_bounds__(kBlock) void k_shape_query(ShapeRec s, TracksDev t, void *out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= t.n) return;
+    const double x = t.x[i], y = t.y[i], z = t.z[i];
+    if (Q == 0) {
+        bool in;
+        if (KIND == kBox) in = box_contains(s.c, x, y, z);
+        else if (KIND == kTube) in = tube_contains(s.c, x, y, z);
+        else in = cone_contains(s.c, s.hole, x, y, z);
+        static_cast<uint8_t *>(out)[i] = in ? 1 : 0;
+        return;
+    }
+    double r;
+    if (Q == 1) {
+        if (KIND == kBox) r = box_safety(s.c, x, y, z);
+        else if (KIND == kTube) r = tube_safety(s.c, s.hole, x, y, z);
+        else r = cone_safety(s.c, s.hole, x, y, z);
+    } else {
+        const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+        int sid;
+        if (Q == 2) {
+            if (KIND == kBox) r = box_dist_in(s.c, x, y, z, ux, uy, uz, sid);
+            else if (KIND == kTube) r = tube_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+            else r = cone_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+        } else {
+            if (KIND == kBox) r = box_dist_out(s.c, x, y, z, ux, uy, uz, sid);
+            else if (KIND == kTube) r = tube_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+            else r = cone_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+        }
+    }
+    static_cast<double *>(out)[i] = r;
+}
+
+template <int KIND>
+static hipError_t launch_shape_kind(const ShapeRec &s, int query, const TracksDev &t, void *out,
+                                   hipStream_t st) {
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
+    switch (query) {
+        case 0: hipLaunchKernelGGL((k_shape_query<KIND, 0>), grid, block, 0, st, s, t, out); break;
+        case 1: hipLaunchKernelGGL((k_shape_query<KIND, 1>), grid, block, 0, st, s, t, out); break;
+        case 2: hipLaunchKernelGGL((k_shape_query<KIND, 2>), grid, block, 0, st, s, t, out); break;
+        default: hipLaunchKernelGGL((k_shape_query<KIND, 3>), grid, block, 0, st, s, t, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, void *out,
+                              hipStream_t st) {
+    if (t.n == 0) return hipSuccess;
+    switch (s.kind) {
+        case kBox: return launch_shape_kind<kBox>(s, query, t, out, st);
+        case kTube: return launch_shape_kind<kTube>(s, query, t, out, st);
+        default: return launch_shape_kind<kCone>(s, query, t, out, st);
+    }
+}
+
+// ---------------------------------------------------------- basket navigator
+template <bool HAS_OFFS, bool HITPT>
+__global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restrict__ vol,
+                                                       const DaughterRec *__restrict__ dau,
+                                                       TracksDev t, const double *__restrict__ offs,
+                                                       double *__restrict__ step,
+                                                       int32_t *__restrict__ hit,
+                                                       double *__restrict__ hitpt) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= t.n) return;
+    const double x = t.x[i], y = t.y[i], z = t.z[i];
+    const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+    double best;
+    int h, sid;
+    nav_track<HAS_OFFS, false>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
+    step[i] = best;
+    hit[i] = h;
+    if (HITPT) {
+        const int64_t n = t.n;
+        hitpt[i] = fma(best, ux, x);
+        hitpt[n + i] = fma(best, uy, y);
+        hitpt[2 * n + i] = fma(best, uz, z);
+    }
+}
+
+hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const TracksDev &t,
+                             const double *offs, double *step, int32_t *hit, double *hitpt,
+                             hipStream_t st) {
+    if (t.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
+    if (offs) {
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<true, false>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+    } else {
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<false, false>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ batched, persistent
+// Each wavefront repeatedly takes the next tile index from `cursor` (tiles come
+// in order of decreasing per-track cost) until the list is exhausted; every
+// wavefront exits once the cursor passes ntiles. A tile holds at most
+// 64 * U tracks of one volume, so the volume and its daughters are uniform
+// over the wavefront.
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_nav_persistent(PersistentArgs a) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned int id = 0;
+        if (lane == 0) id = atomicAdd(a.cursor, 1u);
+        id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
+        if (id >= (unsigned int)a.ntiles) break;
+        const Tile tl = a.tiles[id];
+        const VolumeRec &v = a.vols[tl.volume];
+        const DaughterRec *dau = a.dau + v.first;
+#pragma unroll 1
+        for (int u = 0; u < U; ++u) {
+            const int j = u * 64 + lane;
+            if (j < tl.count) {
+                const int64_t i = tl.offset + j;
+                const double x = a.t.x[i], y = a.t.y[i], z = a.t.z[i];
+                const double ux = a.t.ux[i], uy = a.t.uy[i], uz = a.t.uz[i];
+                double best;
+                int h, sid;
+                nav_track<false, false>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h, sid);
+                a.step[i] = best;
+                a.hit[i] = h;
+            }
+        }
+    }
+}
+
+// Expands the (cost-sorted) basket list into tiles of at most tile_n tracks:
+// basket b owns tiles [tile_start[b], tile_start[b + 1]). Also resets the
+// persistent kernel's cursor.
+__global__ __launch_bounds__(kBlock) void k_build_tiles(BuildTilesArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.cursor = 0u;
+    for (int b = blockIdx.x; b < a.nb; b += gridDim.x) {
+        const BasketRec bk = a.baskets[b];
+        const int64_t first = a.tile_start[b];
+        const int64_t cnt = a.tile_start[b + 1] - first;
+        for (int64_t c = threadIdx.x; c < cnt; c += kBlock) {
+            const int64_t off = c * a.tile_n;
+            const int64_t left = bk.n - off;
+            Tile tl;
+            tl.volume = bk.volume;
+            tl.count = (int32_t)(left < a.tile_n ? left : a.tile_n);
+            tl.offset = bk.offset + off;
+            a.tiles[first + c] = tl;
+        }
+    }
+}
+
+const void *persistent_kernel(int tracks_per_lane) {
+    switch (tracks_per_lane) {
+        case 1: return reinterpret_cast<const void *>(&k_nav_persistent<1>);
+        case 2: return reinterpret_cast<const void *>(&k_nav_persistent<2>);
+        default: return reinterpret_cast<const void *>(&k_nav_persistent<4>);
+    }
+}
+
+const void *build_tiles_kernel() { return reinterpret_cast<const void *>(&k_build_tiles); }
+
+int persistent_grid(int waves_per_simd, int num_cus) {
+    // 4 SIMDs per CU, kBlock / 64 = 4 wavefronts per workgroup
+    return num_cus * waves_per_simd;
+}
+
+// ------------------------------------------------------------------ adjoint
+// For each track: recompute the forward step keeping the surface that set it,
+// take that surface's normal n (mother frame) at the hit point and, by the
+// implicit-function theorem on the surface equation,
+//   ds/dp = -n / (n.d),  ds/dd = s ds/dp,  ds/d delta_hit = n / (n.d).
+// With phi = gstep s + ghit . (p + s d) and c = gstep + ghit . d:
+//   g_p = ghit + c ds/dp,  g_d = s ghit + c ds/dd,  g_delta_hit += c ds/d delta.
+// The offset gradient of the workgroup's tracks is summed per daughter in a
+// fixed lane order into the workgroup's row of `partial`.
+template <bool HAS_OFFS>
+__global__ __launch_bounds__(kBlock) void k_nav_backward(
+    const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau, TracksDev t,
+    const double *__restrict__ offs, const double *__restrict__ gstep,
+    const double *__restrict__ ghit, double *__restrict__ g_o, double *__restrict__ g_d,
+    double *__restrict__ partial) {
+    __shared__ int s_hit[kBlock];
+    __shared__ double s_g[3][kBlock];
+    const int tid = threadIdx.x;
+    const int nd = vol->nd;
+    const int nj = 3 * nd;
+    double *prow = partial ? partial + (size_t)blockIdx.x * nj : nullptr;
+    if (prow)
+        for (int j = tid; j < nj; j += kBlock) prow[j] = 0.0;
+    const int64_t n = t.n;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = base + tid;
+        int h = -2;
+        double gdx = 0.0, gdy = 0.0, gdz = 0.0;
+        if (i < n) {
+            const double x = t.x[i], y = t.y[i], z = t.z[i];
+            const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+            double best;
+            int sid;
+            nav_track<HAS_OFFS, true>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
+            const bool finite = best < kBig;
+            const double s = finite ? best : 0.0;
+            const double hx = fma(s, ux, x), hy = fma(s, uy, y), hz = fma(s, uz, z);
+            double nx, ny, nz;
+            if (h < 0) {
+                surface_normal(vol->mother, sid, hx, hy, hz, nx, ny, nz);
+            } else {
+                const DaughterRec &D = dau[h];
+                double wx = hx - D.tr[0], wy = hy - D.tr[1], wz = hz - D.tr[2];
+                if (HAS_OFFS) {
+                    wx -= offs[3 * h + 0];
+                    wy -= offs[3 * h + 1];
+                    wz -= offs[3 * h + 2];
+                }
+                const double *R = D.rot;
+                const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+                const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+                const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+                double mx, my, mz;
+                surface_normal(D.shape, sid, lx, ly, lz, mx, my, mz);
+                // back to the mother frame: n = R m
+                nx = fma(R[2], mz, fma(R[1], my, R[0] * mx));
+                ny = fma(R[5], mz, fma(R[4], my, R[3] * mx));
+                nz = fma(R[8], mz, fma(R[7], my, R[6] * mx));
+            }
+            const double nd_ = fma(nz, uz, fma(ny, uy, nx * ux));
+            const bool ok = finite && best > 0.0 && nd_ != 0.0;
+            const double inv = ok ? -1.0 / nd_ : 0.0;
+            const double dsx = nx * inv, dsy = ny * inv, dsz = nz * inv;  // ds/dp
+            const double gs = gstep ? gstep[i] : 0.0;
+            double ghx = 0.0, ghy = 0.0, ghz = 0.0;
+            if (ghit) {
+                ghx = ghit[i];
+                ghy = ghit[n + i];
+                ghz = ghit[2 * n + i];
+            }
+            const double c = fma(ghz, uz, fma(ghy, uy, fma(ghx, ux, gs)));
+            if (g_o) {
+                g_o[i] = fma(c, dsx, ghx);
+                g_o[n + i] = fma(c, dsy, ghy);
+                g_o[2 * n + i] = fma(c, dsz, ghz);
+            }
+            if (g_d) {
+                const double cs = c * s;
+                g_d[i] = fma(cs, dsx, s * ghx);
+                g_d[n + i] = fma(cs, dsy, s * ghy);
+                g_d[2 * n + i] = fma(cs, dsz, s * ghz);
+            }
+            gdx = -c * dsx;
+            gdy = -c * dsy;
+            gdz = -c * dsz;
+        }
+        if (prow) {
+            s_hit[tid] = h;
+            s_g[0][tid] = gdx;
+            s_g[1][tid] = gdy;
+            s_g[2][tid] = gdz;
+            __syncthreads();
+            for (int j = tid; j < nj; j += kBlock) {
+                const int k = j / 3, comp = j - 3 * k;
+                double acc = 0.0;
+                for (int l = 0; l < kBlock; ++l) acc += (s_hit[l] == k) ? s_g[comp][l] : 0.0;
+                prow[j] += acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// out[j] = sum over workgroups b of partial[b][j], in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__restrict__ partial,
+                                                            int nblocks, int nj,
+                                                            double *__restrict__ out) {
+    __shared__ double s[kBlock];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) acc += partial[(size_t)b * nj + j];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = s[0];
+}
+
+hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
+                           const TracksDev &t, const double *offs, const double *gstep,
+                           const double *ghit, double *g_o, double *g_d, double *partial,
+                           double *g_off, hipStream_t st) {
+    const int64_t need = (t.n + kBlock - 1) / kBlock;
+    const int nblocks = (int)(need < kBackwardMaxBlocks ? (need > 0 ? need : 1) : kBackwardMaxBlocks);
+    double *part = (g_off && nd > 0) ? partial : nullptr;
+    if (t.n > 0 || part) {
+        if (offs)
+            hipLaunchKernelGGL((k_nav_backward<true>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
+                               offs, gstep, ghit, g_o, g_d, part);
+        else
+            hipLaunchKernelGGL((k_nav_backward<false>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
+                               offs, gstep, ghit, g_o, g_d, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (part) {
+        hipLaunchKernelGGL(k_reduce_partials, dim3(3 * nd), dim3(kBlock), 0, st, part, nblocks, 3 * nd,
+                           g_off);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+}  // namespace gn

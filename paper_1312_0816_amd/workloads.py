@@ -107,7 +107,7 @@ def _sample_in_shape(rng, kind, par, n):
         # Radii vary linearly between the end faces; the cross-section area
         # pi (ro^2 - ri^2) sets the z density. Sample z by acceptance against
         # the bound max(rmax1, rmax2)^2, then r^2 uniform in the annulus.
-        zs = []
+        zs = [np.zeros(0)]
         need = n
         bound = max(rmax1, rmax2) ** 2
         while need > 0:

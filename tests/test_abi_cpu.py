@@ -1,0 +1,113 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/geonav.h declares, and rejects bad arguments before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1312_0816_amd import build as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "geonav.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(geo_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def gv():
+    if not os.path.exists(B.LIB):
+        pytest.skip("libgeonav.so not built")
+    from paper_1312_0816_amd import geonav
+    geonav.load_library()
+    return geonav
+
+
+def test_header_declares_the_boundary():
+    fns = declared_functions()
+    for name in ("geo_shape_query", "geo_navigate_basket", "geo_navigate_batched",
+                 "geo_navigate_backward", "geo_geometry_create", "geo_geometry_destroy",
+                 "geo_autotune", "geo_strerror"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol(gv):
+    lib = C.CDLL(B.LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(gv.EXPORTS) == set(declared_functions())
+
+
+def test_strerror(gv):
+    lib = gv.load_library()
+    assert lib.geo_strerror(0) == b"success"
+    assert lib.geo_strerror(-1)
+    assert lib.geo_strerror(12345) == b"unknown status"
+
+
+def _bad_shape_call(gv, kind, par):
+    lib = gv.load_library()
+    s = gv.GeoShape(kind, 0, (C.c_double * 5)(*par))
+    t = gv.GeoTracks(None, None, None, None, None, None, 0)
+    return lib.geo_shape_query(C.byref(s), 0, t, None, None)
+
+
+def test_shape_validation_without_device(gv):
+    lib = gv.load_library()
+    assert _bad_shape_call(gv, 0, [10, 20, 30, 0, 0]) == 0          # n == 0 is a no-op
+    assert _bad_shape_call(gv, 7, [10, 20, 30, 0, 0]) == -1         # unknown kind
+    assert _bad_shape_call(gv, 0, [10, -1, 30, 0, 0]) == -1         # negative half-length
+    assert _bad_shape_call(gv, 1, [16, 15, 20, 0, 0]) == -1         # rmin > rmax
+    assert _bad_shape_call(gv, 2, [0, 0, 10, 5, 20]) == -1          # dz = 0
+    assert _bad_shape_call(gv, 2, [20, 0, 10, 25, 20]) == -1        # rmin2 > rmax2
+    assert _bad_shape_call(gv, 0, [np.nan, 1, 1, 0, 0]) == -1
+    assert b"rmin" in lib.geo_strerror(_bad_shape_call(gv, 1, [16, 15, 20, 0, 0]))
+    s = gv.GeoShape(0, 0, (C.c_double * 5)(10, 20, 30, 0, 0))
+    t = gv.GeoTracks(None, None, None, None, None, None, 5)          # NULL arrays with n > 0
+    assert lib.geo_shape_query(C.byref(s), 0, t, None, None) == -1
+    t = gv.GeoTracks(None, None, None, None, None, None, -1)
+    assert lib.geo_shape_query(C.byref(s), 0, t, None, None) == -1
+    assert lib.geo_shape_query(C.byref(s), 9, gv.GeoTracks(), None, None) == -1   # bad query
+    assert lib.geo_shape_query(None, 0, gv.GeoTracks(), None, None) == -1
+
+
+def test_geometry_validation_without_device(gv):
+    from paper_1312_0816_amd import workloads as W
+    vol = W.toy_detector_volume()
+    bad = W.Volume(vol.mother_kind, vol.mother_par, vol.kinds, vol.pars, vol.rots.copy(), vol.trs,
+                   vol.bound_r)
+    bad.rots[3] = bad.rots[3] * 1.001                                  # not orthonormal
+    with pytest.raises(gv.GeoError, match="rotation"):
+        gv.Geometry([bad])
+    bad2 = W.Volume(vol.mother_kind, vol.mother_par, vol.kinds, vol.pars, vol.rots.copy(), vol.trs,
+                    vol.bound_r)
+    bad2.rots[0] = -bad2.rots[0]                                       # reflection, det -1
+    with pytest.raises(gv.GeoError, match="rotation"):
+        gv.Geometry([bad2])
+    lib = gv.load_library()
+    h = C.c_void_p()
+    assert lib.geo_geometry_create(None, 0, C.byref(h)) == -1
+    assert lib.geo_geometry_create(None, 1, None) == -1
+
+
+def test_batched_and_nav_validation_without_device(gv):
+    lib = gv.load_library()
+    t = gv.GeoTracks(None, None, None, None, None, None, 0)
+    assert lib.geo_navigate_basket(None, 0, t, None, None, None, None, None) == -1
+    assert lib.geo_navigate_batched(None, None, 0, t, None, None, None) == -1
+    assert lib.geo_navigate_backward(None, 0, t, None, None, None, None, None, None, None) == -1
+    assert lib.geo_set_launch_config(None, 1, 1) == -1
+
+
+def test_binding_rejects_cpu_tensors(gv):
+    import torch
+    t = torch.zeros((6, 4), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        gv.geo_shape_query(0, [10, 20, 30], 0, t)
+    with pytest.raises(ValueError):
+        gv.tracks_struct(torch.zeros((6, 4), dtype=torch.float32))

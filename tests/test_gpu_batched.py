@@ -1,0 +1,159 @@
+"""The batched persistent navigator (geo_navigate_batched): bit-identical to
+per-basket launches, oracle parity on samples, every launch shape, graph
+replays, and the autotuner."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1312_0816_amd import workloads as W
+from tests.parity import check_values, ill_conditioned
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gv():
+    import torch
+    from paper_1312_0816_amd import geonav
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    geonav.load_library()
+    return geonav
+
+
+@pytest.fixture(scope="module")
+def small():
+    return W.batched_c3(scale=0.03)
+
+
+def per_basket(gv, g, wl, t):
+    import torch
+    n = t.shape[1]
+    step = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    hit = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    for b in range(len(wl.basket_n)):
+        o, m = int(wl.basket_offset[b]), int(wl.basket_n[b])
+        if m == 0:
+            continue
+        sub = t[:, o:o + m].contiguous()
+        s, h = gv.geo_navigate_basket(g, int(wl.basket_volume[b]), sub)
+        step[o:o + m] = s
+        hit[o:o + m] = h
+    torch.cuda.synchronize()
+    return step.cpu().numpy(), hit.cpu().numpy()
+
+
+def batched(gv, g, wl, t):
+    import torch
+    s, h = gv.geo_navigate_batched(g, wl.basket_volume, wl.basket_offset, wl.basket_n, t)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), h.cpu().numpy()
+
+
+def test_batched_bit_identical_to_per_basket(gv, small):
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    s0, h0 = per_basket(gv, g, small, t)
+    for U in (1, 2, 4):
+        for Wv in (1, 2, 4, 8):
+            g.set_launch_config(U, Wv)
+            s1, h1 = batched(gv, g, small, t)
+            assert np.array_equal(s1.view(np.int64), s0.view(np.int64)), (U, Wv)
+            assert np.array_equal(h1, h0), (U, Wv)
+    g.close()
+
+
+def test_batched_matches_oracle(gv, orc, small):
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    s, h = batched(gv, g, small, t)
+    rng = np.random.default_rng(4)
+    for b in rng.choice(len(small.basket_n), size=40, replace=False):
+        o, m = int(small.basket_offset[b]), int(small.basket_n[b])
+        vol = small.volumes[int(small.basket_volume[b])]
+        tr = np.ascontiguousarray(small.tracks[:, o:o + m])
+        ref, ill = ill_conditioned(lambda x: orc.navigate(vol, x, None, "d")[0],
+                                   lambda x: orc.navigate(vol, x, None, "ld")[0], tr)
+        check_values(s[o:o + m], ref, ill, f"basket {b}")
+        _, rh, gap = orc.navigate(vol, tr, None, "ld")
+        assert np.array_equal(h[o:o + m][gap >= 1e-9], rh[gap >= 1e-9])
+    g.close()
+
+
+def test_graph_replays_interleaved(gv, small):
+    """Replay the cached graph several times with other device work and host
+    synchronisation in between; every replay equals the first."""
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    s0, h0 = batched(gv, g, small, t)
+    for rep in range(5):
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()
+        step = torch.zeros(t.shape[1], dtype=torch.float64, device="cuda")
+        hit = torch.zeros(t.shape[1], dtype=torch.int32, device="cuda")
+        gv.geo_navigate_batched(g, small.basket_volume, small.basket_offset, small.basket_n, t, step, hit)
+        junk.item()
+        torch.cuda.synchronize()
+        assert np.array_equal(step.cpu().numpy(), s0)
+        assert np.array_equal(hit.cpu().numpy(), h0)
+    # a different basket list (a subset, reversed) on the same handle
+    sel = np.arange(len(small.basket_n))[::-3]
+    step = torch.full((t.shape[1],), -5.0, dtype=torch.float64, device="cuda")
+    hit = torch.full((t.shape[1],), -5, dtype=torch.int32, device="cuda")
+    gv.geo_navigate_batched(g, small.basket_volume[sel], small.basket_offset[sel], small.basket_n[sel], t,
+                            step, hit)
+    torch.cuda.synchronize()
+    s2, h2 = step.cpu().numpy(), hit.cpu().numpy()
+    covered = np.zeros(t.shape[1], bool)
+    for b in sel:
+        covered[small.basket_offset[b]:small.basket_offset[b] + small.basket_n[b]] = True
+    assert np.array_equal(s2[covered], s0[covered]) and np.array_equal(h2[covered], h0[covered])
+    assert np.all(s2[~covered] == -5.0) and np.all(h2[~covered] == -5)
+    g.close()
+
+
+def test_full_workload_bit_identical(gv):
+    """The full 512-basket, 64-volume workload (about 4.4M tracks)."""
+    import torch
+    wl = W.batched_c3()
+    assert len(wl.volumes) == 64 and len(wl.basket_n) == 512
+    g = gv.Geometry(wl.volumes)
+    t = torch.from_numpy(wl.tracks).cuda()
+    s0, h0 = per_basket(gv, g, wl, t)
+    s1, h1 = batched(gv, g, wl, t)
+    assert np.array_equal(s1.view(np.int64), s0.view(np.int64))
+    assert np.array_equal(h1, h0)
+    g.close()
+
+
+def test_empty_baskets_and_errors(gv, small):
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    s, h = gv.geo_navigate_batched(g, [0, 1], [0, 5], [0, 0], t)   # all empty: no-op
+    with pytest.raises(gv.GeoError):
+        gv.geo_navigate_batched(g, [0], [t.shape[1] - 2], [5], t)  # past the pool
+    with pytest.raises(gv.GeoError):
+        gv.geo_navigate_batched(g, [99], [0], [5], t)             # bad volume
+    g.close()
+
+
+def test_autotune_and_cache(gv, small, tmp_path, monkeypatch):
+    import torch
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("GEONAV_AUTOTUNE_CACHE", str(path))
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    u, w = gv.geo_autotune(g, small.basket_volume, small.basket_offset, small.basket_n, t)
+    assert u in (1, 2, 4) and 1 <= w <= 8
+    data = json.loads(path.read_text())
+    assert len(data) == 1 and list(data.values())[0] == [u, w]
+    g2 = gv.Geometry(small.volumes)
+    g2.set_launch_config(1, 1)
+    assert gv.geo_autotune(g2, small.basket_volume, small.basket_offset, small.basket_n, t) == (u, w)
+    g.close()
+    g2.close()
+    assert os.path.exists(path)

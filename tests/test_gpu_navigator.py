@@ -1,0 +1,133 @@
+"""Parity of the HIP navigator (geo_navigate_basket) with the oracle."""
+import numpy as np
+import pytest
+
+from paper_1312_0816_amd import workloads as W
+from tests.parity import check_values, ill_conditioned
+from tests.util import to_local
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gv():
+    import torch
+    from paper_1312_0816_amd import geonav
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    geonav.load_library()
+    return geonav
+
+
+def run_nav(gv, vol, tracks, offsets=None, hitpt=False):
+    import torch
+    g = gv.Geometry([vol])
+    t = torch.from_numpy(np.ascontiguousarray(tracks)).cuda()
+    o = None if offsets is None else torch.from_numpy(np.ascontiguousarray(offsets, np.float64)).cuda()
+    res = gv.geo_navigate_basket(g, 0, t, offsets=o, hitpt=hitpt)
+    torch.cuda.synchronize()
+    out = [r.cpu().numpy() for r in res]
+    g.close()
+    return out
+
+
+def check_nav(orc, vol, tracks, step, hit, offsets=None, what="nav", max_exempt_frac=2e-3):
+    ref, ill = ill_conditioned(lambda t: orc.navigate(vol, t, offsets, "d")[0],
+                               lambda t: orc.navigate(vol, t, offsets, "ld")[0], tracks)
+    rep = check_values(step, ref, ill, what + " step", max_exempt_frac)
+    _, rhit, gap = orc.navigate(vol, tracks, offsets, "ld")
+    tie = gap < 1e-9
+    bad = (hit != rhit) & ~tie
+    assert not bad.any(), f"{what}: {int(bad.sum())} hit mismatches, e.g. {np.nonzero(bad)[0][:5]}"
+    rep["hit_ties"] = int(tie.sum())
+    return rep
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 4099])
+def test_toy_detector_ragged(gv, orc, n):
+    vol, t = W.toy_detector_c2(n=n, seed=1200)
+    step, hit = run_nav(gv, vol, t)
+    check_nav(orc, vol, t, step, hit, what=f"toy n={n}")
+
+
+def test_toy_detector_full_size_sampled(gv, orc):
+    """The 2^22-track toy-detector workload in one launch; 12000 sampled
+    tracks compared with the oracle; every output checked for range."""
+    vol, t = W.toy_detector_c2()
+    step, hit = run_nav(gv, vol, t)
+    assert not np.isnan(step).any()
+    assert np.all((step > 0) & (step < 700))
+    assert np.all((hit >= -1) & (hit < vol.nd))
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(t.shape[1], size=12000, replace=False))
+    rep = check_nav(orc, vol, np.ascontiguousarray(t[:, idx]), step[idx], hit[idx], what="toy full")
+    print(rep)
+    # every daughter is hit by some track
+    assert len(np.unique(hit)) == vol.nd + 1
+
+
+def test_offsets_and_hit_points(gv, orc):
+    vol, t = W.toy_detector_c2(n=5000, seed=77)
+    offs = np.random.default_rng(1).uniform(-3, 3, (vol.nd, 3))
+    step, hit, hp = run_nav(gv, vol, t, offsets=offs, hitpt=True)
+    check_nav(orc, vol, t, step, hit, offsets=offs, what="offsets")
+    want = t[:3] + step[None, :] * t[3:]
+    assert np.all(np.abs(hp - want) <= 1e-12 * np.maximum(np.abs(want), 1))
+    # the hit point lies on the hit daughter's surface
+    for k in range(vol.nd):
+        sel = hit == k
+        if not sel.any():
+            continue
+        q = to_local(vol, k, hp[:, sel], offs)
+        s = orc.safety(int(vol.kinds[k]), vol.pars[k], np.concatenate([q, np.zeros_like(q)]))
+        assert np.all(s < 1e-9)
+
+
+def test_tracks_inside_daughters_and_outside_mother(gv, orc):
+    """A track inside daughter k gets step 0 and hit k; a track outside the
+    mother gets step 0 and hit -1."""
+    vol = W.toy_detector_volume()
+    p = np.array(vol.trs[:5]).T                       # daughter centres (inside unless in a hole)
+    p = np.concatenate([p, np.array([[250.0, 0, 0], [0, -300.0, 10.0]]).T], axis=1)
+    u = np.stack(W.isotropic(np.random.default_rng(0), p.shape[1]))
+    t = np.concatenate([p, u])
+    step, hit = run_nav(gv, vol, t)
+    rs, rh, _ = orc.navigate(vol, t, prec="ld")
+    assert np.array_equal(step == 0, rs == 0)
+    assert np.all(np.abs(step - rs) <= 1e-12 * np.maximum(np.abs(rs), 1))
+    assert np.array_equal(hit, rh)
+    assert step[-1] == 0 and hit[-1] == -1 and step[-2] == 0 and hit[-2] == -1
+
+
+def test_other_mothers_and_no_daughters(gv, orc):
+    """Tube and cone mothers, and a volume with no daughters."""
+    rng = np.random.default_rng(8)
+    cases = [
+        W.Volume(W.TUBE, np.array([20.0, 300.0, 250.0, 0, 0])),
+        W.Volume(W.CONE, np.array([250.0, 10.0, 200.0, 30.0, 350.0])),
+        W.Volume(W.BOX, np.array([100.0, 50.0, 70.0, 0, 0])),
+    ]
+    det = W.toy_detector_volume()
+    cases.append(W.Volume(W.TUBE, np.array([0.0, 330.0, 210.0, 0, 0]), det.kinds, det.pars, det.rots,
+                          det.trs, det.bound_r))
+    for vol in cases:
+        n = 3000
+        p = rng.uniform(-150, 150, (3, n))
+        u = np.stack(W.isotropic(rng, n))
+        t = np.concatenate([p, u])
+        step, hit = run_nav(gv, vol, t)
+        check_nav(orc, vol, t, step, hit, what=f"mother {vol.mother_kind}")
+
+
+def test_empty_and_errors(gv):
+    import torch
+    vol = W.toy_detector_volume()
+    g = gv.Geometry([vol])
+    t = torch.empty((6, 0), dtype=torch.float64, device="cuda")
+    s, h = gv.geo_navigate_basket(g, 0, t)
+    assert s.numel() == 0
+    t = torch.zeros((6, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(gv.GeoError):
+        gv.geo_navigate_basket(g, 3, t)
+    with pytest.raises(ValueError):
+        gv.geo_navigate_basket(g, 0, t, offsets=torch.zeros((2, 3), dtype=torch.float64, device="cuda"))
+    g.close()

@@ -1,0 +1,160 @@
+"""Parity of the HIP shape queries (geo_shape_query) with the oracle."""
+import numpy as np
+import pytest
+
+from paper_1312_0816_amd import workloads as W
+from tests.parity import BIG, check_values, ill_conditioned, rel_diff
+from tests.util import load_closed_forms
+
+pytestmark = pytest.mark.gpu
+
+QUERIES = (0, 1, 2, 3)
+QNAME = {0: "Contains", 1: "Safety", 2: "DistFromInside", 3: "DistFromOutside"}
+
+
+@pytest.fixture(scope="module")
+def gv():
+    import torch
+    from paper_1312_0816_amd import geonav
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    geonav.load_library()
+    return geonav
+
+
+def gpu_query(gv, kind, par, q, tracks_np):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(tracks_np)).cuda()
+    out = gv.geo_shape_query(kind, par, q, t)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def compare(gv, orc, kind, par, tracks, what, max_exempt_frac=2e-3):
+    reps = []
+    for q in QUERIES:
+        got = gpu_query(gv, kind, par, q, tracks)
+        if q == 0:
+            ref = orc.contains(kind, par, tracks, "ld")
+            near = orc.safety(kind, par, tracks, "ld") < 1e-9
+            bad = (got != ref) & ~near
+            assert not bad.any(), f"{what} Contains: {int(bad.sum())} mismatches"
+            assert near.sum() <= max(8, max_exempt_frac * got.size)
+            reps.append({"what": f"{what} Contains", "exempt": int(near.sum())})
+            continue
+        ref, ill = ill_conditioned(lambda t: orc.shape_query(kind, par, q, t, "d"),
+                                   lambda t: orc.shape_query(kind, par, q, t, "ld"), tracks)
+        reps.append(check_values(got, ref, ill, f"{what} {QNAME[q]}", max_exempt_frac))
+    return reps
+
+
+def test_box_small_workload(gv, orc):
+    kind, par, t = W.box_c0()
+    reps = compare(gv, orc, kind, par, t, "box c0")
+    print(reps)
+
+
+def test_closed_forms_on_gpu(gv):
+    """The hand-derived closed forms (axis-aligned and in-plane rays, zero
+    direction components) through the GPU path."""
+    for kind, par, q, p, d, val, text in load_closed_forms():
+        tr = np.array([[p[0]], [p[1]], [p[2]], [d[0]], [d[1]], [d[2]]])
+        got = gpu_query(gv, kind, par, q, tr)[0]
+        if q == 0:
+            assert int(got) == int(val), text
+        elif val == BIG:
+            assert got == BIG, (text, got)
+        else:
+            assert abs(got - val) <= 1e-13 * max(1.0, abs(val)), (text, got, val)
+
+
+@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+@pytest.mark.parametrize("n", [1, 257, 3001])
+def test_suite_ragged_sizes(gv, orc, kind, n):
+    """Several workgroups plus a ragged tail, every track compared."""
+    _, par, t = W.shape_suite_c1(kind, n=n, seed=2024 + n)
+    compare(gv, orc, kind, par, t, f"{W.KIND_NAMES[kind]} n={n}")
+
+
+@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+def test_suite_full_size_sampled(gv, orc, kind):
+    """The 2^20-track shape-suite workload in one launch per query; a random
+    sample of 60000 outputs is compared track by track with the oracle, and
+    every output is checked for NaN and for the hard bounds
+    0 <= DistFrom* and Safety >= 0, with Contains equal to the oracle's
+    everywhere except within 1e-9 of the surface."""
+    _, par, t = W.shape_suite_c1(kind)
+    n = t.shape[1]
+    full = {q: gpu_query(gv, kind, par, q, t) for q in QUERIES}
+    ref_in = orc.contains(kind, par, t, "d")
+    saf = orc.safety(kind, par, t, "d")
+    bad = (full[0] != ref_in) & (saf >= 1e-9)
+    assert not bad.any()
+    for q in (1, 2, 3):
+        assert not np.isnan(full[q]).any()
+        assert (full[q] >= 0).all()
+    # DistFromInside is 0 exactly outside, DistFromOutside 0 exactly inside
+    assert np.all(full[2][full[0] == 0] == 0.0)
+    assert np.all(full[3][full[0] == 1] == 0.0)
+    rng = np.random.default_rng(99)
+    idx = np.sort(rng.choice(n, size=60000, replace=False))
+    sub = np.ascontiguousarray(t[:, idx])
+    for q in (1, 2, 3):
+        ref, ill = ill_conditioned(lambda tt: orc.shape_query(kind, par, q, tt, "d"),
+                                   lambda tt: orc.shape_query(kind, par, q, tt, "ld"), sub)
+        rep = check_values(full[q][idx], ref, ill, f"{W.KIND_NAMES[kind]} full {QNAME[q]}")
+        print(rep)
+
+
+def test_tube_equals_equal_radii_cone_on_gpu(gv):
+    """cone(dz, a, b, a, b) and tube(a, b, dz) go through different kernels and
+    must agree (C12)."""
+    _, par, t = W.shape_suite_c1(W.TUBE, n=50000, seed=5)
+    cpar = [par[2], par[0], par[1], par[0], par[1]]
+    for q in QUERIES:
+        a = gpu_query(gv, W.TUBE, par, q, t)
+        b = gpu_query(gv, W.CONE, cpar, q, t)
+        if q == 0:
+            assert np.mean(a != b) < 1e-4
+        else:
+            assert np.mean(rel_diff(b, a) > 1e-12) < 1e-4
+
+
+def test_hole_free_and_pointed_shapes(gv, orc):
+    """Tubes and cones without a hole, and a pointed cone (rmax1 = 0)."""
+    shapes = [(W.TUBE, [0.0, 15.0, 20.0, 0, 0]), (W.CONE, [20.0, 0.0, 10.0, 0.0, 20.0]),
+              (W.CONE, [10.0, 0.0, 0.0, 0.0, 10.0]), (W.CONE, [15.0, 3.0, 12.0, 0.0, 6.0])]
+    rng = np.random.default_rng(17)
+    for kind, par in shapes:
+        p = rng.uniform(-40, 40, (3, 4000))
+        u = np.stack(W.isotropic(rng, 4000))
+        compare(gv, orc, kind, par, np.concatenate([p, u]), f"{kind} {par}")
+
+
+def test_axis_aligned_and_unnormalised_directions(gv, orc):
+    """Directions with exact zero components and non-unit lengths (C6, C7)."""
+    rng = np.random.default_rng(3)
+    for kind in (W.BOX, W.TUBE, W.CONE):
+        par = W.SUITE_SHAPES[kind]
+        p = rng.uniform(-40, 40, (3, 3000))
+        axis = rng.integers(0, 3, 3000)
+        u = np.zeros((3, 3000))
+        u[axis, np.arange(3000)] = rng.choice([-1.0, 1.0], 3000) * rng.uniform(0.5, 3.0, 3000)
+        t = np.concatenate([p, u])
+        compare(gv, orc, kind, par, t, f"{W.KIND_NAMES[kind]} axis-aligned")
+
+
+def test_empty_basket_is_noop(gv):
+    import torch
+    t = torch.empty((6, 0), dtype=torch.float64, device="cuda")
+    for q in QUERIES:
+        out = gv.geo_shape_query(W.BOX, [1, 1, 1], q, t)
+        assert out.numel() == 0
+
+
+def test_errors_raise(gv):
+    import torch
+    t = torch.zeros((6, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(gv.GeoError):
+        gv.geo_shape_query(W.TUBE, [5, 1, 1], 0, t)
+    with pytest.raises(ValueError):
+        gv.geo_shape_query(W.BOX, [1, 1, 1], 3, t[:3].contiguous())
