@@ -1,0 +1,305 @@
+"""Benchmark: batched navigator throughput on one MI355X.
+
+One step = one geo_navigate_batched call over the batched workload: 512
+baskets (sizes log-uniform in 32..65536 tracks) over 64 logical volumes,
+each a box mother (200)^3 with 1..64 daughters (box/tube/cone) on a 4x4x4
+grid (about 4.26M tracks, FP64). The step runs the whole navigator path:
+basket load, geometry access, master-to-local transforms, every daughter's
+DistFromOutside, the mother's DistFromInside, min/argmin and the outputs,
+scheduled as one persistent launch from a cached HIP graph.
+
+Printed: one JSON line with tracks/s, the plain per-basket comparison (512
+separate geo_navigate_basket launches doing the same work), the roofline of
+the dominant kernel (the persistent navigator, FP64-ALU-bound), the HBM
+fraction, and the CPU oracle timed on this host on the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
+                       [--launch U,W | --no-autotune]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "navigator tracks/sec at 1e-12 rel err (batched vs plain) + % HBM roofline"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6          # 256 CU x 64 FP64 FMA lanes x 2 flop x 2.4 GHz
+BYTES_PER_TRACK = 60             # 6 x 8 B in (x, y, z, ux, uy, uz) + 8 B step + 4 B hit
+
+# Algorithmic FP64 operations (add, sub, mul, div, sqrt = 1; fma = 2) of the
+# navigator formulas, per (track, daughter) and per track for the mother.
+FLOPS_TRANSFORM = 33             # p - T (3), R^T w (15), R^T d (15)
+FLOPS_DIST_OUT = {               # per kind, (no hole, hole)
+    0: (21, 21),                 # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)
+    1: (28, 37),                 # tube: r^2, z planes (10), A, B, outer cylinder (9), inner (9)
+    2: (40, 55),                 # cone: r^2, w_out, w_in, squares, z planes, outer (15), inner (15)
+}
+FLOPS_DIST_IN_MOTHER = {0: 6, 1: 25, 2: 43}   # with a hole (upper count)
+
+
+def _hole(kind, par):
+    if kind == 1:
+        return par[0] > 0
+    if kind == 2:
+        return par[1] > 0 or par[3] > 0
+    return False
+
+
+def flops_per_track(vol) -> int:
+    f = FLOPS_DIST_IN_MOTHER[int(vol.mother_kind)]
+    for k in range(vol.nd):
+        kind = int(vol.kinds[k])
+        f += FLOPS_TRANSFORM + FLOPS_DIST_OUT[kind][1 if _hole(kind, vol.pars[k]) else 0]
+    return f
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("geonav_device.hpp", "geonav_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1312_0816_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(digest: str):
+    """HBM bytes per launch of the persistent kernel from the committed
+    rocprofv3 counter summary, if it was taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", "nav_persistent_batched512_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic:"):
+                for kv in line.split()[1:]:
+                    k, v = kv.split("=")
+                    vals[k] = v
+    if vals.get("kernel_source") != digest:
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, gpu_step, gpu_hit, threads):
+    """Oracle (double build, as it stands) over the whole batched workload on
+    this host's cores; also reports how the GPU outputs compare with it."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle._load()
+    jobs = []
+    for b in range(len(wl.basket_n)):
+        o, m = int(wl.basket_offset[b]), int(wl.basket_n[b])
+        for s in range(0, m, 16384):
+            jobs.append((int(wl.basket_volume[b]), o + s, min(16384, m - s)))
+    n = int(wl.tracks.shape[1])
+    step = np.zeros(n)
+    hit = np.zeros(n, np.int32)
+    gap = np.zeros(n)
+
+    def run(job):
+        v, o, m = job
+        s, h, g = oracle.navigate(wl.volumes[v], np.ascontiguousarray(wl.tracks[:, o:o + m]), None, "d")
+        step[o:o + m] = s
+        hit[o:o + m] = h
+        gap[o:o + m] = g
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, jobs))
+    dt = time.perf_counter() - t0
+    rel = np.abs(gpu_step - step) / np.maximum(np.abs(step), 1.0)
+    parity = {
+        "reference": "oracle double build, all tracks",
+        "tracks": n,
+        "max_rel_err": float(rel.max()),
+        "beyond_1e-12": int((rel > 1e-12).sum()),
+        "hit_mismatch_gap_ge_1e-9": int(((gpu_hit != hit) & (gap >= 1e-9)).sum()),
+        "hit_ties_gap_lt_1e-9": int((gap < 1e-9).sum()),
+    }
+    base = {"value": n / dt, "unit": "tracks/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole batched workload ({n} tracks, {len(wl.basket_n)} baskets), "
+                      f"oracle double build, {threads} threads, {dt:.2f} s"}
+    return base, parity
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="force the batched launch shape 'tracks_per_lane,waves_per_simd' (no autotune)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device copy first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the navigator has no multi-GPU path in this "
+              "build (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1312_0816_amd import geonav as gv
+    from paper_1312_0816_amd import workloads as W
+
+    gv.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    wl = W.batched_c3()
+    n = int(wl.tracks.shape[1])
+    g = gv.Geometry(wl.volumes)
+    t = torch.from_numpy(wl.tracks).to(dev)
+    step = torch.empty(n, dtype=torch.float64, device=dev)
+    hit = torch.empty(n, dtype=torch.int32, device=dev)
+    bv, bo, bn = wl.basket_volume, wl.basket_offset, wl.basket_n
+
+    if args.launch:
+        u_, w_ = (int(v) for v in args.launch.split(","))
+        g.set_launch_config(u_, w_)
+    elif not args.no_autotune:
+        gv.geo_autotune(g, bv, bo, bn, t)
+    U, Wv = g.launch_config()
+
+    # Host-side call arguments are marshalled once; each step is then one C
+    # call (batched) or one C call per basket (plain), on torch's stream.
+    lib = g._lib
+    hs = gv._stream()
+    barr, nb = gv._baskets(bv, bo, bn)
+    tr_all = gv.tracks_struct(t)
+    sp, hp = gv._ptr(step), gv._ptr(hit)
+
+    def batched_step():
+        gv._check(lib.geo_navigate_batched(g.handle, barr, nb, tr_all, sp, hp, hs))
+
+    # plain form: one launch per basket on the same pool, outputs at the same
+    # positions
+    pstep = torch.empty(n, dtype=torch.float64, device=dev)
+    phit = torch.empty(n, dtype=torch.int32, device=dev)
+    plain = []
+    for b in range(len(bn)):
+        o, m = int(bo[b]), int(bn[b])
+        if m == 0:
+            continue
+        tb = gv.GeoTracks(*[tr_all.x + 8 * o, tr_all.y + 8 * o, tr_all.z + 8 * o,
+                            tr_all.ux + 8 * o, tr_all.uy + 8 * o, tr_all.uz + 8 * o], m)
+        plain.append((int(bv[b]), tb, gv.C.c_void_p(pstep.data_ptr() + 8 * o),
+                      gv.C.c_void_p(phit.data_ptr() + 4 * o)))
+
+    def plain_step():
+        for v, tb, s_, h_ in plain:
+            gv._check(lib.geo_navigate_basket(g.handle, v, tb, None, s_, h_, None, hs))
+
+    # warmup
+    for _ in range(args.warmup):
+        batched_step()
+        plain_step()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(step.view(torch.int64), pstep.view(torch.int64)) and torch.equal(hit, phit))
+
+    # timed: batched, with per-launch HIP events on the launch stream
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        batched_step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ms_per_step = 1e3 * wall / args.steps
+
+    # timed: plain per-basket launches
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_step()
+    torch.cuda.synchronize()
+    plain_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+
+    value = n / (ms_per_step * 1e-3)
+    kernel_ms = float(np.mean(ev_ms))
+    flops = float(sum(int(bn[b]) * flops_per_track(wl.volumes[int(bv[b])]) for b in range(len(bn))))
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    digest = kernel_source_digest()
+    traffic = read_traffic(digest)
+    hbm_gbs = BYTES_PER_TRACK * n / (kernel_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tracks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched navigation: {len(bn)} baskets (32-65536 tracks, log-uniform) over "
+                        f"{len(wl.volumes)} volumes (box mother (200)^3, 1-64 box/tube/cone daughters), "
+                        f"{n} tracks, FP64, one persistent graph launch",
+            "baskets": int(len(bn)), "volumes": int(len(wl.volumes)), "tracks": n,
+            "launch": {"tracks_per_lane": U, "waves_per_simd": Wv, "autotuned": not (args.no_autotune or args.launch)},
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_nav_persistent (+ k_build_tiles node)",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "flops_per_launch": flops,
+            "event_ms_per_launch": kernel_ms,
+        },
+        "hbm": {"achieved_GBps": hbm_gbs, "peak_GBps": HBM_PEAK_GBS, "frac": hbm_gbs / HBM_PEAK_GBS,
+                "bytes_per_track": BYTES_PER_TRACK},
+        "plain_per_basket": {"value": n / (plain_ms * 1e-3), "unit": "tracks/s", "ms_per_step": plain_ms,
+                             "launches": len(plain)},
+        "batched_over_plain": plain_ms / ms_per_step,
+        "batched_equals_plain_bitwise": same,
+        "kernel_source": digest,
+    }
+    if not args.no_cpu:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        base, parity = cpu_baseline(wl, step.cpu().numpy(), hit.cpu().numpy(), threads)
+        out["cpu_baseline"] = base
+        out["parity"] = parity
+    else:
+        out["cpu_baseline"] = None
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -476,7 +476,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
 
     const int grid = persistent_grid(g->waves_per_simd, g->num_cus);
     void *bargs[] = {&ba};
-    void *pargs[] = {&pa};
+    void *pargs[] = {&pa.vols, &pa.dau, &pa.tiles, &pa.ntiles, &pa.cursor, &pa.t, &pa.step, &pa.hit};
     hipKernelNodeParams kb = {};
     kb.func = const_cast<void *>(build_tiles_kernel());
     kb.gridDim = dim3(kBuildTilesBlocks);

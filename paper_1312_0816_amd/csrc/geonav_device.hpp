@@ -296,10 +296,11 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
         const double t = az / fabs(uz);
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
-        const bool top = z > 0.0;
-        const double lo2 = top ? c[11] : c[9];
-        const double hi2 = top ? c[12] : c[10];
-        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= lo2 && r2 <= hi2;
+        // select between the two faces' verdicts (not their constants, which
+        // stay uniform scalars)
+        const bool on_bot = r2 >= c[9] && r2 <= c[10];
+        const bool on_top = r2 >= c[11] && r2 <= c[12];
+        const bool ok = az > 0.0 && z * uz < 0.0 && (z > 0.0 ? on_top : on_bot);
         take(ok, t, 0, best, sid);
     }
     const double A0 = ux * ux + uy * uy;

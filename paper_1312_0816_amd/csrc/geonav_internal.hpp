@@ -18,8 +18,9 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
                              const double *offs, double *step, int32_t *hit, double *hitpt,
                              hipStream_t st);
 
-// Persistent batched navigator; `cursor` is reset by k_build_tiles, which
-// runs just before it in the same graph.
+// Arguments of the persistent batched navigator, in kernel-parameter order
+// (graph kernel nodes pass a pointer to each). `cursor` is reset by
+// k_build_tiles, which runs just before it in the same graph.
 struct PersistentArgs {
     const VolumeRec *vols;
     const DaughterRec *dau;

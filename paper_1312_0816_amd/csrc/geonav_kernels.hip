@@ -120,28 +120,33 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
 // 64 * U tracks of one volume, so the volume and its daughters are uniform
 // over the wavefront.
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_nav_persistent(PersistentArgs a) {
+__global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__restrict__ vols,
+                                                           const DaughterRec *__restrict__ dau_all,
+                                                           const Tile *__restrict__ tiles,
+                                                           int32_t ntiles, unsigned int *cursor,
+                                                           TracksDev t, double *__restrict__ step,
+                                                           int32_t *__restrict__ hit) {
     const int lane = threadIdx.x & 63;
     for (;;) {
         unsigned int id = 0;
-        if (lane == 0) id = atomicAdd(a.cursor, 1u);
+        if (lane == 0) id = atomicAdd(cursor, 1u);
         id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
-        if (id >= (unsigned int)a.ntiles) break;
-        const Tile tl = a.tiles[id];
-        const VolumeRec &v = a.vols[tl.volume];
-        const DaughterRec *dau = a.dau + v.first;
+        if (id >= (unsigned int)ntiles) break;
+        const Tile tl = tiles[id];
+        const VolumeRec &v = vols[tl.volume];
+        const DaughterRec *dau = dau_all + v.first;
 #pragma unroll 1
         for (int u = 0; u < U; ++u) {
             const int j = u * 64 + lane;
             if (j < tl.count) {
                 const int64_t i = tl.offset + j;
-                const double x = a.t.x[i], y = a.t.y[i], z = a.t.z[i];
-                const double ux = a.t.ux[i], uy = a.t.uy[i], uz = a.t.uz[i];
+                const double x = t.x[i], y = t.y[i], z = t.z[i];
+                const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
                 double best;
                 int h, sid;
                 nav_track<false, false>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h, sid);
-                a.step[i] = best;
-                a.hit[i] = h;
+                step[i] = best;
+                hit[i] = h;
             }
         }
     }
