@@ -36,31 +36,29 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6          # 256 CU x 64 FP64 FMA lanes x 2 flop x 2.4 GHz
 BYTES_PER_TRACK = 60             # 6 x 8 B in (x, y, z, ux, uy, uz) + 8 B step + 4 B hit
 
-# Algorithmic FP64 operations (add, sub, mul, div, sqrt = 1; fma = 2) of the
-# navigator formulas, per (track, daughter) and per track for the mother.
-FLOPS_TRANSFORM = 33             # p - T (3), R^T w (15), R^T d (15)
-FLOPS_DIST_OUT = {               # per kind, (no hole, hole)
-    0: (21, 21),                 # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)
-    1: (28, 37),                 # tube: r^2, z planes (10), A, B, outer cylinder (9), inner (9)
-    2: (40, 55),                 # cone: r^2, w_out, w_in, squares, z planes, outer (15), inner (15)
-}
-FLOPS_DIST_IN_MOTHER = {0: 6, 1: 25, 2: 43}   # with a hole (upper count)
+# Algorithmic FP64 operations of the navigator formulas (add, sub, mul, div,
+# sqrt = 1 flop; fma = 2), counted from the per-lane algorithm. The work a
+# launch does comes from the library's census (geo_navigate_batched_census):
+# lane-evaluations per daughter kind, culling tests and tracks.
+FLOPS_MOTHER_BOX = 6             # box DistFromInside: 3 x (sub, div)
+FLOPS_TRACK_CULL = 5             # |d|^2 once per track (culling on)
+FLOPS_CULL_TEST = 20             # w = p - T (3), b (5), |w|^2 - R^2 (6), disc (3), m (2), m^2 (1)
+FLOPS_ROTATION = 30              # R^T w and R^T d (2 x 3 x (mul + 2 fma))
+FLOPS_DIST_OUT = [               # census slot 2 * kind + hole
+    21, 21,                      # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)
+    28, 37,                      # tube: r^2, z planes (10), A, B, outer (9) [, inner (9)]
+    40, 55,                      # cone: r^2, radii, squares, z planes, outer (15) [, inner (15)]
+]
 
 
-def _hole(kind, par):
-    if kind == 1:
-        return par[0] > 0
-    if kind == 2:
-        return par[1] > 0 or par[3] > 0
-    return False
-
-
-def flops_per_track(vol) -> int:
-    f = FLOPS_DIST_IN_MOTHER[int(vol.mother_kind)]
-    for k in range(vol.nd):
-        kind = int(vol.kinds[k])
-        f += FLOPS_TRANSFORM + FLOPS_DIST_OUT[kind][1 if _hole(kind, vol.pars[k]) else 0]
-    return f
+def census_flops(counts, cull: bool) -> float:
+    """FP64 flops of one launch from its census counts."""
+    f = counts[7] * (FLOPS_MOTHER_BOX + (FLOPS_TRACK_CULL if cull else 0))
+    f += counts[6] * FLOPS_CULL_TEST
+    per_eval_extra = FLOPS_ROTATION + (0 if cull else 3)   # without culling w is part of the evaluation
+    for slot in range(6):
+        f += counts[slot] * (per_eval_extra + FLOPS_DIST_OUT[slot])
+    return float(f)
 
 
 def kernel_source_digest() -> str:
@@ -221,6 +219,9 @@ def main():
     torch.cuda.synchronize()
     same = bool(torch.equal(step.view(torch.int64), pstep.view(torch.int64)) and torch.equal(hit, phit))
 
+    # work census of one launch (instrumented variant, outside the timed region)
+    _, _, counts = gv.geo_navigate_batched_census(g, bv, bo, bn, t)
+
     # timed: batched, with per-launch HIP events on the launch stream
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
@@ -235,6 +236,21 @@ def main():
     ev_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     ms_per_step = 1e3 * wall / args.steps
 
+    # the same batched launch without wavefront culling (every daughter of
+    # every track evaluated), for the record
+    g.culling = False
+    _, _, counts_nocull = gv.geo_navigate_batched_census(g, bv, bo, bn, t)
+    for _ in range(2):
+        batched_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched_step()
+    torch.cuda.synchronize()
+    nocull_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    g.culling = True
+    batched_step()
+
     # timed: plain per-basket launches
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -245,7 +261,8 @@ def main():
 
     value = n / (ms_per_step * 1e-3)
     kernel_ms = float(np.mean(ev_ms))
-    flops = float(sum(int(bn[b]) * flops_per_track(wl.volumes[int(bv[b])]) for b in range(len(bn))))
+    flops = census_flops(counts, True)
+    flops_nocull = census_flops(counts_nocull, False)
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     digest = kernel_source_digest()
     traffic = read_traffic(digest)
@@ -273,7 +290,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_nav_persistent (+ k_build_tiles node)",
+            "kernel": "k_nav_persistent (+ k_build_tiles node), culling on",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
@@ -287,6 +304,12 @@ def main():
         "plain_per_basket": {"value": n / (plain_ms * 1e-3), "unit": "tracks/s", "ms_per_step": plain_ms,
                              "launches": len(plain)},
         "batched_over_plain": plain_ms / ms_per_step,
+        "batched_without_culling": {"value": n / (nocull_ms * 1e-3), "unit": "tracks/s",
+                                    "ms_per_step": nocull_ms, "flops_per_launch": flops_nocull,
+                                    "achieved_TFLOPs": flops_nocull / (nocull_ms * 1e-3) / 1e12,
+                                    "frac": flops_nocull / (nocull_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+        "census": {"evaluations_by_kind_hole": counts[:6], "cull_tests": counts[6], "tracks": counts[7],
+                   "evaluations_without_culling": int(sum(counts_nocull[:6]))},
         "batched_equals_plain_bitwise": same,
         "kernel_source": digest,
     }

@@ -159,6 +159,19 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
                           const double *gstep, const double *ghit, double *g_o, double *g_d,
                           double *g_off, hipStream_t stream);
 
+/* Instrumented run of geo_navigate_batched (same outputs, not for timing):
+ * launches directly (no graph) a variant of the batched kernel that tallies
+ * the work it does. counts (host uint64_t[8]):
+ *   counts[2 * kind + hole]  lane-evaluations of DistFromOutside for daughters
+ *                            of that kind (hole = 1 for a tube/cone with an
+ *                            inner surface): every active lane of a
+ *                            wavefront that evaluates the daughter,
+ *   counts[6]                lane culling tests (0 with culling off),
+ *   counts[7]                tracks navigated (mother DistFromInside).
+ * Synchronises the stream. */
+int geo_navigate_batched_census(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
+                                double *step, int32_t *hit, uint64_t counts[8], hipStream_t stream);
+
 /* Time the candidate launch shapes of the batched kernel (tile size, waves
  * per SIMD) on these baskets and keep the fastest in the handle; also records
  * it in the JSON cache named by the GEONAV_AUTOTUNE_CACHE environment
@@ -171,6 +184,15 @@ int geo_autotune(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tra
 int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd);
 /* Force a launch shape (tracks_per_lane in {1, 2, 4}, waves_per_simd 1..8). */
 int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd);
+
+/* Wavefront culling in the navigators (basket, batched, backward): a
+ * daughter is skipped by a whole wavefront when no lane's line can enter the
+ * daughter's bounding sphere (radius enlarged by 1e-6 relative + 1e-6) before
+ * that lane's current best step. The daughter could neither lower a step nor
+ * win a tie, so results are bit-identical with culling on or off; only the
+ * work done changes. On by default. */
+int geo_set_culling(geo_geometry *g, int32_t enable);
+int geo_get_culling(const geo_geometry *g, int32_t *enabled);
 
 /* Message for a status code; for the most recent failure on the calling
  * thread it includes that failure's detail. Never NULL. */

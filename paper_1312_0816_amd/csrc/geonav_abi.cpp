@@ -175,8 +175,9 @@ struct geo_geometry {
     // adjoint partial sums: kBackwardMaxBlocks x 3 x max_nd
     double *d_partial = nullptr;
     // batched state
-    int tracks_per_lane = 2;
+    int tracks_per_lane = 4;
     int waves_per_simd = 4;
+    bool cull = true;               // wavefront bounding-sphere culling in the navigators
     BasketRec *h_baskets = nullptr;  // pinned staging: nb baskets then nb + 1 tile starts
     size_t h_cap = 0;                // bytes
     void *d_bstage = nullptr;        // device copy of the staging block
@@ -189,7 +190,7 @@ struct geo_geometry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node_build = nullptr, node_nav = nullptr;
-    int graph_U = 0, graph_grid = 0;
+    int graph_U = 0, graph_grid = 0, graph_cull = -1;
     std::vector<BasketRec> sorted;   // reused host scratch
 };
 
@@ -202,6 +203,7 @@ void destroy_graph(geo_geometry *g) {
     g->graph = nullptr;
     g->node_build = g->node_nav = nullptr;
     g->graph_U = g->graph_grid = 0;
+    g->graph_cull = -1;
 }
 
 int check_device(const geo_geometry *g) {
@@ -257,6 +259,10 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             snprintf(what, sizeof what, "volume %d daughter %d", iv, k);
             rc = make_shape(d.daughters[k], dr.shape, &dr.bound_r, what);
             if (rc) return rc;
+            {
+                const double rc2 = dr.bound_r * (1.0 + 1e-6) + 1e-6;
+                dr.cull_r2 = rc2 * rc2;
+            }
             rc = check_rotation(d.placements[k].rot, what);
             if (rc) return rc;
             for (int i = 0; i < 3; ++i)
@@ -353,7 +359,8 @@ int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, con
     if ((rc = check_device(g))) return rc;
     const int first = g->h_vols[volume].first;
     hipError_t e = launch_nav_basket(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr, to_dev(t),
-                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, step, hit, hitpt, stream);
+                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, step, hit, hitpt, g->cull,
+                                     stream);
     if (e != hipSuccess) return hip_fail(e, "navigator launch");
     return GEO_OK;
 }
@@ -375,7 +382,7 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
     const int first = g->h_vols[volume].first;
     hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr, nd, to_dev(t),
                                    nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, g->d_partial,
-                                   nd > 0 ? g_off : nullptr, stream);
+                                   nd > 0 ? g_off : nullptr, g->cull, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     return GEO_OK;
 }
@@ -422,7 +429,7 @@ int ensure_capacity(geo_geometry *g, int nb, int64_t ntiles, hipStream_t stream)
 }
 
 int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_tracks &all, double *step,
-                   int32_t *hit, hipStream_t stream) {
+                   int32_t *hit, hipStream_t stream, unsigned long long *census = nullptr) {
     const int U = g->tracks_per_lane;
     const int tile_n = 64 * U;
     // cost-sorted basket list (per-track cost ~ daughters + mother), stable
@@ -474,20 +481,27 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     pa.step = step;
     pa.hit = hit;
 
-    const int grid = persistent_grid(g->waves_per_simd, g->num_cus);
     void *bargs[] = {&ba};
-    void *pargs[] = {&pa.vols, &pa.dau, &pa.tiles, &pa.ntiles, &pa.cursor, &pa.t, &pa.step, &pa.hit};
+    pa.census = nullptr;
+    const int grid = persistent_grid(g->waves_per_simd, g->num_cus);
+    if (census) {
+        GN_HIP(hipMemsetAsync(census, 0, 8 * sizeof(unsigned long long), stream));
+        GN_HIP(launch_census(U, g->cull, grid, ba, pa, census, stream));
+        return GEO_OK;
+    }
+    void *pargs[] = {&pa.vols, &pa.dau, &pa.tiles, &pa.ntiles, &pa.cursor, &pa.t, &pa.step, &pa.hit,
+                     &pa.census};
     hipKernelNodeParams kb = {};
     kb.func = const_cast<void *>(build_tiles_kernel());
     kb.gridDim = dim3(kBuildTilesBlocks);
     kb.blockDim = dim3(kBlock);
     kb.kernelParams = bargs;
     hipKernelNodeParams kn = {};
-    kn.func = const_cast<void *>(persistent_kernel(U));
+    kn.func = const_cast<void *>(persistent_kernel(U, g->cull));
     kn.gridDim = dim3(grid);
     kn.blockDim = dim3(kBlock);
     kn.kernelParams = pargs;
-    if (!g->exec || g->graph_U != U || g->graph_grid != grid) {
+    if (!g->exec || g->graph_U != U || g->graph_grid != grid || g->graph_cull != (int)g->cull) {
         destroy_graph(g);
         GN_HIP(hipGraphCreate(&g->graph, 0));
         GN_HIP(hipGraphAddKernelNode(&g->node_build, g->graph, nullptr, 0, &kb));
@@ -495,6 +509,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
         GN_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
         g->graph_U = U;
         g->graph_grid = grid;
+        g->graph_cull = (int)g->cull;
     } else {
         GN_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->node_build, &kb));
         GN_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->node_nav, &kn));
@@ -536,6 +551,30 @@ int geo_navigate_batched(geo_geometry *g, const geo_basket *b, int32_t nb, geo_t
     return launch_batched(g, b, nb, all, step, hit, stream);
 }
 
+int geo_navigate_batched_census(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks all,
+                                double *step, int32_t *hit, uint64_t counts[8], hipStream_t stream) {
+    if (!counts) return fail(GEO_ERR_INVALID_ARG, "counts is NULL");
+    for (int i = 0; i < 8; ++i) counts[i] = 0;
+    int rc = validate_batched(g, b, nb, all, step, hit, true);
+    if (rc) return rc;
+    if (nb == 0 || all.n == 0) return GEO_OK;
+    if ((rc = check_device(g))) return rc;
+    unsigned long long *d = nullptr;
+    if (hipMalloc(&d, 8 * sizeof(unsigned long long)) != hipSuccess)
+        return fail(GEO_ERR_NOMEM, "census counter allocation failed");
+    rc = launch_batched(g, b, nb, all, step, hit, stream, d);
+    if (rc == GEO_OK) {
+        unsigned long long h[8];
+        hipError_t e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) rc = hip_fail(e, "census readback");
+        else
+            for (int i = 0; i < 8; ++i) counts[i] = h[i];
+    }
+    (void)hipFree(d);
+    return rc;
+}
+
 int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd) {
     if (!g || !tracks_per_lane || !waves_per_simd) return fail(GEO_ERR_INVALID_ARG, "NULL argument");
     *tracks_per_lane = g->tracks_per_lane;
@@ -550,6 +589,18 @@ int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t wave
     if (waves_per_simd < 1 || waves_per_simd > 8) return fail(GEO_ERR_INVALID_ARG, "waves_per_simd must be 1..8");
     g->tracks_per_lane = tracks_per_lane;
     g->waves_per_simd = waves_per_simd;
+    return GEO_OK;
+}
+
+int geo_set_culling(geo_geometry *g, int32_t enable) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    g->cull = enable != 0;
+    return GEO_OK;
+}
+
+int geo_get_culling(const geo_geometry *g, int32_t *enabled) {
+    if (!g || !enabled) return fail(GEO_ERR_INVALID_ARG, "NULL argument");
+    *enabled = g->cull ? 1 : 0;
     return GEO_OK;
 }
 

@@ -41,7 +41,8 @@ struct alignas(16) DaughterRec {
     double rot[9];   // R, row-major
     double tr[3];    // T
     double bound_r;  // radius of a sphere about the local origin holding the shape
-    double pad[3];
+    double cull_r2;  // square of bound_r enlarged by 1e-6 relative + 1e-6 (culling test)
+    double pad[2];
     ShapeRec shape;
 };
 static_assert(sizeof(DaughterRec) == 288, "DaughterRec layout");
@@ -70,6 +71,37 @@ struct Tile {
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ double sq(double a) { return a * a; }
 
+// n / d from the hardware reciprocal refined by two Newton steps: within
+// about one ulp of the rounded quotient, six instructions instead of the
+// eleven of the IEEE division sequence (which also rescales denormal and
+// huge operands). A zero d gives NaN; every call site either has d in the
+// normal range or rejects the result (the NaN fails its t >= 0 / ordering
+// tests).
+__device__ __forceinline__ double fdiv(double n, double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return n * r;
+}
+
+// sqrt(x) from the hardware reciprocal square root with a Goldschmidt step
+// and two corrections (within about one ulp). x below 1e-300 (including 0 and
+// the clamped negative discriminants) gives 0: a tangent line.
+__device__ __forceinline__ double fsqrt(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 1e-300 ? g : 0.0;
+}
+
 // Candidate update: keep the smallest valid t; on equal t the earlier
 // candidate (lower surface id) stays.
 __device__ __forceinline__ void take(bool ok, double t, int id, double &best, int &sid) {
@@ -84,14 +116,14 @@ __device__ __forceinline__ double root_down(double A, double B, double C, double
     const bool neg = B <= 0.0;
     const double num = neg ? C : -(B + s);
     const double den = neg ? (s - B) : A;
-    return num / den;
+    return fdiv(num, den);
 }
 // Root where f goes from - to + (A t + B = +s): (-B + s) / A = -C / (s + B).
 __device__ __forceinline__ double root_up(double A, double B, double C, double s) {
     const bool pos = B >= 0.0;
     const double num = pos ? -C : (s - B);
     const double den = pos ? (s + B) : A;
-    return num / den;
+    return fdiv(num, den);
 }
 
 // ---------------------------------------------------------------------- box
@@ -116,19 +148,19 @@ __device__ __forceinline__ double box_dist_out(const double *c, double x, double
     double best = kBig;
     sid = -1;
     {
-        const double t = ax / fabs(ux);
+        const double t = fdiv(ax, fabs(ux));
         const bool ok = ax > 0.0 && x * ux < 0.0 && fabs(fma(t, uy, y)) <= c[1] &&
                         fabs(fma(t, uz, z)) <= c[2];
         take(ok, t, 0, best, sid);
     }
     {
-        const double t = ay / fabs(uy);
+        const double t = fdiv(ay, fabs(uy));
         const bool ok = ay > 0.0 && y * uy < 0.0 && fabs(fma(t, ux, x)) <= c[0] &&
                         fabs(fma(t, uz, z)) <= c[2];
         take(ok, t, 1, best, sid);
     }
     {
-        const double t = az / fabs(uz);
+        const double t = fdiv(az, fabs(uz));
         const bool ok = az > 0.0 && z * uz < 0.0 && fabs(fma(t, ux, x)) <= c[0] &&
                         fabs(fma(t, uy, y)) <= c[1];
         take(ok, t, 2, best, sid);
@@ -142,9 +174,9 @@ __device__ __forceinline__ double box_dist_in(const double *c, double x, double 
     const bool inside = box_contains(c, x, y, z);
     double best = kBig;
     sid = -1;
-    take(ux != 0.0, (c[0] - (ux > 0.0 ? x : -x)) / fabs(ux), 0, best, sid);
-    take(uy != 0.0, (c[1] - (uy > 0.0 ? y : -y)) / fabs(uy), 1, best, sid);
-    take(uz != 0.0, (c[2] - (uz > 0.0 ? z : -z)) / fabs(uz), 2, best, sid);
+    take(ux != 0.0, fdiv(c[0] - (ux > 0.0 ? x : -x), fabs(ux)), 0, best, sid);
+    take(uy != 0.0, fdiv(c[1] - (uy > 0.0 ? y : -y), fabs(uy)), 1, best, sid);
+    take(uz != 0.0, fdiv(c[2] - (uz > 0.0 ? z : -z), fabs(uz)), 2, best, sid);
     return inside ? best : 0.0;
 }
 
@@ -180,7 +212,7 @@ __device__ __forceinline__ double tube_dist_out(const double *c, int hole, doubl
     sid = -1;
     {   // z planes: from beyond the slab, moving towards it, landing on the annulus
         const double az = fabs(z) - dz;
-        const double t = az / fabs(uz);
+        const double t = fdiv(az, fabs(uz));
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
         const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= c[3] && r2 <= c[4];
@@ -191,15 +223,15 @@ __device__ __forceinline__ double tube_dist_out(const double *c, int hole, doubl
     {   // outer cylinder, entered from r > rmax
         const double C = rsq - c[4];
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
-        const double t = C / (s - B);
+        const double s = fsqrt(fmax(disc, 0.0));
+        const double t = fdiv(C, s - B);
         const bool ok = C > 0.0 && B < 0.0 && disc >= 0.0 && fabs(fma(t, uz, z)) <= dz;
         take(ok, t, 1, best, sid);
     }
     if (hole) {  // inner cylinder, left from inside the hole into the material
         const double C = rsq - c[3];
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_up(A, B, C, s);
         const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
         take(ok, t, 2, best, sid);
@@ -215,20 +247,20 @@ __device__ __forceinline__ double tube_dist_in(const double *c, int hole, double
     const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3];
     double best = kBig;
     sid = -1;
-    take(uz != 0.0, (dz - (uz > 0.0 ? z : -z)) / fabs(uz), 0, best, sid);
+    take(uz != 0.0, fdiv(dz - (uz > 0.0 ? z : -z), fabs(uz)), 0, best, sid);
     const double A = ux * ux + uy * uy;
     const double B = x * ux + y * uy;
     {   // leave the outer cylinder
         const double C = rsq - c[4];
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_up(A, B, C, s);
         take(disc >= 0.0 && t >= 0.0, t, 1, best, sid);
     }
     if (hole) {  // enter the hole's cylinder
         const double C = rsq - c[3];
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_down(A, B, C, s);
         take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
     }
@@ -293,7 +325,7 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
     sid = -1;
     {   // z planes: the face's annulus depends on which end is hit
         const double az = fabs(z) - dz;
-        const double t = az / fabs(uz);
+        const double t = fdiv(az, fabs(uz));
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
         // select between the two faces' verdicts (not their constants, which
@@ -309,7 +341,7 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
         const double v = c[2] * uz;
         const double A = A0 - v * v, B = B0 - v * wo, C = rsq - wo * wo;
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_down(A, B, C, s);
         const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
         take(ok, t, 1, best, sid);
@@ -318,7 +350,7 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
         const double v = c[4] * uz;
         const double A = A0 - v * v, B = B0 - v * wi, C = rsq - wi * wi;
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_up(A, B, C, s);
         const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
         take(ok, t, 2, best, sid);
@@ -336,14 +368,14 @@ __device__ __forceinline__ double cone_dist_in(const double *c, int hole, double
     const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi);
     double best = kBig;
     sid = -1;
-    take(uz != 0.0, (dz - (uz > 0.0 ? z : -z)) / fabs(uz), 0, best, sid);
+    take(uz != 0.0, fdiv(dz - (uz > 0.0 ? z : -z), fabs(uz)), 0, best, sid);
     const double A0 = ux * ux + uy * uy;
     const double B0 = x * ux + y * uy;
     {   // leave the outer nappe
         const double v = c[2] * uz;
         const double A = A0 - v * v, B = B0 - v * wo, C = rsq - wo * wo;
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_up(A, B, C, s);
         take(disc >= 0.0 && t >= 0.0, t, 1, best, sid);
     }
@@ -351,7 +383,7 @@ __device__ __forceinline__ double cone_dist_in(const double *c, int hole, double
         const double v = c[4] * uz;
         const double A = A0 - v * v, B = B0 - v * wi, C = rsq - wi * wi;
         const double disc = B * B - A * C;
-        const double s = sqrt(fmax(disc, 0.0));
+        const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_down(A, B, C, s);
         take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
     }
@@ -421,15 +453,38 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, doubl
 // the mother, then the lowest index). Daughters are walked in lockstep by
 // the whole wavefront, so the daughter record and its kind are uniform
 // (scalar loads, scalar branch).
-template <bool HAS_OFFS, bool TRACK_SURF>
+//
+// With CULL, a daughter is skipped for the whole wavefront when no lane's
+// line can enter the daughter's (slightly enlarged) bounding sphere before
+// that lane's current best step: such a daughter could not lower the best
+// step nor win a tie (ties keep the earlier candidate), so the results are
+// bit-identical to evaluating it. With the sphere centre c, w = p - c,
+// b = w.d, cc = |w|^2 - R^2, disc = b^2 - |d|^2 cc, the line misses the
+// sphere when cc > 0 and (b >= 0 or disc < 0), and it enters no earlier than
+// `best` when m = -b - best |d|^2 >= 0 and m^2 >= disc.
+//
+// With COUNT, the work done is tallied into census[8] (one atomic per
+// wavefront and event, adding the number of active lanes): slots
+// 2 * kind + hole count daughter evaluations, slot 6 culling tests, slot 7
+// tracks.
+__device__ __forceinline__ void census_add(unsigned long long *census, int slot) {
+    const unsigned long long act = __ballot(1);
+    if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1)
+        atomicAdd(&census[slot], (unsigned long long)__popcll(act));
+}
+
+template <bool HAS_OFFS, bool TRACK_SURF, bool CULL, bool COUNT = false>
 __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                           const double *__restrict__ offs, double x, double y,
                                           double z, double ux, double uy, double uz, double &best,
-                                          int &hit, int &bsid) {
+                                          int &hit, int &bsid,
+                                          unsigned long long *census = nullptr) {
     int sid;
+    if (COUNT) census_add(census, 7);
     best = any_dist_in(v.mother, x, y, z, ux, uy, uz, sid);
     hit = -1;
     bsid = sid;
+    const double dd = CULL ? fma(uz, uz, fma(uy, uy, ux * ux)) : 0.0;
     const int nd = v.nd;
     for (int k = 0; k < nd; ++k) {
         const DaughterRec &D = dau[k];
@@ -439,6 +494,17 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
             wy -= offs[3 * k + 1];
             wz -= offs[3 * k + 2];
         }
+        if (CULL) {
+            if (COUNT) census_add(census, 6);
+            const double b = fma(wz, uz, fma(wy, uy, wx * ux));
+            const double cc = fma(wz, wz, fma(wy, wy, wx * wx)) - D.cull_r2;
+            const double disc = fma(-dd, cc, b * b);
+            const double m = fma(-best, dd, -b);
+            const bool reach =
+                cc <= 0.0 || (b < 0.0 && disc >= 0.0 && !(m >= 0.0 && m * m >= disc));
+            if (__ballot(reach) == 0) continue;
+        }
+        if (COUNT) census_add(census, 2 * D.shape.kind + D.shape.hole);
         const double *R = D.rot;
         // local = R^T w
         const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));

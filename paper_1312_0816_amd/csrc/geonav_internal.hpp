@@ -15,7 +15,7 @@ hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, 
                               hipStream_t st);
 
 hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const TracksDev &t,
-                             const double *offs, double *step, int32_t *hit, double *hitpt,
+                             const double *offs, double *step, int32_t *hit, double *hitpt, bool cull,
                              hipStream_t st);
 
 // Arguments of the persistent batched navigator, in kernel-parameter order
@@ -30,6 +30,7 @@ struct PersistentArgs {
     TracksDev t;
     double *step;
     int32_t *hit;
+    unsigned long long *census;  // NULL except in the census launch
 };
 
 // A basket as the device sees it (sorted by decreasing per-track cost).
@@ -52,13 +53,18 @@ struct BuildTilesArgs {
 constexpr int kBuildTilesBlocks = 256;
 
 // Kernel function handles for graph kernel nodes.
-const void *persistent_kernel(int tracks_per_lane);
+const void *persistent_kernel(int tracks_per_lane, bool cull);
 const void *build_tiles_kernel();
 int persistent_grid(int waves_per_simd, int num_cus);
+
+// Direct (non-graph) launch of the tile expansion and the counting variant
+// of the persistent kernel.
+hipError_t launch_census(int tracks_per_lane, bool cull, int grid, const BuildTilesArgs &ba,
+                         const PersistentArgs &pa, unsigned long long *census, hipStream_t st);
 
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
-                           double *g_off, hipStream_t st);
+                           double *g_off, bool cull, hipStream_t st);
 
 }  // namespace gn

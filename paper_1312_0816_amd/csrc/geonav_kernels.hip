@@ -74,7 +74,7 @@ hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, 
 }
 
 // ---------------------------------------------------------- basket navigator
-template <bool HAS_OFFS, bool HITPT>
+template <bool HAS_OFFS, bool HITPT, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
                                                        TracksDev t, const double *__restrict__ offs,
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
     double best;
     int h, sid;
-    nav_track<HAS_OFFS, false>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
+    nav_track<HAS_OFFS, false, CULL>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
     step[i] = best;
     hit[i] = h;
     if (HITPT) {
@@ -98,18 +98,27 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     }
 }
 
+template <bool CULL>
+static void launch_basket_variant(dim3 grid, const VolumeRec *vol, const DaughterRec *dau,
+                                  const TracksDev &t, const double *offs, double *step, int32_t *hit,
+                                  double *hitpt, hipStream_t st) {
+    const dim3 block(kBlock);
+    if (offs) {
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+    } else {
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+    }
+}
+
 hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const TracksDev &t,
-                             const double *offs, double *step, int32_t *hit, double *hitpt,
+                             const double *offs, double *step, int32_t *hit, double *hitpt, bool cull,
                              hipStream_t st) {
     if (t.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
-    if (offs) {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<true, false>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
-    } else {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<false, false>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
-    }
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
+    if (cull) launch_basket_variant<true>(grid, vol, dau, t, offs, step, hit, hitpt, st);
+    else launch_basket_variant<false>(grid, vol, dau, t, offs, step, hit, hitpt, st);
     return hipGetLastError();
 }
 
@@ -119,13 +128,14 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
 // wavefront exits once the cursor passes ntiles. A tile holds at most
 // 64 * U tracks of one volume, so the volume and its daughters are uniform
 // over the wavefront.
-template <int U>
+template <int U, bool CULL, bool COUNT = false>
 __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__restrict__ vols,
                                                            const DaughterRec *__restrict__ dau_all,
                                                            const Tile *__restrict__ tiles,
                                                            int32_t ntiles, unsigned int *cursor,
                                                            TracksDev t, double *__restrict__ step,
-                                                           int32_t *__restrict__ hit) {
+                                                           int32_t *__restrict__ hit,
+                                                           unsigned long long *census) {
     const int lane = threadIdx.x & 63;
     for (;;) {
         unsigned int id = 0;
@@ -144,7 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
                 const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
                 double best;
                 int h, sid;
-                nav_track<false, false>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h, sid);
+                nav_track<false, false, CULL, COUNT>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h,
+                                                     sid, census);
                 step[i] = best;
                 hit[i] = h;
             }
@@ -173,15 +184,43 @@ __global__ __launch_bounds__(kBlock) void k_build_tiles(BuildTilesArgs a) {
     }
 }
 
-const void *persistent_kernel(int tracks_per_lane) {
+const void *persistent_kernel(int tracks_per_lane, bool cull) {
+    if (cull) {
+        switch (tracks_per_lane) {
+            case 1: return reinterpret_cast<const void *>(&k_nav_persistent<1, true>);
+            case 2: return reinterpret_cast<const void *>(&k_nav_persistent<2, true>);
+            default: return reinterpret_cast<const void *>(&k_nav_persistent<4, true>);
+        }
+    }
     switch (tracks_per_lane) {
-        case 1: return reinterpret_cast<const void *>(&k_nav_persistent<1>);
-        case 2: return reinterpret_cast<const void *>(&k_nav_persistent<2>);
-        default: return reinterpret_cast<const void *>(&k_nav_persistent<4>);
+        case 1: return reinterpret_cast<const void *>(&k_nav_persistent<1, false>);
+        case 2: return reinterpret_cast<const void *>(&k_nav_persistent<2, false>);
+        default: return reinterpret_cast<const void *>(&k_nav_persistent<4, false>);
     }
 }
 
 const void *build_tiles_kernel() { return reinterpret_cast<const void *>(&k_build_tiles); }
+
+hipError_t launch_census(int tracks_per_lane, bool cull, int grid, const BuildTilesArgs &ba,
+                         const PersistentArgs &pa, unsigned long long *census, hipStream_t st) {
+    hipLaunchKernelGGL(k_build_tiles, dim3(kBuildTilesBlocks), dim3(kBlock), 0, st, ba);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define GN_CENSUS(U_, C_)                                                                              \
+    hipLaunchKernelGGL((k_nav_persistent<U_, C_, true>), dim3(grid), dim3(kBlock), 0, st, pa.vols,    \
+                       pa.dau, pa.tiles, pa.ntiles, pa.cursor, pa.t, pa.step, pa.hit, census)
+    if (cull) {
+        if (tracks_per_lane == 1) GN_CENSUS(1, true);
+        else if (tracks_per_lane == 2) GN_CENSUS(2, true);
+        else GN_CENSUS(4, true);
+    } else {
+        if (tracks_per_lane == 1) GN_CENSUS(1, false);
+        else if (tracks_per_lane == 2) GN_CENSUS(2, false);
+        else GN_CENSUS(4, false);
+    }
+#undef GN_CENSUS
+    return hipGetLastError();
+}
 
 int persistent_grid(int waves_per_simd, int num_cus) {
     // 4 SIMDs per CU, kBlock / 64 = 4 wavefronts per workgroup
@@ -197,7 +236,7 @@ int persistent_grid(int waves_per_simd, int num_cus) {
 //   g_p = ghit + c ds/dp,  g_d = s ghit + c ds/dd,  g_delta_hit += c ds/d delta.
 // The offset gradient of the workgroup's tracks is summed per daughter in a
 // fixed lane order into the workgroup's row of `partial`.
-template <bool HAS_OFFS>
+template <bool HAS_OFFS, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_nav_backward(
     const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau, TracksDev t,
     const double *__restrict__ offs, const double *__restrict__ gstep,
@@ -221,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int sid;
-            nav_track<HAS_OFFS, true>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
+            nav_track<HAS_OFFS, true, CULL>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
             const bool finite = best < kBig;
             const double s = finite ? best : 0.0;
             const double hx = fma(s, ux, x), hy = fma(s, uy, y), hz = fma(s, uz, z);
@@ -308,20 +347,29 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__rest
     if (threadIdx.x == 0) out[j] = s[0];
 }
 
+template <bool CULL>
+static void launch_backward_variant(int nblocks, const VolumeRec *vol, const DaughterRec *dau,
+                                    const TracksDev &t, const double *offs, const double *gstep,
+                                    const double *ghit, double *g_o, double *g_d, double *part,
+                                    hipStream_t st) {
+    if (offs)
+        hipLaunchKernelGGL((k_nav_backward<true, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
+                           offs, gstep, ghit, g_o, g_d, part);
+    else
+        hipLaunchKernelGGL((k_nav_backward<false, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
+                           offs, gstep, ghit, g_o, g_d, part);
+}
+
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
-                           double *g_off, hipStream_t st) {
+                           double *g_off, bool cull, hipStream_t st) {
     const int64_t need = (t.n + kBlock - 1) / kBlock;
     const int nblocks = (int)(need < kBackwardMaxBlocks ? (need > 0 ? need : 1) : kBackwardMaxBlocks);
     double *part = (g_off && nd > 0) ? partial : nullptr;
     if (t.n > 0 || part) {
-        if (offs)
-            hipLaunchKernelGGL((k_nav_backward<true>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
-                               offs, gstep, ghit, g_o, g_d, part);
-        else
-            hipLaunchKernelGGL((k_nav_backward<false>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
-                               offs, gstep, ghit, g_o, g_d, part);
+        if (cull) launch_backward_variant<true>(nblocks, vol, dau, t, offs, gstep, ghit, g_o, g_d, part, st);
+        else launch_backward_variant<false>(nblocks, vol, dau, t, offs, gstep, ghit, g_o, g_d, part, st);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -53,7 +53,8 @@ class GeoBasket(C.Structure):
 
 EXPORTS = ("geo_geometry_create", "geo_geometry_destroy", "geo_shape_query",
            "geo_navigate_basket", "geo_navigate_batched", "geo_navigate_backward",
-           "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_strerror")
+           "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_set_culling",
+           "geo_get_culling", "geo_navigate_batched_census", "geo_strerror")
 
 _lib = None
 
@@ -76,6 +77,10 @@ def load_library(path: str = LIB_PATH):
     lib.geo_autotune.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P]
     lib.geo_get_launch_config.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     lib.geo_set_launch_config.argtypes = [P, I32, I32]
+    lib.geo_set_culling.argtypes = [P, I32]
+    lib.geo_navigate_batched_census.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P, P,
+                                                C.POINTER(C.c_uint64), P]
+    lib.geo_get_culling.argtypes = [P, C.POINTER(I32)]
     lib.geo_strerror.argtypes = [C.c_int]
     lib.geo_strerror.restype = C.c_char_p
     for name in EXPORTS:
@@ -226,6 +231,16 @@ class Geometry:
     def set_launch_config(self, tracks_per_lane: int, waves_per_simd: int):
         _check(self._lib.geo_set_launch_config(self._h, int(tracks_per_lane), int(waves_per_simd)))
 
+    @property
+    def culling(self) -> bool:
+        v = C.c_int32()
+        _check(self._lib.geo_get_culling(self._h, C.byref(v)))
+        return bool(v.value)
+
+    @culling.setter
+    def culling(self, enable: bool):
+        _check(self._lib.geo_set_culling(self._h, 1 if enable else 0))
+
 
 def geo_geometry_create(volumes) -> Geometry:
     return Geometry(volumes)
@@ -278,6 +293,22 @@ def geo_navigate_batched(g: Geometry, basket_volume, basket_offset, basket_n, tr
     arr, nb = _baskets(basket_volume, basket_offset, basket_n)
     _check(g._lib.geo_navigate_batched(g.handle, arr, nb, t, _ptr(step), _ptr(hit), _stream(stream)))
     return step, hit
+
+
+def geo_navigate_batched_census(g: Geometry, basket_volume, basket_offset, basket_n,
+                                tracks: torch.Tensor, stream=None):
+    """Instrumented batched run. Returns (step, hit, counts[8]) with counts as
+    documented in geonav.h (lane-evaluations per kind/hole slot, culling
+    tests, tracks)."""
+    t = tracks_struct(tracks)
+    n = t.n
+    step = torch.empty(n, dtype=torch.float64, device=tracks.device)
+    hit = torch.empty(n, dtype=torch.int32, device=tracks.device)
+    arr, nb = _baskets(basket_volume, basket_offset, basket_n)
+    counts = (C.c_uint64 * 8)()
+    _check(g._lib.geo_navigate_batched_census(g.handle, arr, nb, t, _ptr(step), _ptr(hit), counts,
+                                              _stream(stream)))
+    return step, hit, [int(c) for c in counts]
 
 
 def geo_autotune(g: Geometry, basket_volume, basket_offset, basket_n, tracks: torch.Tensor, stream=None):
