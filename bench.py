@@ -6,7 +6,8 @@ each a box mother (200)^3 with 1..64 daughters (box/tube/cone) on a 4x4x4
 grid (about 4.26M tracks, FP64). The step runs the whole navigator path:
 basket load, geometry access, master-to-local transforms, every daughter's
 DistFromOutside, the mother's DistFromInside, min/argmin and the outputs,
-scheduled as one persistent launch from a cached HIP graph.
+scheduled as one launch from a cached HIP graph (the persistent kernel, or
+one wavefront per tile, whichever the autotuner finds faster).
 
 Printed: one JSON line with tracks/s, the plain per-basket comparison (512
 separate geo_navigate_basket launches doing the same work), the roofline of
@@ -284,13 +285,14 @@ def main():
         "config": {
             "workload": f"batched navigation: {len(bn)} baskets (32-65536 tracks, log-uniform) over "
                         f"{len(wl.volumes)} volumes (box mother (200)^3, 1-64 box/tube/cone daughters), "
-                        f"{n} tracks, FP64, one persistent graph launch",
+                        f"{n} tracks, FP64, one graph launch",
             "baskets": int(len(bn)), "volumes": int(len(wl.volumes)), "tracks": n,
             "launch": {"tracks_per_lane": U, "waves_per_simd": Wv, "autotuned": not (args.no_autotune or args.launch)},
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_nav_persistent (+ k_build_tiles node), culling on",
+            "kernel": ("k_nav_persistent" if Wv > 0 else "k_nav_tiles") + f"<{U}, cull>" +
+                      " (+ k_build_tiles graph node)",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -172,17 +172,21 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
 int geo_navigate_batched_census(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
                                 double *step, int32_t *hit, uint64_t counts[8], hipStream_t stream);
 
-/* Time the candidate launch shapes of the batched kernel (tile size, waves
- * per SIMD) on these baskets and keep the fastest in the handle; also records
+/* Time the candidate launch shapes of the batched kernel (tracks per lane
+ * 1/2/4/8 x waves per SIMD 0/2/3/4/6/8) on these baskets and keep the fastest in the handle; also records
  * it in the JSON cache named by the GEONAV_AUTOTUNE_CACHE environment
  * variable, if set. Writes step/hit scratch internally; synchronises the
  * stream. */
 int geo_autotune(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
                  hipStream_t stream);
 
-/* The batched launch shape currently used by the handle. */
+/* Launch shape of the batched kernel. tracks_per_lane (1, 2, 4 or 8) sets the
+ * tile size (64 * tracks_per_lane tracks of one volume per wavefront task);
+ * waves_per_simd 1..8 selects the persistent kernel with that many
+ * wavefronts per SIMD pulling tiles from per-XCD queues, 0 selects one
+ * wavefront per tile scheduled by the hardware. Default 4 and 4; the
+ * autotuner may change them. Results do not depend on the launch shape. */
 int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd);
-/* Force a launch shape (tracks_per_lane in {1, 2, 4}, waves_per_simd 1..8). */
 int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd);
 
 /* Wavefront culling in the navigators (basket, batched, backward): a

@@ -184,13 +184,13 @@ struct geo_geometry {
     size_t d_bcap = 0;
     Tile *d_tiles = nullptr;
     int64_t tiles_cap = 0;
-    unsigned int *d_cursor = nullptr;
+    unsigned int *d_cursors = nullptr;  // kQueues cursors, kQueueStride apart
     hipEvent_t staged = nullptr;     // the last upload from h_baskets has completed
     bool staged_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node_build = nullptr, node_nav = nullptr;
-    int graph_U = 0, graph_grid = 0, graph_cull = -1;
+    int graph_U = 0, graph_grid = 0, graph_cull = -1, graph_mode = -1;
     std::vector<BasketRec> sorted;   // reused host scratch
 };
 
@@ -203,7 +203,7 @@ void destroy_graph(geo_geometry *g) {
     g->graph = nullptr;
     g->node_build = g->node_nav = nullptr;
     g->graph_U = g->graph_grid = 0;
-    g->graph_cull = -1;
+    g->graph_cull = g->graph_mode = -1;
 }
 
 int check_device(const geo_geometry *g) {
@@ -296,8 +296,8 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
     if (max_nd > 0 &&
         hipMalloc(&g->d_partial, sizeof(double) * 3 * (size_t)max_nd * kBackwardMaxBlocks) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of adjoint partials failed"));
-    if (hipMalloc(&g->d_cursor, sizeof(unsigned int)) != hipSuccess)
-        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of the cursor failed"));
+    if (hipMalloc(&g->d_cursors, sizeof(unsigned int) * kQueues * kQueueStride) != hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of the queue cursors failed"));
     e = hipMemcpy(g->d_vols, vols.data(), sizeof(VolumeRec) * nvol, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy volumes"));
     if (!dau.empty()) {
@@ -323,7 +323,7 @@ int geo_geometry_destroy(geo_geometry *g) {
     (void)hipFree(g->d_partial);
     (void)hipFree(g->d_tiles);
     (void)hipFree(g->d_bstage);
-    (void)hipFree(g->d_cursor);
+    (void)hipFree(g->d_cursors);
     if (g->h_baskets) (void)hipHostFree(g->h_baskets);
     if (dev >= 0 && dev != g->device) (void)hipSetDevice(dev);
     delete g;
@@ -470,50 +470,62 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     ba.nb = ns;
     ba.tile_n = tile_n;
     ba.tiles = g->d_tiles;
-    ba.cursor = g->d_cursor;
+    ba.cursors = g->d_cursors;
     PersistentArgs pa;
     pa.vols = g->d_vols;
     pa.dau = g->d_dau;
     pa.tiles = g->d_tiles;
     pa.ntiles = (int32_t)ntiles;
-    pa.cursor = g->d_cursor;
+    pa.cursors = g->d_cursors;
     pa.t = to_dev(all);
     pa.step = step;
     pa.hit = hit;
+    pa.census = census;
 
+    const bool persistent = g->waves_per_simd > 0;
+    const int grid = batched_grid(g->waves_per_simd, g->num_cus, ntiles);
     void *bargs[] = {&ba};
-    pa.census = nullptr;
-    const int grid = persistent_grid(g->waves_per_simd, g->num_cus);
-    if (census) {
+    void *pargs[] = {&pa.vols, &pa.dau, &pa.tiles, &pa.ntiles, &pa.cursors, &pa.t, &pa.step, &pa.hit,
+                     &pa.census};
+    if (census) {  // instrumented run: direct launches, no graph
         GN_HIP(hipMemsetAsync(census, 0, 8 * sizeof(unsigned long long), stream));
-        GN_HIP(launch_census(U, g->cull, grid, ba, pa, census, stream));
+        GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));
+        GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true), dim3(grid), dim3(kBlock), pargs, 0,
+                               stream));
         return GEO_OK;
     }
-    void *pargs[] = {&pa.vols, &pa.dau, &pa.tiles, &pa.ntiles, &pa.cursor, &pa.t, &pa.step, &pa.hit,
-                     &pa.census};
     hipKernelNodeParams kb = {};
     kb.func = const_cast<void *>(build_tiles_kernel());
     kb.gridDim = dim3(kBuildTilesBlocks);
     kb.blockDim = dim3(kBlock);
     kb.kernelParams = bargs;
     hipKernelNodeParams kn = {};
-    kn.func = const_cast<void *>(persistent_kernel(U, g->cull));
+    kn.func = const_cast<void *>(batched_kernel(U, g->cull, persistent, false));
     kn.gridDim = dim3(grid);
     kn.blockDim = dim3(kBlock);
     kn.kernelParams = pargs;
-    if (!g->exec || g->graph_U != U || g->graph_grid != grid || g->graph_cull != (int)g->cull) {
+    const int mode = persistent ? 1 : 0;
+    bool rebuild = !g->exec || g->graph_U != U || g->graph_cull != (int)g->cull || g->graph_mode != mode;
+    if (!rebuild) {
+        // same kernels: update arguments (and the grid, which the hardware-
+        // scheduled form sizes by tile count); rebuild if the update is refused
+        if (hipGraphExecKernelNodeSetParams(g->exec, g->node_build, &kb) != hipSuccess ||
+            hipGraphExecKernelNodeSetParams(g->exec, g->node_nav, &kn) != hipSuccess) {
+            (void)hipGetLastError();
+            rebuild = true;
+        }
+    }
+    if (rebuild) {
         destroy_graph(g);
         GN_HIP(hipGraphCreate(&g->graph, 0));
         GN_HIP(hipGraphAddKernelNode(&g->node_build, g->graph, nullptr, 0, &kb));
         GN_HIP(hipGraphAddKernelNode(&g->node_nav, g->graph, &g->node_build, 1, &kn));
         GN_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
         g->graph_U = U;
-        g->graph_grid = grid;
         g->graph_cull = (int)g->cull;
-    } else {
-        GN_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->node_build, &kb));
-        GN_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->node_nav, &kn));
+        g->graph_mode = mode;
     }
+    g->graph_grid = grid;
     GN_HIP(hipGraphLaunch(g->exec, stream));
     return GEO_OK;
 }
@@ -584,9 +596,10 @@ int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32
 
 int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd) {
     if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
-    if (!(tracks_per_lane == 1 || tracks_per_lane == 2 || tracks_per_lane == 4))
-        return fail(GEO_ERR_INVALID_ARG, "tracks_per_lane must be 1, 2 or 4");
-    if (waves_per_simd < 1 || waves_per_simd > 8) return fail(GEO_ERR_INVALID_ARG, "waves_per_simd must be 1..8");
+    if (!(tracks_per_lane == 1 || tracks_per_lane == 2 || tracks_per_lane == 4 || tracks_per_lane == 8))
+        return fail(GEO_ERR_INVALID_ARG, "tracks_per_lane must be 1, 2, 4 or 8");
+    if (waves_per_simd < 0 || waves_per_simd > 8)
+        return fail(GEO_ERR_INVALID_ARG, "waves_per_simd must be 0 (one wavefront per tile) or 1..8");
     g->tracks_per_lane = tracks_per_lane;
     g->waves_per_simd = waves_per_simd;
     return GEO_OK;
@@ -684,8 +697,8 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    const int Us[] = {1, 2, 4};
-    const int Ws[] = {1, 2, 4, 8};
+    const int Us[] = {1, 2, 4, 8};
+    const int Ws[] = {0, 2, 3, 4, 6, 8};
     int bestU = g->tracks_per_lane, bestW = g->waves_per_simd;
     float best = 1e30f;
     rc = GEO_OK;

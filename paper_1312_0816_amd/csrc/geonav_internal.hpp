@@ -18,15 +18,20 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
                              const double *offs, double *step, int32_t *hit, double *hitpt, bool cull,
                              hipStream_t st);
 
-// Arguments of the persistent batched navigator, in kernel-parameter order
-// (graph kernel nodes pass a pointer to each). `cursor` is reset by
-// k_build_tiles, which runs just before it in the same graph.
+// Tile queues of the persistent batched kernel: one per XCD, cursors 256 B
+// apart.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 64;  // in unsigned ints
+
+// Arguments of the batched kernels, in kernel-parameter order (graph kernel
+// nodes pass a pointer to each). The queue cursors are reset by
+// k_build_tiles, which runs just before in the same graph.
 struct PersistentArgs {
     const VolumeRec *vols;
     const DaughterRec *dau;
     const Tile *tiles;
     int32_t ntiles;
-    unsigned int *cursor;
+    unsigned int *cursors;       // kQueues * kQueueStride
     TracksDev t;
     double *step;
     int32_t *hit;
@@ -47,20 +52,19 @@ struct BuildTilesArgs {
     int32_t nb;
     int32_t tile_n;             // tracks per tile (64 * tracks per lane)
     Tile *tiles;
-    unsigned int *cursor;
+    unsigned int *cursors;
 };
 
 constexpr int kBuildTilesBlocks = 256;
 
-// Kernel function handles for graph kernel nodes.
-const void *persistent_kernel(int tracks_per_lane, bool cull);
+// Kernel function handles (for graph kernel nodes and hipLaunchKernel).
+// persistent: k_nav_persistent, else k_nav_tiles (one wavefront per tile);
+// count: the variant that fills the work census.
+const void *batched_kernel(int tracks_per_lane, bool cull, bool persistent, bool count);
 const void *build_tiles_kernel();
-int persistent_grid(int waves_per_simd, int num_cus);
-
-// Direct (non-graph) launch of the tile expansion and the counting variant
-// of the persistent kernel.
-hipError_t launch_census(int tracks_per_lane, bool cull, int grid, const BuildTilesArgs &ba,
-                         const PersistentArgs &pa, unsigned long long *census, hipStream_t st);
+// Workgroups of a batched launch: num_cus * waves_per_simd (persistent) or
+// one wavefront per tile (waves_per_simd == 0).
+int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles);
 
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,

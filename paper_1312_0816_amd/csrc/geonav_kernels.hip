@@ -122,52 +122,87 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
     return hipGetLastError();
 }
 
-// ------------------------------------------------------ batched, persistent
-// Each wavefront repeatedly takes the next tile index from `cursor` (tiles come
-// in order of decreasing per-track cost) until the list is exhausted; every
-// wavefront exits once the cursor passes ntiles. A tile holds at most
-// 64 * U tracks of one volume, so the volume and its daughters are uniform
-// over the wavefront.
-template <int U, bool CULL, bool COUNT = false>
-__global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__restrict__ vols,
-                                                           const DaughterRec *__restrict__ dau_all,
-                                                           const Tile *__restrict__ tiles,
-                                                           int32_t ntiles, unsigned int *cursor,
-                                                           TracksDev t, double *__restrict__ step,
-                                                           int32_t *__restrict__ hit,
-                                                           unsigned long long *census) {
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        unsigned int id = 0;
-        if (lane == 0) id = atomicAdd(cursor, 1u);
-        id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
-        if (id >= (unsigned int)ntiles) break;
-        const Tile tl = tiles[id];
-        const VolumeRec &v = vols[tl.volume];
-        const DaughterRec *dau = dau_all + v.first;
+// ------------------------------------------------------------------ batched
+// A tile holds at most 64 * U tracks of one volume: U rounds of one track
+// per lane, so the volume and its daughters are uniform over the wavefront.
+// Tiles come in order of decreasing per-track cost (the host sorts the
+// baskets by daughter count; k_build_tiles expands them in that order).
+template <int U, bool CULL, bool COUNT>
+__device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__restrict__ vols,
+                                         const DaughterRec *__restrict__ dau_all, const TracksDev &t,
+                                         double *__restrict__ step, int32_t *__restrict__ hit,
+                                         unsigned long long *census, int lane) {
+    const VolumeRec &v = vols[tl.volume];
+    const DaughterRec *dau = dau_all + v.first;
 #pragma unroll 1
-        for (int u = 0; u < U; ++u) {
-            const int j = u * 64 + lane;
-            if (j < tl.count) {
-                const int64_t i = tl.offset + j;
-                const double x = t.x[i], y = t.y[i], z = t.z[i];
-                const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
-                double best;
-                int h, sid;
-                nav_track<false, false, CULL, COUNT>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h,
-                                                     sid, census);
-                step[i] = best;
-                hit[i] = h;
-            }
+    for (int u = 0; u < U; ++u) {
+        const int j = u * 64 + lane;
+        if (j < tl.count) {
+            const int64_t i = tl.offset + j;
+            const double x = t.x[i], y = t.y[i], z = t.z[i];
+            const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+            double best;
+            int h, sid;
+            nav_track<false, false, CULL, COUNT>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h, sid,
+                                                 census);
+            step[i] = best;
+            hit[i] = h;
         }
     }
 }
 
+// Persistent form: a grid sized to the machine; tiles are dealt round-robin
+// into kQueues queues (tile i to queue i mod kQueues, in order), each with its
+// own cursor on its own 256-byte line, so the atomics that hand out tiles
+// spread over kQueues addresses instead of contending on one. A wavefront
+// drains the queue of its workgroup's XCD slot (blockIdx mod kQueues) first,
+// then the others in turn; it exits once every queue's cursor has passed the
+// queue's length, so every wavefront terminates.
+template <int U, bool CULL, bool COUNT = false>
+__global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__restrict__ vols,
+                                                           const DaughterRec *__restrict__ dau_all,
+                                                           const Tile *__restrict__ tiles,
+                                                           int32_t ntiles, unsigned int *cursors,
+                                                           TracksDev t, double *__restrict__ step,
+                                                           int32_t *__restrict__ hit,
+                                                           unsigned long long *census) {
+    const int lane = threadIdx.x & 63;
+    const int home = (int)(blockIdx.x % kQueues);
+    for (int qq = 0; qq < kQueues; ++qq) {
+        const int q = (home + qq) % kQueues;
+        const unsigned int count = ntiles > q ? (unsigned int)((ntiles - q + kQueues - 1) / kQueues) : 0u;
+        for (;;) {
+            unsigned int id = 0;
+            if (lane == 0) id = atomicAdd(&cursors[q * kQueueStride], 1u);
+            id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
+            if (id >= count) break;
+            run_tile<U, CULL, COUNT>(tiles[q + kQueues * (int64_t)id], vols, dau_all, t, step, hit,
+                                     census, lane);
+        }
+    }
+}
+
+// Hardware-scheduled form: one wavefront per tile, workgroups dispatched in
+// tile order (same parameters as the persistent form; `cursors` unused).
+template <int U, bool CULL, bool COUNT = false>
+__global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restrict__ vols,
+                                                      const DaughterRec *__restrict__ dau_all,
+                                                      const Tile *__restrict__ tiles, int32_t ntiles,
+                                                      unsigned int *cursors, TracksDev t,
+                                                      double *__restrict__ step,
+                                                      int32_t *__restrict__ hit,
+                                                      unsigned long long *census) {
+    (void)cursors;
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    if (w >= ntiles) return;
+    run_tile<U, CULL, COUNT>(tiles[w], vols, dau_all, t, step, hit, census, (int)(threadIdx.x & 63));
+}
+
 // Expands the (cost-sorted) basket list into tiles of at most tile_n tracks:
 // basket b owns tiles [tile_start[b], tile_start[b + 1]). Also resets the
-// persistent kernel's cursor.
+// persistent kernel's queue cursors.
 __global__ __launch_bounds__(kBlock) void k_build_tiles(BuildTilesArgs a) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.cursor = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kQueues) a.cursors[threadIdx.x * kQueueStride] = 0u;
     for (int b = blockIdx.x; b < a.nb; b += gridDim.x) {
         const BasketRec bk = a.baskets[b];
         const int64_t first = a.tile_start[b];
@@ -184,47 +219,37 @@ __global__ __launch_bounds__(kBlock) void k_build_tiles(BuildTilesArgs a) {
     }
 }
 
-const void *persistent_kernel(int tracks_per_lane, bool cull) {
-    if (cull) {
-        switch (tracks_per_lane) {
-            case 1: return reinterpret_cast<const void *>(&k_nav_persistent<1, true>);
-            case 2: return reinterpret_cast<const void *>(&k_nav_persistent<2, true>);
-            default: return reinterpret_cast<const void *>(&k_nav_persistent<4, true>);
-        }
+template <int U, bool CULL, bool COUNT>
+static const void *pick_mode(bool persistent) {
+    return persistent ? reinterpret_cast<const void *>(&k_nav_persistent<U, CULL, COUNT>)
+                      : reinterpret_cast<const void *>(&k_nav_tiles<U, CULL, COUNT>);
+}
+
+template <bool CULL, bool COUNT>
+static const void *pick_u(int U, bool persistent) {
+    switch (U) {
+        case 1: return pick_mode<1, CULL, COUNT>(persistent);
+        case 2: return pick_mode<2, CULL, COUNT>(persistent);
+        case 4: return pick_mode<4, CULL, COUNT>(persistent);
+        default: return pick_mode<8, CULL, COUNT>(persistent);
     }
-    switch (tracks_per_lane) {
-        case 1: return reinterpret_cast<const void *>(&k_nav_persistent<1, false>);
-        case 2: return reinterpret_cast<const void *>(&k_nav_persistent<2, false>);
-        default: return reinterpret_cast<const void *>(&k_nav_persistent<4, false>);
-    }
+}
+
+const void *batched_kernel(int tracks_per_lane, bool cull, bool persistent, bool count) {
+    if (cull) return count ? pick_u<true, true>(tracks_per_lane, persistent)
+                           : pick_u<true, false>(tracks_per_lane, persistent);
+    return count ? pick_u<false, true>(tracks_per_lane, persistent)
+                 : pick_u<false, false>(tracks_per_lane, persistent);
 }
 
 const void *build_tiles_kernel() { return reinterpret_cast<const void *>(&k_build_tiles); }
 
-hipError_t launch_census(int tracks_per_lane, bool cull, int grid, const BuildTilesArgs &ba,
-                         const PersistentArgs &pa, unsigned long long *census, hipStream_t st) {
-    hipLaunchKernelGGL(k_build_tiles, dim3(kBuildTilesBlocks), dim3(kBlock), 0, st, ba);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-#define GN_CENSUS(U_, C_)                                                                              \
-    hipLaunchKernelGGL((k_nav_persistent<U_, C_, true>), dim3(grid), dim3(kBlock), 0, st, pa.vols,    \
-                       pa.dau, pa.tiles, pa.ntiles, pa.cursor, pa.t, pa.step, pa.hit, census)
-    if (cull) {
-        if (tracks_per_lane == 1) GN_CENSUS(1, true);
-        else if (tracks_per_lane == 2) GN_CENSUS(2, true);
-        else GN_CENSUS(4, true);
-    } else {
-        if (tracks_per_lane == 1) GN_CENSUS(1, false);
-        else if (tracks_per_lane == 2) GN_CENSUS(2, false);
-        else GN_CENSUS(4, false);
-    }
-#undef GN_CENSUS
-    return hipGetLastError();
-}
-
-int persistent_grid(int waves_per_simd, int num_cus) {
-    // 4 SIMDs per CU, kBlock / 64 = 4 wavefronts per workgroup
-    return num_cus * waves_per_simd;
+int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles) {
+    // persistent: 4 SIMDs per CU and kBlock / 64 = 4 wavefronts per workgroup,
+    // so num_cus * waves_per_simd workgroups give waves_per_simd per SIMD;
+    // hardware-scheduled: one wavefront per tile
+    if (waves_per_simd > 0) return num_cus * waves_per_simd;
+    return (int)((ntiles + kBlock / 64 - 1) / (kBlock / 64));
 }
 
 // ------------------------------------------------------------------ adjoint

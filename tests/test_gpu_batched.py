@@ -56,8 +56,8 @@ def test_batched_bit_identical_to_per_basket(gv, small):
     g = gv.Geometry(small.volumes)
     t = torch.from_numpy(small.tracks).cuda()
     s0, h0 = per_basket(gv, g, small, t)
-    for U in (1, 2, 4):
-        for Wv in (1, 2, 4, 8):
+    for U in (1, 2, 4, 8):
+        for Wv in (0, 2, 4, 8):
             g.set_launch_config(U, Wv)
             s1, h1 = batched(gv, g, small, t)
             assert np.array_equal(s1.view(np.int64), s0.view(np.int64)), (U, Wv)
@@ -148,7 +148,7 @@ def test_autotune_and_cache(gv, small, tmp_path, monkeypatch):
     g = gv.Geometry(small.volumes)
     t = torch.from_numpy(small.tracks).cuda()
     u, w = gv.geo_autotune(g, small.basket_volume, small.basket_offset, small.basket_n, t)
-    assert u in (1, 2, 4) and 1 <= w <= 8
+    assert u in (1, 2, 4, 8) and 0 <= w <= 8
     data = json.loads(path.read_text())
     assert len(data) == 1 and list(data.values())[0] == [u, w]
     g2 = gv.Geometry(small.volumes)
