@@ -62,6 +62,83 @@ def census_flops(counts, cull: bool) -> float:
     return float(f)
 
 
+def _time_ms(fn, reps=10, warm=3):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
+
+
+def measure_rows(gv, W, dev):
+    """The other rows of the hot path, each on its own workload (not part of
+    the step above): the shape queries on the shape-suite distribution tiled
+    to 2^26 tracks (3.2 GB, far above the 256 MB last-level cache), the plain
+    navigator on the toy detector (2^22 tracks, 32 daughters) and the adjoint
+    on the toy detector (2^20 tracks)."""
+    import torch
+    rows = {}
+    qbytes = {0: 25, 1: 32, 2: 56, 3: 56}
+    qname = {0: "contains", 1: "safety", 2: "dist_in", 3: "dist_out"}
+    shapes = {}
+    for kind in (0, 1, 2):
+        _, par, tr = W.shape_suite_c1(kind)
+        big = torch.from_numpy(tr).to(dev).repeat(1, 64).contiguous()   # 2^26 tracks
+        n = big.shape[1]
+        outs = {0: torch.empty(n, dtype=torch.uint8, device=dev),
+                1: torch.empty(n, dtype=torch.float64, device=dev)}
+        res = {}
+        for q in (0, 1, 2, 3):
+            out = outs[0] if q == 0 else outs[1]
+            ms = _time_ms(lambda: gv.geo_shape_query(kind, par, q, big, out))
+            gbs = qbytes[q] * n / (ms * 1e-3) / 1e9
+            res[qname[q]] = {"ms": ms, "tracks_per_s": n / (ms * 1e-3), "GBps": gbs,
+                             "hbm_frac": gbs / HBM_PEAK_GBS}
+        shapes[W.KIND_NAMES[kind]] = res
+        del big, outs
+        torch.cuda.empty_cache()
+    rows["shape_queries_2^26"] = shapes
+
+    vol, tr = W.toy_detector_c2()
+    g = gv.Geometry([vol])
+    t = torch.from_numpy(tr).to(dev)
+    n = t.shape[1]
+    step = torch.empty(n, dtype=torch.float64, device=dev)
+    hit = torch.empty(n, dtype=torch.int32, device=dev)
+    trs, sp, hp = gv.tracks_struct(t), gv._ptr(step), gv._ptr(hit)
+    lib, hs = g._lib, gv._stream()
+    ms = _time_ms(lambda: gv._check(lib.geo_navigate_basket(g.handle, 0, trs, None, sp, hp, None, hs)))
+    _, _, counts = gv.geo_navigate_batched_census(g, [0], [0], [n], t)
+    fl = census_flops(counts, True)
+    rows["navigator_toy_detector_2^22"] = {"ms": ms, "tracks_per_s": n / (ms * 1e-3),
+                                          "TFLOPs": fl / (ms * 1e-3) / 1e12,
+                                          "alu_frac": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                          "evaluated_fraction": sum(counts[:6]) / max(1, counts[6])}
+    g.close()
+    del t, step, hit
+
+    vol, tr, tgt = W.adjoint_c4()
+    g = gv.Geometry([vol])
+    n = tr.shape[1]
+    o = torch.from_numpy(np.ascontiguousarray(tr[:3])).to(dev)
+    d = torch.from_numpy(np.ascontiguousarray(tr[3:])).to(dev)
+    gh = torch.from_numpy(np.ascontiguousarray(tgt)).to(dev)
+    offs = torch.zeros((vol.nd, 3), dtype=torch.float64, device=dev)
+    ms = _time_ms(lambda: gv.geo_navigate_backward(g, 0, o, d, offs, None, gh))
+    rows["adjoint_toy_detector_2^20"] = {"ms": ms, "tracks_per_s": n / (ms * 1e-3),
+                                        "outputs": "g_o, g_d (3 x n) and g_off (32 x 3)"}
+    g.close()
+    return rows
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for f in ("geonav_device.hpp", "geonav_kernels.hip"):
@@ -73,7 +150,7 @@ def kernel_source_digest() -> str:
 def read_traffic(digest: str):
     """HBM bytes per launch of the persistent kernel from the committed
     rocprofv3 counter summary, if it was taken on this kernel source."""
-    path = os.path.join(ROOT, "profiles", "nav_persistent_batched512_traffic.md")
+    path = os.path.join(ROOT, "profiles", "navigator_batched512_traffic.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -138,9 +215,10 @@ def cpu_baseline(wl, gpu_step, gpu_hit, threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-rows", action="store_true", help="skip the per-row measurements")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="force the batched launch shape 'tracks_per_lane,waves_per_simd' (no autotune)")
@@ -223,18 +301,19 @@ def main():
     # work census of one launch (instrumented variant, outside the timed region)
     _, _, counts = gv.geo_navigate_batched_census(g, bv, bo, bn, t)
 
-    # timed: batched, with per-launch HIP events on the launch stream
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    # timed: batched. HIP events on the launch stream bracket the timed region
+    # (one pair, so that no per-step event packets sit between the launches);
+    # the average launch duration is their interval over the steps.
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
+    e0.record(stream)
+    for _ in range(args.steps):
         batched_step()
-        e1.record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ev_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = 1e3 * wall / args.steps
 
     # the same batched launch without wavefront culling (every daughter of
@@ -261,7 +340,7 @@ def main():
     plain_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
     value = n / (ms_per_step * 1e-3)
-    kernel_ms = float(np.mean(ev_ms))
+    kernel_ms = float(ev_ms)
     flops = census_flops(counts, True)
     flops_nocull = census_flops(counts_nocull, False)
     achieved = flops / (kernel_ms * 1e-3) / 1e12
@@ -323,6 +402,10 @@ def main():
     else:
         out["cpu_baseline"] = None
     g.close()
+    del t, step, hit, pstep, phit
+    torch.cuda.empty_cache()
+    if not args.no_rows:
+        out["rows"] = measure_rows(gv, W, dev)
     print(json.dumps(out), flush=True)
 
 

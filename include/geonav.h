@@ -135,9 +135,10 @@ int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, con
  * pool (entry offset + j for track j of a basket); pool entries not covered
  * by any basket are left untouched. Results are bit-identical to
  * geo_navigate_basket on each basket with offsets = NULL.
- * The handle keeps per-call state (tile list, graph): calls on one handle
- * must not run concurrently from several host threads; stream order is
- * respected. */
+ * The handle keeps per-call state (tile buffer, graph, a ring of pinned
+ * staging buffers): calls on one handle must come from one host thread at a
+ * time and be ordered on the device (the same stream, or streams the caller
+ * synchronises); a call may return before the device has run it. */
 int geo_navigate_batched(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
                          double *step, int32_t *hit, hipStream_t stream);
 

@@ -178,15 +178,22 @@ struct geo_geometry {
     int tracks_per_lane = 4;
     int waves_per_simd = 4;
     bool cull = true;               // wavefront bounding-sphere culling in the navigators
-    BasketRec *h_baskets = nullptr;  // pinned staging: nb baskets then nb + 1 tile starts
-    size_t h_cap = 0;                // bytes
-    void *d_bstage = nullptr;        // device copy of the staging block
-    size_t d_bcap = 0;
+    // Basket lists are staged in a ring of mapped pinned host buffers that the
+    // tile-expansion kernel reads directly (no copy node); a buffer is reused
+    // once the graph launch that read it has completed.
+    struct Stage {
+        void *host = nullptr;
+        void *dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    static constexpr int kStages = 4;
+    Stage stage[kStages];
+    int stage_next = 0;
     Tile *d_tiles = nullptr;
     int64_t tiles_cap = 0;
     unsigned int *d_cursors = nullptr;  // kQueues cursors, kQueueStride apart
-    hipEvent_t staged = nullptr;     // the last upload from h_baskets has completed
-    bool staged_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node_build = nullptr, node_nav = nullptr;
@@ -304,8 +311,10 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         e = hipMemcpy(g->d_dau, dau.data(), sizeof(DaughterRec) * dau.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy daughters"));
     }
-    e = hipEventCreateWithFlags(&g->staged, hipEventDisableTiming);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventCreate"));
+    for (auto &st : g->stage) {
+        e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventCreate"));
+    }
     *out = g;
     return GEO_OK;
 }
@@ -317,14 +326,15 @@ int geo_geometry_destroy(geo_geometry *g) {
     if (dev != g->device) (void)hipSetDevice(g->device);
     (void)hipDeviceSynchronize();
     destroy_graph(g);
-    if (g->staged) (void)hipEventDestroy(g->staged);
+    for (auto &st : g->stage) {
+        if (st.done) (void)hipEventDestroy(st.done);
+        if (st.host) (void)hipHostFree(st.host);
+    }
     (void)hipFree(g->d_vols);
     (void)hipFree(g->d_dau);
     (void)hipFree(g->d_partial);
     (void)hipFree(g->d_tiles);
-    (void)hipFree(g->d_bstage);
     (void)hipFree(g->d_cursors);
-    if (g->h_baskets) (void)hipHostFree(g->h_baskets);
     if (dev >= 0 && dev != g->device) (void)hipSetDevice(dev);
     delete g;
     return GEO_OK;
@@ -390,40 +400,34 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
 // ------------------------------------------------------------- batched
 namespace {
 
+// Make the next staging buffer free and large enough for nb baskets, and the
+// device tile buffer large enough for ntiles tiles.
 int ensure_capacity(geo_geometry *g, int nb, int64_t ntiles, hipStream_t stream) {
     const size_t need = sizeof(BasketRec) * (size_t)nb + sizeof(int64_t) * (size_t)(nb + 1);
-    if (need > g->h_cap) {
-        if (g->staged_pending) GN_HIP(hipEventSynchronize(g->staged));
-        g->staged_pending = false;
-        if (g->h_baskets) (void)hipHostFree(g->h_baskets);
-        g->h_baskets = nullptr;
+    geo_geometry::Stage &st = g->stage[g->stage_next];
+    if (st.pending) GN_HIP(hipEventSynchronize(st.done));
+    st.pending = false;
+    if (need > st.cap) {
+        if (st.host) (void)hipHostFree(st.host);
+        st.host = st.dev = nullptr;
+        st.cap = 0;
         const size_t cap = std::max(need, (size_t)(1 << 16));
-        if (hipHostMalloc(reinterpret_cast<void **>(&g->h_baskets), cap, hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc(&st.host, cap, hipHostMallocMapped) != hipSuccess)
             return fail(GEO_ERR_NOMEM, "pinned staging allocation failed");
-        g->h_cap = cap;
+        GN_HIP(hipHostGetDevicePointer(&st.dev, st.host, 0));
+        st.cap = cap;
     }
-    const bool grow_stage = need > g->d_bcap;
-    const bool grow_tiles = ntiles > g->tiles_cap;
-    if (grow_stage || grow_tiles) {
-        // buffers may still be in use by a previous graph launch on this stream
+    if (ntiles > g->tiles_cap) {
+        // the tile buffer may still be in use by a previous launch
         GN_HIP(hipStreamSynchronize(stream));
         GN_HIP(hipDeviceSynchronize());
         destroy_graph(g);
-        if (grow_stage) {
-            (void)hipFree(g->d_bstage);
-            g->d_bstage = nullptr;
-            const size_t cap = std::max(need, (size_t)(1 << 16));
-            if (hipMalloc(&g->d_bstage, cap) != hipSuccess) return fail(GEO_ERR_NOMEM, "device staging allocation failed");
-            g->d_bcap = cap;
-        }
-        if (grow_tiles) {
-            (void)hipFree(g->d_tiles);
-            g->d_tiles = nullptr;
-            const int64_t cap = std::max<int64_t>(ntiles + ntiles / 4, 4096);
-            if (hipMalloc(&g->d_tiles, sizeof(Tile) * (size_t)cap) != hipSuccess)
-                return fail(GEO_ERR_NOMEM, "device tile allocation failed");
-            g->tiles_cap = cap;
-        }
+        (void)hipFree(g->d_tiles);
+        g->d_tiles = nullptr;
+        const int64_t cap = std::max<int64_t>(ntiles + ntiles / 4, 4096);
+        if (hipMalloc(&g->d_tiles, sizeof(Tile) * (size_t)cap) != hipSuccess)
+            return fail(GEO_ERR_NOMEM, "device tile allocation failed");
+        g->tiles_cap = cap;
     }
     return GEO_OK;
 }
@@ -447,10 +451,9 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     if (ntiles > 0x7fffffff) return fail(GEO_ERR_INVALID_ARG, "too many tiles");
     int rc = ensure_capacity(g, ns, ntiles, stream);
     if (rc) return rc;
-    // stage baskets and tile starts in pinned memory, once the previous
-    // upload from it has completed
-    if (g->staged_pending) GN_HIP(hipEventSynchronize(g->staged));
-    BasketRec *hb = g->h_baskets;
+    // stage the sorted baskets and their tile starts in the free buffer
+    geo_geometry::Stage &st = g->stage[g->stage_next];
+    BasketRec *hb = static_cast<BasketRec *>(st.host);
     int64_t *hs = reinterpret_cast<int64_t *>(hb + ns);
     int64_t acc = 0;
     for (int i = 0; i < ns; ++i) {
@@ -459,14 +462,10 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
         acc += (s[i].n + tile_n - 1) / tile_n;
     }
     hs[ns] = acc;
-    const size_t bytes = sizeof(BasketRec) * (size_t)ns + sizeof(int64_t) * (size_t)(ns + 1);
-    GN_HIP(hipMemcpyAsync(g->d_bstage, hb, bytes, hipMemcpyHostToDevice, stream));
-    GN_HIP(hipEventRecord(g->staged, stream));
-    g->staged_pending = true;
 
     BuildTilesArgs ba;
-    ba.baskets = reinterpret_cast<const BasketRec *>(g->d_bstage);
-    ba.tile_start = reinterpret_cast<const int64_t *>(reinterpret_cast<const BasketRec *>(g->d_bstage) + ns);
+    ba.baskets = static_cast<const BasketRec *>(st.dev);
+    ba.tile_start = reinterpret_cast<const int64_t *>(static_cast<const BasketRec *>(st.dev) + ns);
     ba.nb = ns;
     ba.tile_n = tile_n;
     ba.tiles = g->d_tiles;
@@ -492,6 +491,9 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
         GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));
         GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true), dim3(grid), dim3(kBlock), pargs, 0,
                                stream));
+        GN_HIP(hipEventRecord(st.done, stream));
+        st.pending = true;
+        g->stage_next = (g->stage_next + 1) % geo_geometry::kStages;
         return GEO_OK;
     }
     hipKernelNodeParams kb = {};
@@ -527,6 +529,9 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     }
     g->graph_grid = grid;
     GN_HIP(hipGraphLaunch(g->exec, stream));
+    GN_HIP(hipEventRecord(st.done, stream));
+    st.pending = true;
+    g->stage_next = (g->stage_next + 1) % geo_geometry::kStages;
     return GEO_OK;
 }
 
