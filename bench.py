@@ -42,8 +42,8 @@ BYTES_PER_TRACK = 60             # 6 x 8 B in (x, y, z, ux, uy, uz) + 8 B step +
 # launch does comes from the library's census (geo_navigate_batched_census):
 # lane-evaluations per daughter kind, culling tests and tracks.
 FLOPS_MOTHER_BOX = 6             # box DistFromInside: 3 x (sub, div)
-FLOPS_TRACK_CULL = 5             # |d|^2 once per track (culling on)
-FLOPS_CULL_TEST = 20             # w = p - T (3), b (5), |w|^2 - R^2 (6), disc (3), m (2), m^2 (1)
+FLOPS_TRACK_CULL = 9             # |d|^2 (5), 1 / (2 |d|^2) (1), 2 d (3), once per track
+FLOPS_CULL_TEST = 18             # w = p - T (3), 2 w.d (5), |w|^2 (5), tau (1), |w + tau d|^2 (4)
 FLOPS_ROTATION = 30              # R^T w and R^T d (2 x 3 x (mul + 2 fma))
 FLOPS_DIST_OUT = [               # census slot 2 * kind + hole
     21, 21,                      # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)
@@ -56,7 +56,7 @@ def census_flops(counts, cull: bool) -> float:
     """FP64 flops of one launch from its census counts."""
     f = counts[7] * (FLOPS_MOTHER_BOX + (FLOPS_TRACK_CULL if cull else 0))
     f += counts[6] * FLOPS_CULL_TEST
-    per_eval_extra = FLOPS_ROTATION + (0 if cull else 3)   # without culling w is part of the evaluation
+    per_eval_extra = FLOPS_ROTATION + (0 if cull else 3)   # with culling, w = p - T belongs to the test
     for slot in range(6):
         f += counts[slot] * (per_eval_extra + FLOPS_DIST_OUT[slot])
     return float(f)

@@ -172,6 +172,7 @@ struct geo_geometry {
     std::vector<VolumeRec> h_vols;
     VolumeRec *d_vols = nullptr;
     DaughterRec *d_dau = nullptr;
+    CullRec *d_cull = nullptr;
     // adjoint partial sums: kBackwardMaxBlocks x 3 x max_nd
     double *d_partial = nullptr;
     // batched state
@@ -243,6 +244,7 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
     if (nvol <= 0 || !v) return fail(GEO_ERR_INVALID_ARG, "need nvol > 0 volumes");
     std::vector<VolumeRec> vols(nvol);
     std::vector<DaughterRec> dau;
+    std::vector<CullRec> cul;
     int max_nd = 0;
     for (int iv = 0; iv < nvol; ++iv) {
         const geo_volume_desc &d = v[iv];
@@ -278,6 +280,7 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             std::memcpy(dr.rot, d.placements[k].rot, sizeof dr.rot);
             std::memcpy(dr.tr, d.placements[k].tr, sizeof dr.tr);
             dau.push_back(dr);
+            cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2});
         }
     }
     geo_geometry *g = new (std::nothrow) geo_geometry();
@@ -300,6 +303,8 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of volumes failed"));
     if (!dau.empty() && hipMalloc(&g->d_dau, sizeof(DaughterRec) * dau.size()) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of daughters failed"));
+    if (!cul.empty() && hipMalloc(&g->d_cull, sizeof(CullRec) * cul.size()) != hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of culling records failed"));
     if (max_nd > 0 &&
         hipMalloc(&g->d_partial, sizeof(double) * 3 * (size_t)max_nd * kBackwardMaxBlocks) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of adjoint partials failed"));
@@ -310,6 +315,8 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
     if (!dau.empty()) {
         e = hipMemcpy(g->d_dau, dau.data(), sizeof(DaughterRec) * dau.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy daughters"));
+        e = hipMemcpy(g->d_cull, cul.data(), sizeof(CullRec) * cul.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy culling records"));
     }
     for (auto &st : g->stage) {
         e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
@@ -332,6 +339,7 @@ int geo_geometry_destroy(geo_geometry *g) {
     }
     (void)hipFree(g->d_vols);
     (void)hipFree(g->d_dau);
+    (void)hipFree(g->d_cull);
     (void)hipFree(g->d_partial);
     (void)hipFree(g->d_tiles);
     (void)hipFree(g->d_cursors);
@@ -368,7 +376,8 @@ int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, con
         return rc;
     if ((rc = check_device(g))) return rc;
     const int first = g->h_vols[volume].first;
-    hipError_t e = launch_nav_basket(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr, to_dev(t),
+    hipError_t e = launch_nav_basket(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
+                                     g->d_cull ? g->d_cull + first : nullptr, to_dev(t),
                                      g->h_vols[volume].nd > 0 ? offsets : nullptr, step, hit, hitpt, g->cull,
                                      stream);
     if (e != hipSuccess) return hip_fail(e, "navigator launch");
@@ -390,7 +399,8 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
     if (t.n == 0 && !(g_off && nd > 0)) return GEO_OK;
     if ((rc = check_device(g))) return rc;
     const int first = g->h_vols[volume].first;
-    hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr, nd, to_dev(t),
+    hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
+                                   g->d_cull ? g->d_cull + first : nullptr, nd, to_dev(t),
                                    nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, g->d_partial,
                                    nd > 0 ? g_off : nullptr, g->cull, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
@@ -473,6 +483,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     PersistentArgs pa;
     pa.vols = g->d_vols;
     pa.dau = g->d_dau;
+    pa.cul = g->d_cull;
     pa.tiles = g->d_tiles;
     pa.ntiles = (int32_t)ntiles;
     pa.cursors = g->d_cursors;
@@ -484,8 +495,8 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     const bool persistent = g->waves_per_simd > 0;
     const int grid = batched_grid(g->waves_per_simd, g->num_cus, ntiles);
     void *bargs[] = {&ba};
-    void *pargs[] = {&pa.vols, &pa.dau, &pa.tiles, &pa.ntiles, &pa.cursors, &pa.t, &pa.step, &pa.hit,
-                     &pa.census};
+    void *pargs[] = {&pa.vols, &pa.dau, &pa.cul, &pa.tiles, &pa.ntiles, &pa.cursors, &pa.t, &pa.step,
+                     &pa.hit, &pa.census};
     if (census) {  // instrumented run: direct launches, no graph
         GN_HIP(hipMemsetAsync(census, 0, 8 * sizeof(unsigned long long), stream));
         GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));

@@ -47,10 +47,19 @@ struct alignas(16) DaughterRec {
 };
 static_assert(sizeof(DaughterRec) == 288, "DaughterRec layout");
 
+// Culling record of a daughter, in its own compact array (32 B, so the
+// records of a whole volume stay in the scalar cache during the daughter
+// loop): the centre of the bounding sphere in the mother frame (T) and the
+// squared culling radius.
+struct alignas(16) CullRec {
+    double tx, ty, tz, r2;
+};
+static_assert(sizeof(CullRec) == 32, "CullRec layout");
+
 struct alignas(16) VolumeRec {
     ShapeRec mother;
     int32_t nd;     // number of daughters
-    int32_t first;  // index of daughter 0 in the daughter table
+    int32_t first;  // index of daughter 0 in the daughter and culling tables
     int32_t pad[6];
 };
 static_assert(sizeof(VolumeRec) == 192, "VolumeRec layout");
@@ -455,13 +464,14 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, doubl
 // (scalar loads, scalar branch).
 //
 // With CULL, a daughter is skipped for the whole wavefront when no lane's
-// line can enter the daughter's (slightly enlarged) bounding sphere before
-// that lane's current best step: such a daughter could not lower the best
-// step nor win a tie (ties keep the earlier candidate), so the results are
-// bit-identical to evaluating it. With the sphere centre c, w = p - c,
-// b = w.d, cc = |w|^2 - R^2, disc = b^2 - |d|^2 cc, the line misses the
-// sphere when cc > 0 and (b >= 0 or disc < 0), and it enters no earlier than
-// `best` when m = -b - best |d|^2 >= 0 and m^2 >= disc.
+// segment from p to p + best d (best = that lane's current step) comes within
+// the daughter's bounding-sphere radius of the sphere's centre c (radius
+// enlarged by 1e-6 relative + 1e-6, which covers the rounding of this test).
+// Such a daughter cannot be entered before `best`, so it could neither lower
+// the step nor win a tie (ties keep the earlier candidate): the results are
+// bit-identical to evaluating it. With w = p - c the squared distance from c
+// to the point at parameter tau is |w|^2 + tau (2 w.d + tau |d|^2), smallest
+// over [0, best] at tau = clamp(-w.d / |d|^2, 0, best).
 //
 // With COUNT, the work done is tallied into census[8] (one atomic per
 // wavefront and event, adding the number of active lanes): slots
@@ -475,6 +485,7 @@ __device__ __forceinline__ void census_add(unsigned long long *census, int slot)
 
 template <bool HAS_OFFS, bool TRACK_SURF, bool CULL, bool COUNT = false>
 __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                          const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, double x, double y,
                                           double z, double ux, double uy, double uz, double &best,
                                           int &hit, int &bsid,
@@ -484,11 +495,14 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
     best = any_dist_in(v.mother, x, y, z, ux, uy, uz, sid);
     hit = -1;
     bsid = sid;
+    // per-track constants of the culling test: |d|^2, 1 / (2 |d|^2), 2 d
     const double dd = CULL ? fma(uz, uz, fma(uy, uy, ux * ux)) : 0.0;
+    const double hdd = (CULL && dd > 0.0) ? fdiv(0.5, dd) : 0.0;
+    const double ux2 = 2.0 * ux, uy2 = 2.0 * uy, uz2 = 2.0 * uz;
     const int nd = v.nd;
     for (int k = 0; k < nd; ++k) {
-        const DaughterRec &D = dau[k];
-        double wx = x - D.tr[0], wy = y - D.tr[1], wz = z - D.tr[2];
+        const CullRec &Q = cul[k];
+        double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
         if (HAS_OFFS) {
             wx -= offs[3 * k + 0];
             wy -= offs[3 * k + 1];
@@ -496,14 +510,13 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
         }
         if (CULL) {
             if (COUNT) census_add(census, 6);
-            const double b = fma(wz, uz, fma(wy, uy, wx * ux));
-            const double cc = fma(wz, wz, fma(wy, wy, wx * wx)) - D.cull_r2;
-            const double disc = fma(-dd, cc, b * b);
-            const double m = fma(-best, dd, -b);
-            const bool reach =
-                cc <= 0.0 || (b < 0.0 && disc >= 0.0 && !(m >= 0.0 && m * m >= disc));
-            if (__ballot(reach) == 0) continue;
+            const double b2 = fma(wz, uz2, fma(wy, uy2, wx * ux2));    // 2 w.d
+            const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
+            const double tau = fmax(fmin(-b2 * hdd, best), 0.0);
+            const double f = fma(tau, fma(tau, dd, b2), ww);            // |w + tau d|^2
+            if (__ballot(f <= Q.r2) == 0) continue;
         }
+        const DaughterRec &D = dau[k];
         if (COUNT) census_add(census, 2 * D.shape.kind + D.shape.hole);
         const double *R = D.rot;
         // local = R^T w

@@ -14,9 +14,9 @@ constexpr int kBackwardMaxBlocks = 2048;
 hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, void *out,
                               hipStream_t st);
 
-hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const TracksDev &t,
-                             const double *offs, double *step, int32_t *hit, double *hitpt, bool cull,
-                             hipStream_t st);
+hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
+                             const TracksDev &t, const double *offs, double *step, int32_t *hit,
+                             double *hitpt, bool cull, hipStream_t st);
 
 // Tile queues of the persistent batched kernel: one per XCD, cursors 256 B
 // apart.
@@ -29,6 +29,7 @@ constexpr int kQueueStride = 64;  // in unsigned ints
 struct PersistentArgs {
     const VolumeRec *vols;
     const DaughterRec *dau;
+    const CullRec *cul;
     const Tile *tiles;
     int32_t ntiles;
     unsigned int *cursors;       // kQueues * kQueueStride
@@ -66,7 +67,7 @@ const void *build_tiles_kernel();
 // one wavefront per tile (waves_per_simd == 0).
 int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles);
 
-hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
+hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
                            double *g_off, bool cull, hipStream_t st);

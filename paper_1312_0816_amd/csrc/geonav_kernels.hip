@@ -77,6 +77,7 @@ hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, 
 template <bool HAS_OFFS, bool HITPT, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
+                                                       const CullRec *__restrict__ cul,
                                                        TracksDev t, const double *__restrict__ offs,
                                                        double *__restrict__ step,
                                                        int32_t *__restrict__ hit,
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
     double best;
     int h, sid;
-    nav_track<HAS_OFFS, false, CULL>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
+    nav_track<HAS_OFFS, false, CULL>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h, sid);
     step[i] = best;
     hit[i] = h;
     if (HITPT) {
@@ -100,25 +101,25 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
 
 template <bool CULL>
 static void launch_basket_variant(dim3 grid, const VolumeRec *vol, const DaughterRec *dau,
-                                  const TracksDev &t, const double *offs, double *step, int32_t *hit,
+                                  const CullRec *cul, const TracksDev &t, const double *offs, double *step, int32_t *hit,
                                   double *hitpt, hipStream_t st) {
     const dim3 block(kBlock);
     if (offs) {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
     } else {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL>), grid, block, 0, st, vol, dau, t, offs, step, hit, hitpt);
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
     }
 }
 
-hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const TracksDev &t,
-                             const double *offs, double *step, int32_t *hit, double *hitpt, bool cull,
-                             hipStream_t st) {
+hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
+                             const TracksDev &t, const double *offs, double *step, int32_t *hit,
+                             double *hitpt, bool cull, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
-    if (cull) launch_basket_variant<true>(grid, vol, dau, t, offs, step, hit, hitpt, st);
-    else launch_basket_variant<false>(grid, vol, dau, t, offs, step, hit, hitpt, st);
+    if (cull) launch_basket_variant<true>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st);
+    else launch_basket_variant<false>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st);
     return hipGetLastError();
 }
 
@@ -129,11 +130,13 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
 // baskets by daughter count; k_build_tiles expands them in that order).
 template <int U, bool CULL, bool COUNT>
 __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__restrict__ vols,
-                                         const DaughterRec *__restrict__ dau_all, const TracksDev &t,
+                                         const DaughterRec *__restrict__ dau_all,
+                                         const CullRec *__restrict__ cul_all, const TracksDev &t,
                                          double *__restrict__ step, int32_t *__restrict__ hit,
                                          unsigned long long *census, int lane) {
     const VolumeRec &v = vols[tl.volume];
     const DaughterRec *dau = dau_all + v.first;
+    const CullRec *cul = cul_all + v.first;
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;
@@ -143,8 +146,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__rest
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int h, sid;
-            nav_track<false, false, CULL, COUNT>(v, dau, nullptr, x, y, z, ux, uy, uz, best, h, sid,
-                                                 census);
+            nav_track<false, false, CULL, COUNT>(v, dau, cul, nullptr, x, y, z, ux, uy, uz, best, h,
+                                                 sid, census);
             step[i] = best;
             hit[i] = h;
         }
@@ -161,6 +164,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__rest
 template <int U, bool CULL, bool COUNT = false>
 __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__restrict__ vols,
                                                            const DaughterRec *__restrict__ dau_all,
+                                                           const CullRec *__restrict__ cul_all,
                                                            const Tile *__restrict__ tiles,
                                                            int32_t ntiles, unsigned int *cursors,
                                                            TracksDev t, double *__restrict__ step,
@@ -176,8 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
             if (lane == 0) id = atomicAdd(&cursors[q * kQueueStride], 1u);
             id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
             if (id >= count) break;
-            run_tile<U, CULL, COUNT>(tiles[q + kQueues * (int64_t)id], vols, dau_all, t, step, hit,
-                                     census, lane);
+            run_tile<U, CULL, COUNT>(tiles[q + kQueues * (int64_t)id], vols, dau_all, cul_all, t, step,
+                                     hit, census, lane);
         }
     }
 }
@@ -187,6 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
 template <int U, bool CULL, bool COUNT = false>
 __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restrict__ vols,
                                                       const DaughterRec *__restrict__ dau_all,
+                                                      const CullRec *__restrict__ cul_all,
                                                       const Tile *__restrict__ tiles, int32_t ntiles,
                                                       unsigned int *cursors, TracksDev t,
                                                       double *__restrict__ step,
@@ -195,7 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restric
     (void)cursors;
     const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
     if (w >= ntiles) return;
-    run_tile<U, CULL, COUNT>(tiles[w], vols, dau_all, t, step, hit, census, (int)(threadIdx.x & 63));
+    run_tile<U, CULL, COUNT>(tiles[w], vols, dau_all, cul_all, t, step, hit, census,
+                             (int)(threadIdx.x & 63));
 }
 
 // Expands the (cost-sorted) basket list into tiles of at most tile_n tracks:
@@ -263,8 +269,9 @@ int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles) {
 // fixed lane order into the workgroup's row of `partial`.
 template <bool HAS_OFFS, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_nav_backward(
-    const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau, TracksDev t,
-    const double *__restrict__ offs, const double *__restrict__ gstep,
+    const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau,
+    const CullRec *__restrict__ cul, TracksDev t, const double *__restrict__ offs,
+    const double *__restrict__ gstep,
     const double *__restrict__ ghit, double *__restrict__ g_o, double *__restrict__ g_d,
     double *__restrict__ partial) {
     __shared__ int s_hit[kBlock];
@@ -285,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int sid;
-            nav_track<HAS_OFFS, true, CULL>(*vol, dau, offs, x, y, z, ux, uy, uz, best, h, sid);
+            nav_track<HAS_OFFS, true, CULL>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h, sid);
             const bool finite = best < kBig;
             const double s = finite ? best : 0.0;
             const double hx = fma(s, ux, x), hy = fma(s, uy, y), hz = fma(s, uz, z);
@@ -374,18 +381,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__rest
 
 template <bool CULL>
 static void launch_backward_variant(int nblocks, const VolumeRec *vol, const DaughterRec *dau,
-                                    const TracksDev &t, const double *offs, const double *gstep,
+                                    const CullRec *cul, const TracksDev &t, const double *offs, const double *gstep,
                                     const double *ghit, double *g_o, double *g_d, double *part,
                                     hipStream_t st) {
     if (offs)
-        hipLaunchKernelGGL((k_nav_backward<true, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
+        hipLaunchKernelGGL((k_nav_backward<true, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
                            offs, gstep, ghit, g_o, g_d, part);
     else
-        hipLaunchKernelGGL((k_nav_backward<false, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, t,
+        hipLaunchKernelGGL((k_nav_backward<false, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
                            offs, gstep, ghit, g_o, g_d, part);
 }
 
-hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
+hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
                            double *g_off, bool cull, hipStream_t st) {
@@ -393,8 +400,8 @@ hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, int nd,
     const int nblocks = (int)(need < kBackwardMaxBlocks ? (need > 0 ? need : 1) : kBackwardMaxBlocks);
     double *part = (g_off && nd > 0) ? partial : nullptr;
     if (t.n > 0 || part) {
-        if (cull) launch_backward_variant<true>(nblocks, vol, dau, t, offs, gstep, ghit, g_o, g_d, part, st);
-        else launch_backward_variant<false>(nblocks, vol, dau, t, offs, gstep, ghit, g_o, g_d, part, st);
+        if (cull) launch_backward_variant<true>(nblocks, vol, dau, cul, t, offs, gstep, ghit, g_o, g_d, part, st);
+        else launch_backward_variant<false>(nblocks, vol, dau, cul, t, offs, gstep, ghit, g_o, g_d, part, st);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
