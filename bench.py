@@ -136,7 +136,53 @@ def measure_rows(gv, W, dev):
     rows["adjoint_toy_detector_2^20"] = {"ms": ms, "tracks_per_s": n / (ms * 1e-3),
                                         "outputs": "g_o, g_d (3 x n) and g_off (32 x 3)"}
     g.close()
+    del o, d, gh
+    rows["paper_toy_detector_basket_scan"] = basket_scan(gv, W, dev)
     return rows
+
+
+SCAN_TOTAL = 1 << 20
+
+
+def basket_scan(gv, W, dev):
+    """The paper's benchmark protocol on its toy detector: P baskets of N
+    consecutive particles from a random start in a 2^20-track pool, N x P =
+    2^20 fixed; runtime per particle for one launch per basket and for all
+    baskets in one batched launch (N x P = 2^20)."""
+    import torch
+    vol = W.paper_toy_detector()
+    pool = W.paper_toy_tracks(n=1 << 21)
+    g = gv.Geometry([vol])
+    t = torch.from_numpy(pool).to(dev)
+    n = t.shape[1]
+    step = torch.empty(n, dtype=torch.float64, device=dev)
+    hit = torch.empty(n, dtype=torch.int32, device=dev)
+    lib, hs = g._lib, gv._stream()
+    tr = gv.tracks_struct(t)
+    start = 0 if n == SCAN_TOTAL else int(np.random.default_rng(1501).integers(0, n - SCAN_TOTAL))
+    out = {}
+    for N in (16, 64, 256, 1024, 4096, 16384, 65536):
+        P = SCAN_TOTAL // N
+        offs = start + N * np.arange(P)
+        barr, nb = gv._baskets(np.zeros(P, np.int32), offs, np.full(P, N))
+        sp, hp = gv._ptr(step), gv._ptr(hit)
+        ms_b = _time_ms(lambda: gv._check(lib.geo_navigate_batched(g.handle, barr, nb, tr, sp, hp, hs)),
+                        reps=5, warm=2)
+        plain = [(gv.GeoTracks(tr.x + 8 * o, tr.y + 8 * o, tr.z + 8 * o, tr.ux + 8 * o, tr.uy + 8 * o,
+                               tr.uz + 8 * o, N),
+                  gv.C.c_void_p(step.data_ptr() + 8 * o), gv.C.c_void_p(hit.data_ptr() + 4 * o))
+                 for o in (int(v) for v in offs)]
+
+        def run_plain():
+            for tb, s_, h_ in plain:
+                gv._check(lib.geo_navigate_basket(g.handle, 0, tb, None, s_, h_, None, hs))
+
+        ms_p = _time_ms(run_plain, reps=1 if P > 1024 else 3, warm=1 if P <= 4096 else 0)
+        out[str(N)] = {"baskets": P,
+                       "batched_ns_per_particle": ms_b * 1e6 / SCAN_TOTAL,
+                       "per_basket_launches_ns_per_particle": ms_p * 1e6 / SCAN_TOTAL}
+    g.close()
+    return out
 
 
 def kernel_source_digest() -> str:
@@ -209,6 +255,15 @@ def cpu_baseline(wl, gpu_step, gpu_hit, threads):
     base = {"value": n / dt, "unit": "tracks/s", "cores": threads, "kind": "oracle",
             "sample": f"the whole batched workload ({n} tracks, {len(wl.basket_n)} baskets), "
                       f"oracle double build, {threads} threads, {dt:.2f} s"}
+    # the sequential (one particle at a time) navigator of Fig. 1a on the
+    # paper's toy detector, one thread: the analogue of the paper's scalar
+    # baseline in its basket-size scan
+    from paper_1312_0816_amd import workloads as W
+    vol = W.paper_toy_detector()
+    sub = np.ascontiguousarray(W.paper_toy_tracks()[:, :SCAN_TOTAL])
+    t0 = time.perf_counter()
+    oracle.navigate(vol, sub, None, "d")
+    base["paper_toy_detector_1thread_ns_per_particle"] = (time.perf_counter() - t0) * 1e9 / SCAN_TOTAL
     return base, parity
 
 

@@ -205,22 +205,46 @@ __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restric
 }
 
 // Expands the (cost-sorted) basket list into tiles of at most tile_n tracks:
-// basket b owns tiles [tile_start[b], tile_start[b + 1]). Also resets the
-// persistent kernel's queue cursors.
+// basket b owns tiles [tile_start[b], tile_start[b + 1]). The baskets are
+// split into one contiguous run per wavefront (ceil(nb / waves) baskets, so
+// a few hundred baskets spread over as many wavefronts); within its run a
+// wavefront reads up to 64 basket records at once, lane j taking record j
+// (mapped host memory: one round trip per 64), then writes each basket's
+// tiles 64 at a time. Also resets the persistent kernel's queue cursors.
 __global__ __launch_bounds__(kBlock) void k_build_tiles(BuildTilesArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * (kBlock / 64);
     if (blockIdx.x == 0 && threadIdx.x < kQueues) a.cursors[threadIdx.x * kQueueStride] = 0u;
-    for (int b = blockIdx.x; b < a.nb; b += gridDim.x) {
-        const BasketRec bk = a.baskets[b];
-        const int64_t first = a.tile_start[b];
-        const int64_t cnt = a.tile_start[b + 1] - first;
-        for (int64_t c = threadIdx.x; c < cnt; c += kBlock) {
-            const int64_t off = c * a.tile_n;
-            const int64_t left = bk.n - off;
-            Tile tl;
-            tl.volume = bk.volume;
-            tl.count = (int32_t)(left < a.tile_n ? left : a.tile_n);
-            tl.offset = bk.offset + off;
-            a.tiles[first + c] = tl;
+    const int run = (a.nb + nwaves - 1) / nwaves;
+    const int b0 = wave * run;
+    const int b1 = b0 + run < a.nb ? b0 + run : a.nb;
+    for (int base = b0; base < b1; base += 64) {
+        const int b = base + lane;
+        int vol = 0;
+        int64_t off = 0, n = 0, first = 0, last = 0;
+        if (b < b1) {
+            const BasketRec bk = a.baskets[b];
+            vol = bk.volume;
+            off = bk.offset;
+            n = bk.n;
+            first = a.tile_start[b];
+            last = a.tile_start[b + 1];
+        }
+        const int m = b1 - base < 64 ? b1 - base : 64;
+        for (int i = 0; i < m; ++i) {
+            const int v_i = __shfl(vol, i);
+            const int64_t off_i = __shfl(off, i), n_i = __shfl(n, i);
+            const int64_t f_i = __shfl(first, i), l_i = __shfl(last, i);
+            for (int64_t c = lane; c < l_i - f_i; c += 64) {
+                const int64_t o = c * a.tile_n;
+                const int64_t left = n_i - o;
+                Tile tl;
+                tl.volume = v_i;
+                tl.count = (int32_t)(left < a.tile_n ? left : a.tile_n);
+                tl.offset = off_i + o;
+                a.tiles[f_i + c] = tl;
+            }
         }
     }
 }

@@ -310,3 +310,80 @@ def adjoint_c4(seed: int = 1400, n: int = 1 << 20, detector_seed: int = 1200):
     rng_t = np.random.default_rng(seed + 1)
     targets = np.ascontiguousarray(rng_t.uniform(-MOTHER_HALF, MOTHER_HALF, (3, n)))
     return vol, tracks, targets
+
+
+# ----------------------------------------------------------------------------
+# The paper's toy detector (section 3.2): a tubular mother holding two tubes
+# (beampipe, shield), four boxes (detector plates) and two cones (endcaps).
+# The paper gives its composition but no dimensions; the ones below are this
+# project's choice, non-overlapping by construction.
+# ----------------------------------------------------------------------------
+
+PAPER_MOTHER = np.array([0.0, 100.0, 200.0, 0.0, 0.0])      # tube rmin, rmax, dz
+
+
+def paper_toy_detector() -> Volume:
+    """Tube mother (0, 100, 200) with
+      beampipe tube (3, 4, 180) and shield tube (40, 45, 150) on the axis,
+      four plates: boxes (5, 20, 100) at radius 70 on the x and y axes
+        (the y ones turned by 90 degrees about z),
+      two endcaps: cones (dz 10; rmin 5 -> 5, rmax 50 -> 90) at z = +170 and,
+        turned by 180 degrees about x, at z = -170.
+    Radial layout: beampipe r <= 4, shield 40..45, plates 65..77.7,
+    endcaps 5..90 for 160 <= |z| <= 180; the shield ends at |z| = 150 and the
+    plates at |z| = 100."""
+    kinds = np.array([TUBE, TUBE, BOX, BOX, BOX, BOX, CONE, CONE], np.int32)
+    pars = np.array([
+        [3.0, 4.0, 180.0, 0.0, 0.0],
+        [40.0, 45.0, 150.0, 0.0, 0.0],
+        [5.0, 20.0, 100.0, 0.0, 0.0],
+        [5.0, 20.0, 100.0, 0.0, 0.0],
+        [5.0, 20.0, 100.0, 0.0, 0.0],
+        [5.0, 20.0, 100.0, 0.0, 0.0],
+        [10.0, 5.0, 50.0, 5.0, 90.0],
+        [10.0, 5.0, 50.0, 5.0, 90.0],
+    ])
+    rz90 = euler_zxz(np.pi / 2, 0.0, 0.0)
+    rx180 = euler_zxz(0.0, np.pi, 0.0)
+    eye = np.eye(3).reshape(9)
+    rots = np.stack([eye, eye, eye, eye, rz90, rz90, eye, rx180])
+    trs = np.array([
+        [0.0, 0.0, 0.0], [0.0, 0.0, 0.0],
+        [70.0, 0.0, 0.0], [-70.0, 0.0, 0.0], [0.0, 70.0, 0.0], [0.0, -70.0, 0.0],
+        [0.0, 0.0, 170.0], [0.0, 0.0, -170.0],
+    ])
+    bound = np.array([np.hypot(4.0, 180.0), np.hypot(45.0, 150.0)] +
+                     [float(np.sqrt(5.0 ** 2 + 20.0 ** 2 + 100.0 ** 2))] * 4 +
+                     [float(np.hypot(90.0, 10.0))] * 2)
+    return Volume(TUBE, PAPER_MOTHER.copy(), kinds, pars, rots, trs, bound)
+
+
+def _cyl_shell(rng, n, r0, r1, z0, z1):
+    """n points uniform in {r0 <= r <= r1, z0 <= z <= z1} (cylindrical shell)."""
+    r = np.sqrt(rng.uniform(r0 * r0, r1 * r1, n))
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    z = rng.uniform(z0, z1, n)
+    return np.stack([r * np.cos(ph), r * np.sin(ph), z])
+
+
+def paper_toy_tracks(seed: int = 1500, n: int = 1 << 20) -> np.ndarray:
+    """Tracks in the mother's exclusive part (outside every daughter), drawn
+    from cylindrical regions that are empty by construction of
+    paper_toy_detector(), each with probability proportional to its volume:
+      5 <= r <= 39,  |z| <= 150      between beampipe and shield
+      46 <= r <= 64, |z| <= 150      between shield and plates
+      78 <= r <= 99, |z| <= 150      outside the plates
+      5 <= r <= 99, 151 <= |z| <= 159 between shield end and endcaps
+      5 <= r <= 99, 181 <= |z| <= 199 beyond the endcaps
+    Isotropic directions. (The thin regions next to each daughter are left
+    out, so origins stay at least 1 unit from every daughter.)"""
+    rng = np.random.default_rng(seed)
+    regions = [(5.0, 39.0, -150.0, 150.0), (46.0, 64.0, -150.0, 150.0), (78.0, 99.0, -150.0, 150.0),
+               (5.0, 99.0, 151.0, 159.0), (5.0, 99.0, -159.0, -151.0),
+               (5.0, 99.0, 181.0, 199.0), (5.0, 99.0, -199.0, -181.0)]
+    vol = np.array([(r1 * r1 - r0 * r0) * (z1 - z0) for r0, r1, z0, z1 in regions])
+    counts = rng.multinomial(n, vol / vol.sum())
+    pts = np.concatenate([_cyl_shell(rng, c, *reg) for c, reg in zip(counts, regions)], axis=1)
+    pts = pts[:, rng.permutation(n)]
+    u = isotropic(rng, n)
+    return pack_tracks(pts[0], pts[1], pts[2], *u)

@@ -403,3 +403,27 @@ def test_workloads_are_deterministic():
     w2 = W.batched_c3(scale=0.01)
     assert np.array_equal(w1.tracks, w2.tracks)
     assert np.array_equal(w1.basket_n, w2.basket_n)
+
+
+def test_paper_toy_detector_is_valid(orc):
+    """Daughters of the paper's toy detector do not overlap and lie in the
+    mother (points sampled inside each daughter are in no other daughter and
+    in the mother), and the sampled tracks are in the mother's exclusive
+    part."""
+    vol = W.paper_toy_detector()
+    rng = np.random.default_rng(3)
+    for k in range(vol.nd):
+        q = np.stack(W._sample_in_shape(rng, int(vol.kinds[k]), vol.pars[k], 20000))
+        R = vol.rots[k].reshape(3, 3)
+        p = R @ q + vol.trs[k][:, None]                        # daughter frame -> mother frame
+        assert orc.contains(W.TUBE, vol.mother_par, np.concatenate([p, np.zeros_like(p)])).all()
+        for j in range(vol.nd):
+            if j != k:
+                qj = to_local(vol, j, p)
+                assert not orc.contains(int(vol.kinds[j]), vol.pars[j],
+                                        np.concatenate([qj, np.zeros_like(qj)])).any(), (k, j)
+    t = W.paper_toy_tracks(n=50000)
+    assert orc.contains(W.TUBE, vol.mother_par, t).all()
+    for k in range(vol.nd):
+        q = to_local(vol, k, t[:3])
+        assert not orc.contains(int(vol.kinds[k]), vol.pars[k], np.concatenate([q, np.zeros_like(q)])).any()
