@@ -122,8 +122,13 @@ def measure_rows(gv, W, dev):
                                           "TFLOPs": fl / (ms * 1e-3) / 1e12,
                                           "alu_frac": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                                           "evaluated_fraction": sum(counts[:6]) / max(1, counts[6])}
+    saf = torch.empty(n, dtype=torch.float64, device=dev)
+    ms_s = _time_ms(lambda: gv._check(lib.geo_navigate_safety(g.handle, 0, trs, None, gv._ptr(saf), hs)))
+    ms_l = _time_ms(lambda: gv._check(lib.geo_locate(g.handle, 0, trs, None, hp, hs)))
+    rows["navigator_safety_toy_detector_2^22"] = {"ms": ms_s, "points_per_s": n / (ms_s * 1e-3)}
+    rows["locate_toy_detector_2^22"] = {"ms": ms_l, "points_per_s": n / (ms_l * 1e-3)}
     g.close()
-    del t, step, hit
+    del t, step, hit, saf
 
     vol, tr, tgt = W.adjoint_c4()
     g = gv.Geometry([vol])

@@ -129,6 +129,23 @@ int geo_shape_query(const geo_shape *s, int32_t query, geo_tracks t, void *out, 
 int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
                         double *step, int32_t *hit, double *hitpt, hipStream_t stream);
 
+/* The navigator's isotropic safety (section 3: safe distances to the
+ * volume's boundaries) for every point of a basket of `volume`:
+ *   safety[i] = min( Safety_mother(p_i), min_k Safety_k(R_k^T (p_i - T_k - delta_k)) )
+ * with each Safety the Euclidean distance to that shape's surface, so for a
+ * point in the mother's own part it is the distance to the nearest boundary
+ * of the volume. Only x, y, z of t are read (directions may be NULL).
+ * offsets as for geo_navigate_basket. safety: device double[n]. */
+int geo_navigate_safety(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                        double *safety, hipStream_t stream);
+
+/* Localization (section 3: the containing volume of a point): where[i] = the
+ * lowest daughter index k whose shape contains R_k^T (p_i - T_k - delta_k),
+ * -1 for a point in the mother but in no daughter, -2 for a point outside
+ * the mother. Only x, y, z of t are read. where: device int32[n]. */
+int geo_locate(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets, int32_t *where,
+               hipStream_t stream);
+
 /* Many baskets of possibly different volumes in ONE persistent launch
  * (replayed from a cached HIP graph). baskets: host array of nb entries
  * indexing into the shared pool `all`; step and hit are indexed like the
@@ -195,7 +212,9 @@ int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t wave
  * daughter's bounding sphere (radius enlarged by 1e-6 relative + 1e-6) before
  * that lane's current best step. The daughter could neither lower a step nor
  * win a tie, so results are bit-identical with culling on or off; only the
- * work done changes. On by default. */
+ * work done changes. Applies likewise to geo_navigate_safety (a daughter
+ * whose sphere is farther than the current safety) and geo_locate (a point
+ * outside the sphere). On by default. */
 int geo_set_culling(geo_geometry *g, int32_t enable);
 int geo_get_culling(const geo_geometry *g, int32_t *enabled);
 

@@ -58,6 +58,12 @@ def _load():
             f.argtypes = ([C.c_int, P, C.c_int, P, P, P, P, P, C.c_int64] + [P] * 6 +
                           [P, P, C.c_double, C.c_double, C.c_double, C.c_double] + [P] * 5)
             f.restype = None
+            f = getattr(lib, "or_navigate_safety" + sfx)
+            f.argtypes = [C.c_int, P, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P]
+            f.restype = None
+            f = getattr(lib, "or_locate" + sfx)
+            f.argtypes = [C.c_int, P, C.c_int, P, P, P, P, P, C.c_int64, P, P, P, P]
+            f.restype = None
         lib.or_max_daughters.restype = C.c_int
         _lib = lib
     return _lib
@@ -163,3 +169,30 @@ def navigate_fd(vol, tracks, offsets=None, gstep=None, ghit=None, h: float = 1e-
                                            float(kink_tol), float(fd_tol), _ptr(g_o), _ptr(g_d),
                                            _ptr(g_off), _ptr(hit), _ptr(mask))
     return {"g_o": g_o, "g_d": g_d, "g_off_hit": g_off, "hit": hit, "mask": mask.astype(bool)}
+
+
+def navigate_safety(vol, points, offsets=None, prec: str = "d"):
+    """Safe distance to the volume's boundaries: min of the mother's Safety
+    and every daughter's Safety in its frame. points: (3, n) or (6, n)."""
+    lib = _load()
+    v, args = _vol_args(vol)
+    t = _tracks(points)
+    n = t.shape[1]
+    offs = None if offsets is None else _f64(offsets, (v.nd, 3))
+    out = np.zeros(n)
+    getattr(lib, "or_navigate_safety_" + prec)(*args, _ptr(offs), n, _ptr(t[0]), _ptr(t[1]), _ptr(t[2]),
+                                               _ptr(out))
+    return out
+
+
+def locate(vol, points, offsets=None, prec: str = "d"):
+    """Index of the daughter holding each point (lowest index), -1 for the
+    mother's own part, -2 outside the mother."""
+    lib = _load()
+    v, args = _vol_args(vol)
+    t = _tracks(points)
+    n = t.shape[1]
+    offs = None if offsets is None else _f64(offsets, (v.nd, 3))
+    out = np.zeros(n, np.int32)
+    getattr(lib, "or_locate_" + prec)(*args, _ptr(offs), n, _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(out))
+    return out

@@ -415,3 +415,65 @@ void FN(or_navigate_fd)(int mother_kind, const double *mother_par, int nd,
         mask[i] = (uint8_t)ok;
     }
 }
+
+/* ------------------------------------------- navigator safety and locate
+ * The navigator's other two tasks (section 3): the safe distance to the
+ * boundaries of the volume — the smaller of the mother's Safety and every
+ * daughter's Safety taken in the daughter's frame — and localization: the
+ * daughter holding the point (lowest index), -1 for the mother's own part,
+ * -2 for a point outside the mother.                                      */
+static void FN(local_point)(const FN(vol) *v, int k, const R *p, const R *offs, R *pl)
+{
+    const double *rm = v->rots + 9 * k;
+    R w[3];
+    for (int i = 0; i < 3; ++i)
+        w[i] = p[i] - (R)v->trs[3 * k + i] - (offs ? offs[3 * k + i] : 0);
+    for (int j = 0; j < 3; ++j)
+        pl[j] = (R)rm[0 + j] * w[0] + (R)rm[3 + j] * w[1] + (R)rm[6 + j] * w[2];
+}
+
+void FN(or_navigate_safety)(int mother_kind, const double *mother_par, int nd,
+                            const int32_t *kinds, const double *pars, const double *rots,
+                            const double *trs, const double *offsets, int64_t n,
+                            const double *x, const double *y, const double *z, double *safety)
+{
+    FN(vol) v = { mother_kind, mother_par, nd, kinds, pars, rots, trs };
+    R offs[3 * OR_MAX_DAUGHTERS];
+    if (offsets)
+        for (int i = 0; i < 3 * nd; ++i) offs[i] = offsets[i];
+    for (int64_t i = 0; i < n; ++i) {
+        R p[3] = { x[i], y[i], z[i] };
+        R best = FN(safety)(mother_kind, mother_par, p[0], p[1], p[2]);
+        for (int k = 0; k < nd; ++k) {
+            R pl[3];
+            FN(local_point)(&v, k, p, offsets ? offs : 0, pl);
+            R s = FN(safety)(kinds[k], pars + 5 * k, pl[0], pl[1], pl[2]);
+            if (s < best) best = s;
+        }
+        safety[i] = (double)best;
+    }
+}
+
+void FN(or_locate)(int mother_kind, const double *mother_par, int nd, const int32_t *kinds,
+                   const double *pars, const double *rots, const double *trs,
+                   const double *offsets, int64_t n, const double *x, const double *y,
+                   const double *z, int32_t *where)
+{
+    FN(vol) v = { mother_kind, mother_par, nd, kinds, pars, rots, trs };
+    R offs[3 * OR_MAX_DAUGHTERS];
+    if (offsets)
+        for (int i = 0; i < 3 * nd; ++i) offs[i] = offsets[i];
+    for (int64_t i = 0; i < n; ++i) {
+        R p[3] = { x[i], y[i], z[i] };
+        int32_t w = -2;
+        if (FN(contains)(mother_kind, mother_par, p[0], p[1], p[2])) {
+            w = -1;
+            for (int k = 0; k < nd && w < 0; ++k) {
+                R pl[3];
+                FN(local_point)(&v, k, p, offsets ? offs : 0, pl);
+                if (FN(contains)(kinds[k], pars + 5 * k, pl[0], pl[1], pl[2])) w = k;
+            }
+        }
+        where[i] = w;
+    }
+}

@@ -280,7 +280,7 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             std::memcpy(dr.rot, d.placements[k].rot, sizeof dr.rot);
             std::memcpy(dr.tr, d.placements[k].tr, sizeof dr.tr);
             dau.push_back(dr);
-            cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2});
+            cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2, std::sqrt(dr.cull_r2), 0.0});
         }
     }
     geo_geometry *g = new (std::nothrow) geo_geometry();
@@ -404,6 +404,45 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
                                    nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, g->d_partial,
                                    nd > 0 ? g_off : nullptr, g->cull, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return GEO_OK;
+}
+
+namespace {
+
+int point_call_checks(const geo_geometry *g, int32_t volume, const geo_tracks &t, const double *offsets,
+                      const void *out, size_t out_align) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (volume < 0 || volume >= g->nvol) return fail(GEO_ERR_INVALID_ARG, "volume %d out of range", volume);
+    int rc = check_tracks(t, false, "points");
+    if (rc) return rc;
+    if (t.n == 0) return GEO_OK;
+    if ((rc = check_out(out, out_align, "out")) || (rc = check_opt(offsets, 8, "offsets"))) return rc;
+    return check_device(g);
+}
+
+}  // namespace
+
+int geo_navigate_safety(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                        double *safety, hipStream_t stream) {
+    int rc = point_call_checks(g, volume, t, offsets, safety, 8);
+    if (rc || t.n == 0) return rc;
+    const int first = g->h_vols[volume].first;
+    hipError_t e = launch_nav_safety(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
+                                     g->d_cull ? g->d_cull + first : nullptr, to_dev(t),
+                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, safety, g->cull, stream);
+    if (e != hipSuccess) return hip_fail(e, "safety launch");
+    return GEO_OK;
+}
+
+int geo_locate(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets, int32_t *where,
+               hipStream_t stream) {
+    int rc = point_call_checks(g, volume, t, offsets, where, 4);
+    if (rc || t.n == 0) return rc;
+    const int first = g->h_vols[volume].first;
+    hipError_t e = launch_nav_locate(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
+                                     g->d_cull ? g->d_cull + first : nullptr, to_dev(t),
+                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, where, g->cull, stream);
+    if (e != hipSuccess) return hip_fail(e, "locate launch");
     return GEO_OK;
 }
 

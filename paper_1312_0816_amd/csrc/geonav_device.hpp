@@ -49,12 +49,15 @@ static_assert(sizeof(DaughterRec) == 288, "DaughterRec layout");
 
 // Culling record of a daughter, in its own compact array (32 B, so the
 // records of a whole volume stay in the scalar cache during the daughter
-// loop): the centre of the bounding sphere in the mother frame (T) and the
-// squared culling radius.
+// loop): the centre of the bounding sphere in the mother frame (T), the
+// culling radius (bounding radius enlarged by 1e-6 relative + 1e-6) and its
+// square.
 struct alignas(16) CullRec {
     double tx, ty, tz, r2;
+    double r;    // the enlarged radius itself
+    double pad;
 };
-static_assert(sizeof(CullRec) == 32, "CullRec layout");
+static_assert(sizeof(CullRec) == 48, "CullRec layout");
 
 struct alignas(16) VolumeRec {
     ShapeRec mother;
@@ -532,6 +535,77 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
         hit = better ? k : hit;
         if (TRACK_SURF) bsid = better ? sid : bsid;
     }
+}
+
+// ------------------------------------------ navigator safety and locate
+// The navigator's other two per-track tasks (section 3). With CULL, a
+// daughter is skipped by the whole wavefront when its bounding sphere (the
+// culling radius r, enlarged as above) is too far to matter for every lane:
+// for the safety when |w| >= best + r (its Safety is at least |w| - r, so it
+// cannot lower the minimum), for localisation when |w| > r (the point is
+// outside the sphere, hence outside the daughter). Results are identical to
+// evaluating every daughter.
+template <bool HAS_OFFS, bool CULL>
+__device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                             const CullRec *__restrict__ cul,
+                                             const double *__restrict__ offs, double x, double y,
+                                             double z) {
+    double best = any_safety(v.mother, x, y, z);
+    const int nd = v.nd;
+    for (int k = 0; k < nd; ++k) {
+        const CullRec &Q = cul[k];
+        double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
+        if (HAS_OFFS) {
+            wx -= offs[3 * k + 0];
+            wy -= offs[3 * k + 1];
+            wz -= offs[3 * k + 2];
+        }
+        if (CULL) {
+            const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
+            const double reach = best + Q.r;
+            if (__ballot(ww < reach * reach) == 0) continue;
+        }
+        const DaughterRec &D = dau[k];
+        const double *R = D.rot;
+        const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+        const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+        const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+        best = fmin(best, any_safety(D.shape, lx, ly, lz));
+    }
+    return best;
+}
+
+// Daughter holding the point (lowest index), -1 for the mother's own part,
+// -2 outside the mother.
+template <bool HAS_OFFS, bool CULL>
+__device__ __forceinline__ int nav_locate(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                          const CullRec *__restrict__ cul,
+                                          const double *__restrict__ offs, double x, double y,
+                                          double z) {
+    int where = any_contains(v.mother, x, y, z) ? -1 : -2;
+    const int nd = v.nd;
+    for (int k = 0; k < nd; ++k) {
+        if (__ballot(where == -1) == 0) break;  // every lane placed
+        const CullRec &Q = cul[k];
+        double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
+        if (HAS_OFFS) {
+            wx -= offs[3 * k + 0];
+            wy -= offs[3 * k + 1];
+            wz -= offs[3 * k + 2];
+        }
+        if (CULL) {
+            const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
+            if (__ballot(where == -1 && ww <= Q.r2) == 0) continue;
+        }
+        const DaughterRec &D = dau[k];
+        const double *R = D.rot;
+        const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+        const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+        const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+        const bool in = any_contains(D.shape, lx, ly, lz);
+        where = (where == -1 && in) ? k : where;
+    }
+    return where;
 }
 
 }  // namespace gn

@@ -18,6 +18,13 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
                              const TracksDev &t, const double *offs, double *step, int32_t *hit,
                              double *hitpt, bool cull, hipStream_t st);
 
+hipError_t launch_nav_safety(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
+                             const TracksDev &t, const double *offs, double *out, bool cull,
+                             hipStream_t st);
+hipError_t launch_nav_locate(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
+                             const TracksDev &t, const double *offs, int32_t *out, bool cull,
+                             hipStream_t st);
+
 // Tile queues of the persistent batched kernel: one per XCD, cursors 256 B
 // apart.
 constexpr int kQueues = 8;

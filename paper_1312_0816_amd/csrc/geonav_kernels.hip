@@ -4,6 +4,8 @@
 //                    streaming, one lane per track, HBM-bound.
 //  k_nav_basket      the simple navigator (section 3, Fig. 1b) over one
 //                    basket; FP64-ALU-bound (every lane walks every daughter).
+//  k_nav_safety      the navigator's isotropic safety (section 3) per point;
+//  k_nav_locate      the daughter holding each point (localization);
 //  k_nav_persistent  the same per-track navigator over many baskets of many
 //                    volumes in one launch: wavefronts pull tiles of one
 //                    volume from a global cursor (largest cost first).
@@ -120,6 +122,59 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
     const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
     if (cull) launch_basket_variant<true>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st);
     else launch_basket_variant<false>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------- safety and locate
+template <bool HAS_OFFS, bool CULL>
+__global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restrict__ vol,
+                                                       const DaughterRec *__restrict__ dau,
+                                                       const CullRec *__restrict__ cul, TracksDev t,
+                                                       const double *__restrict__ offs,
+                                                       double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= t.n) return;
+    out[i] = nav_safety<HAS_OFFS, CULL>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+}
+
+template <bool HAS_OFFS, bool CULL>
+__global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restrict__ vol,
+                                                       const DaughterRec *__restrict__ dau,
+                                                       const CullRec *__restrict__ cul, TracksDev t,
+                                                       const double *__restrict__ offs,
+                                                       int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= t.n) return;
+    out[i] = nav_locate<HAS_OFFS, CULL>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+}
+
+hipError_t launch_nav_safety(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
+                             const TracksDev &t, const double *offs, double *out, bool cull,
+                             hipStream_t st) {
+    if (t.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
+    if (offs) {
+        if (cull) hipLaunchKernelGGL((k_nav_safety<true, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+        else hipLaunchKernelGGL((k_nav_safety<true, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+    } else {
+        if (cull) hipLaunchKernelGGL((k_nav_safety<false, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+        else hipLaunchKernelGGL((k_nav_safety<false, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nav_locate(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
+                             const TracksDev &t, const double *offs, int32_t *out, bool cull,
+                             hipStream_t st) {
+    if (t.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
+    if (offs) {
+        if (cull) hipLaunchKernelGGL((k_nav_locate<true, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+        else hipLaunchKernelGGL((k_nav_locate<true, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+    } else {
+        if (cull) hipLaunchKernelGGL((k_nav_locate<false, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+        else hipLaunchKernelGGL((k_nav_locate<false, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
+    }
     return hipGetLastError();
 }
 

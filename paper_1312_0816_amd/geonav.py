@@ -54,7 +54,8 @@ class GeoBasket(C.Structure):
 EXPORTS = ("geo_geometry_create", "geo_geometry_destroy", "geo_shape_query",
            "geo_navigate_basket", "geo_navigate_batched", "geo_navigate_backward",
            "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_set_culling",
-           "geo_get_culling", "geo_navigate_batched_census", "geo_strerror")
+           "geo_get_culling", "geo_navigate_batched_census", "geo_navigate_safety",
+           "geo_locate", "geo_strerror")
 
 _lib = None
 
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH):
     lib.geo_get_launch_config.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     lib.geo_set_launch_config.argtypes = [P, I32, I32]
     lib.geo_set_culling.argtypes = [P, I32]
+    lib.geo_navigate_safety.argtypes = [P, I32, GeoTracks, P, P, P]
+    lib.geo_locate.argtypes = [P, I32, GeoTracks, P, P, P]
     lib.geo_navigate_batched_census.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P, P,
                                                 C.POINTER(C.c_uint64), P]
     lib.geo_get_culling.argtypes = [P, C.POINTER(I32)]
@@ -263,6 +266,28 @@ def geo_navigate_basket(g: Geometry, volume: int, o: torch.Tensor, d: torch.Tens
     _check(g._lib.geo_navigate_basket(g.handle, int(volume), t, _ptr(offsets), _ptr(step), _ptr(hit),
                                       _ptr(hp), _stream(stream)))
     return (step, hit, hp) if hitpt else (step, hit)
+
+
+def geo_navigate_safety(g: Geometry, volume: int, points: torch.Tensor,
+                        offsets: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Isotropic safety of the navigator for (3, n) or (6, n) points."""
+    t = tracks_struct(points)
+    if offsets is not None:
+        _need(offsets, "offsets", (g.nd[volume], 3))
+    out = torch.empty(t.n, dtype=torch.float64, device=points.device)
+    _check(g._lib.geo_navigate_safety(g.handle, int(volume), t, _ptr(offsets), _ptr(out), _stream(stream)))
+    return out
+
+
+def geo_locate(g: Geometry, volume: int, points: torch.Tensor, offsets: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """Daughter index holding each point, -1 (mother only) or -2 (outside)."""
+    t = tracks_struct(points)
+    if offsets is not None:
+        _need(offsets, "offsets", (g.nd[volume], 3))
+    out = torch.empty(t.n, dtype=torch.int32, device=points.device)
+    _check(g._lib.geo_locate(g.handle, int(volume), t, _ptr(offsets), _ptr(out), _stream(stream)))
+    return out
 
 
 def _baskets(volume, offset, n):

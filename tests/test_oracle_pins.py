@@ -427,3 +427,59 @@ def test_paper_toy_detector_is_valid(orc):
     for k in range(vol.nd):
         q = to_local(vol, k, t[:3])
         assert not orc.contains(int(vol.kinds[k]), vol.pars[k], np.concatenate([q, np.zeros_like(q)])).any()
+
+
+# ------------------------------------------- navigator safety and locate
+
+def test_navigator_safety_is_min_over_directions(orc):
+    """The navigator's isotropic safety at a point of the mother's own part is
+    the distance to the nearest boundary, i.e. the minimum over directions of
+    the navigator step: a lower bound for every direction, attained after
+    refinement around the best direction."""
+    vol, t = W.toy_detector_c2(n=60, seed=1234)
+    saf = orc.navigate_safety(vol, t)
+    P = t.shape[1]
+    pts = t[:3]
+
+    def steps(dirs):                           # (3, P, m) -> (P, m)
+        m = dirs.shape[2]
+        tt = np.concatenate([np.repeat(pts[:, :, None], m, axis=2), dirs], axis=0).reshape(6, -1)
+        return orc.navigate(vol, tt)[0].reshape(P, m)
+
+    base = fib_dirs(3000)
+    st = steps(np.repeat(base[:, None, :], P, axis=1))
+    assert np.all(st >= saf[:, None] - 1e-12 * np.maximum(saf[:, None], 1))
+    bi = np.argmin(st, axis=1)
+    best_d, best_v = base[:, bi], st[np.arange(P), bi]
+    rng = np.random.default_rng(2)
+    ang = 0.06
+    for _ in range(14):
+        cand = best_d[:, :, None] + rng.normal(size=(3, P, 300)) * ang
+        cand /= np.linalg.norm(cand, axis=0, keepdims=True)
+        v = steps(cand)
+        assert np.all(v >= saf[:, None] - 1e-12 * np.maximum(saf[:, None], 1))
+        j = np.argmin(v, axis=1)
+        better = v[np.arange(P), j] < best_v
+        best_v = np.where(better, v[np.arange(P), j], best_v)
+        best_d = np.where(better[None, :], cand[:, np.arange(P), j], best_d)
+        ang *= 0.6
+    err = (best_v - saf) / np.maximum(saf, 1e-6)
+    assert np.quantile(err, 0.95) < 1e-4 and err.max() < 2e-3, np.sort(err)[-5:]
+
+
+def test_locate_constructed_points(orc):
+    """Points drawn inside daughter k by construction are located in k;
+    generated tracks (mother's own part) give -1; points outside the mother
+    give -2."""
+    vol = W.toy_detector_volume()
+    rng = np.random.default_rng(9)
+    for k in range(vol.nd):
+        q = np.stack(W._sample_in_shape(rng, int(vol.kinds[k]), vol.pars[k], 500))
+        p = vol.rots[k].reshape(3, 3) @ q + vol.trs[k][:, None]
+        saf = orc.navigate_safety(vol, p)
+        w = orc.locate(vol, p)
+        assert np.all((w == k) | (saf < 1e-9))
+    t = W.tracks_in_mother(np.random.default_rng(5), vol, 5000)
+    assert np.all(orc.locate(vol, t) == -1)
+    far = rng.uniform(201.0, 400.0, (3, 100)) * rng.choice([-1.0, 1.0], (3, 100))
+    assert np.all(orc.locate(vol, far) == -2)
