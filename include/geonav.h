@@ -63,7 +63,7 @@ typedef struct {
 typedef struct {
     int32_t kind; /* GEO_BOX, GEO_TUBE or GEO_CONE */
     int32_t _pad;
-    double par[5];
+    double par[7];
 } geo_shape;
 
 /* Placement of a daughter in its mother (the coordinate transformations of

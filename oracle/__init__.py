@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle_body.h")]
 
-BOX, TUBE, CONE = 0, 1, 2
+BOX, TUBE, CONE, TUBS, CONS = 0, 1, 2, 3, 4
 CONTAINS, SAFETY, DIST_IN, DIST_OUT = 0, 1, 2, 3
 BIG = 1e30
 
@@ -80,6 +80,17 @@ def _f64(a, shape=None):
     return a
 
 
+NPAR = 7
+
+
+def _par7(par):
+    """Shape parameters padded with zeros to the 7 the library reads."""
+    p = np.zeros(NPAR)
+    v = np.asarray(par, np.float64).reshape(-1)
+    p[:v.size] = v
+    return p
+
+
 def _tracks(t):
     t = _f64(t)
     if t.ndim != 2 or t.shape[0] not in (3, 6):
@@ -94,7 +105,7 @@ def shape_query(kind: int, par, query: int, tracks, prec: str = "d"):
     lib = _load()
     t = _tracks(tracks)
     n = t.shape[1]
-    par = _f64(par, (5,))
+    par = _par7(par)
     vals = np.zeros(n, np.float64)
     ins = np.zeros(n, np.uint8)
     rows = [t[i] for i in range(6)]

@@ -11,8 +11,17 @@
 
 /* ---------------------------------------------------------------- Contains
  * Closed-set membership test ("inside/outside checks", section 3.1).      */
+static int FN(in_wedge)(R phi1, R dphi, R x, R y);
+static int FN(segment)(int kind, const double *par, int *base, R *phi1, R *dphi);
+
 static int FN(contains)(int kind, const double *par, R x, R y, R z)
 {
+    int base;
+    R phi1, dphi;
+    if (FN(segment)(kind, par, &base, &phi1, &dphi))
+        return FN(contains)(base, par, x, y, z) && FN(in_wedge)(phi1, dphi, x, y);
+    if (kind == OR_TUBS || kind == OR_CONS)      /* uncut: the base solid */
+        return FN(contains)(kind == OR_TUBS ? OR_TUBE : OR_CONE, par, x, y, z);
     if (kind == OR_BOX)
         return fabs(x) <= (R)par[0] && fabs(y) <= (R)par[1] && fabs(z) <= (R)par[2];
     if (kind == OR_TUBE) {
@@ -29,6 +38,31 @@ static int FN(contains)(int kind, const double *par, R x, R y, R z)
         return r >= rin && r <= rout;
     }
     return -1;
+}
+
+/* -------------------------------------------------------------- Segments
+ * The segmented tube and cone (section 3.1 lists the shapes "with their
+ * segmented forms"): the base solid of revolution cut to the azimuth range
+ * [phi1, phi1 + dphi], the z axis included. The leading parameters are the
+ * base kind's (TUBS: rmin rmax dz phi1 dphi; CONS: dz rmin1 rmax1 rmin2 rmax2
+ * phi1 dphi), angles in radians. dphi at or above 2 pi (as a double) leaves
+ * the base uncut. Returns 1 for a cut segment, with the base kind.          */
+static int FN(segment)(int kind, const double *par, int *base, R *phi1, R *dphi)
+{
+    if (kind == OR_TUBS) { *base = OR_TUBE; *phi1 = par[3]; *dphi = par[4]; }
+    else if (kind == OR_CONS) { *base = OR_CONE; *phi1 = par[5]; *dphi = par[6]; }
+    else return 0;
+    return *dphi < (R)OR_FULL_TURN;
+}
+
+/* Azimuth of (x, y) in the closed range [phi1, phi1 + dphi] modulo 2 pi;
+ * the axis has every azimuth. */
+static int FN(in_wedge)(R phi1, R dphi, R x, R y)
+{
+    if (x == 0 && y == 0) return 1;
+    R a = atan2(y, x) - phi1;
+    a -= (R)OR_TWO_PI * floor(a / (R)OR_TWO_PI);   /* into [0, 2 pi] */
+    return a <= dphi;
 }
 
 /* ------------------------------------------------------------------ Safety
@@ -51,8 +85,74 @@ static R FN(seg_dist)(R u, R v, R u0, R v0, R u1, R v1)
     return sqrt(du * du + dv * dv);
 }
 
+/* Profile quadrilateral of a tube or cone in its (r, z) half-plane:
+ *   A(rin1, -dz) B(rout1, -dz) C(rout2, +dz) D(rin2, +dz). */
+static int FN(profile)(int kind, const double *par, R *rin1, R *rout1, R *rin2, R *rout2, R *dz)
+{
+    if (kind == OR_TUBE || kind == OR_TUBS) {
+        *rin1 = *rin2 = par[0];
+        *rout1 = *rout2 = par[1];
+        *dz = par[2];
+        return 1;
+    }
+    if (kind == OR_CONE || kind == OR_CONS) {
+        *dz = par[0];
+        *rin1 = par[1]; *rout1 = par[2];
+        *rin2 = par[3]; *rout2 = par[4];
+        return 1;
+    }
+    return 0;
+}
+
+/* Distance from (u, z) to the closed quadrilateral (0 inside or on it). */
+static R FN(quad_dist)(R u, R z, R rin1, R rout1, R rin2, R rout2, R dz)
+{
+    if (fabs(z) <= dz) {
+        R f = (z + dz) / (2 * dz);
+        if (u >= rin1 + (rin2 - rin1) * f && u <= rout1 + (rout2 - rout1) * f) return 0;
+    }
+    R best = FN(seg_dist)(u, z, rin1, -dz, rout1, -dz);
+    R s = FN(seg_dist)(u, z, rout1, -dz, rout2, dz);
+    if (s < best) best = s;
+    s = FN(seg_dist)(u, z, rout2, dz, rin2, dz);
+    if (s < best) best = s;
+    s = FN(seg_dist)(u, z, rin2, dz, rin1, -dz);
+    if (s < best) best = s;
+    return best;
+}
+
+/* Distance from p to the flat face of a segment at azimuth phi: the profile
+ * quadrilateral laid in the half-plane at that azimuth. With u the
+ * coordinate along the half-plane's direction (cos phi, sin phi, 0) and v the
+ * distance from its plane, it is sqrt(v^2 + dist((u, z), quadrilateral)^2). */
+static R FN(face_dist)(int kind, const double *par, R phi, R x, R y, R z)
+{
+    R rin1 = 0, rout1 = 0, rin2 = 0, rout2 = 0, dz = 0;
+    FN(profile)(kind, par, &rin1, &rout1, &rin2, &rout2, &dz);
+    R c = cos(phi), sn = sin(phi);
+    R u = c * x + sn * y, v = -sn * x + c * y;
+    R q = FN(quad_dist)(u, z, rin1, rout1, rin2, rout2, dz);
+    return sqrt(v * v + q * q);
+}
+
 static R FN(safety)(int kind, const double *par, R x, R y, R z)
 {
+    int base;
+    R phi1, dphi;
+    if (FN(segment)(kind, par, &base, &phi1, &dphi)) {
+        /* The boundary is the base's surfaces within the azimuth range plus
+         * the two faces. For p in the range the nearest point of the base's
+         * surfaces has p's own azimuth, so it is the base's Safety; for p
+         * outside the range it lies on the edge of a face (the face distance
+         * covers it). */
+        R best = INFINITY;
+        if (FN(in_wedge)(phi1, dphi, x, y)) best = FN(safety)(base, par, x, y, z);
+        R s = FN(face_dist)(kind, par, phi1, x, y, z);
+        if (s < best) best = s;
+        s = FN(face_dist)(kind, par, phi1 + dphi, x, y, z);
+        if (s < best) best = s;
+        return best;
+    }
     if (kind == OR_BOX) {
         R ax = fabs(x), ay = fabs(y), az = fabs(z);
         R dx = par[0], dy = par[1], dz = par[2];
@@ -74,17 +174,7 @@ static R FN(safety)(int kind, const double *par, R x, R y, R z)
      *   A(rin1, -dz) B(rout1, -dz) C(rout2, +dz) D(rin2, +dz).
      * An edge on the axis (r = 0) bounds no surface and is skipped. */
     R rin1, rout1, rin2, rout2, dz;
-    if (kind == OR_TUBE) {
-        rin1 = rin2 = par[0];
-        rout1 = rout2 = par[1];
-        dz = par[2];
-    } else if (kind == OR_CONE) {
-        dz = par[0];
-        rin1 = par[1]; rout1 = par[2];
-        rin2 = par[3]; rout2 = par[4];
-    } else {
-        return -1;
-    }
+    if (!FN(profile)(kind, par, &rin1, &rout1, &rin2, &rout2, &dz)) return -1;
     R r = sqrt(x * x + y * y);
     R best = FN(seg_dist)(r, z, rin1, -dz, rout1, -dz);              /* bottom AB */
     R s = FN(seg_dist)(r, z, rout1, -dz, rout2, dz);                  /* outer  BC */
@@ -123,20 +213,17 @@ static int FN(in_nappe)(R a, R b, const R *p, const R *d, R t)
     return sqrt(x * x + y * y) <= a + b * z;
 }
 
-/* Line intersected with the convex solid N(a, b): a single closed interval
- * (maybe unbounded) or empty (returns 0). On the boundary of N the squared
- * form f(t) = (a + b z(t))^2 - (x(t)^2 + y(t)^2) vanishes, so the line's
- * crossings are among the real roots of this quadratic; membership is then
- * decided by testing one interior point of every piece between roots (this
- * test also rejects the mirror nappe a + b z < 0). */
-static int FN(line_nappe)(R a, R b, const R *p, const R *d, R *lo, R *hi)
+/* On the boundary of N the squared form
+ * f(t) = (a + b z(t))^2 - (x(t)^2 + y(t)^2) vanishes, so the line's crossings
+ * of the nappe are among the real roots of this quadratic (ascending; the
+ * mirror nappe a + b z < 0 contributes roots too). */
+static int FN(nappe_roots)(R a, R b, const R *p, const R *d, R *roots)
 {
     R w0 = a + b * p[2];
     R wz = b * d[2];
     R qa = wz * wz - (d[0] * d[0] + d[1] * d[1]);
     R qb = 2 * (w0 * wz - (p[0] * d[0] + p[1] * d[1]));
     R qc = w0 * w0 - (p[0] * p[0] + p[1] * p[1]);
-    R roots[2];
     int nr = 0;
     if (qa == 0) {
         if (qb != 0) roots[nr++] = -qc / qb;
@@ -153,6 +240,17 @@ static int FN(line_nappe)(R a, R b, const R *p, const R *d, R *lo, R *hi)
             nr = 2;
         }
     }
+    return nr;
+}
+
+/* Line intersected with the convex solid N(a, b): a single closed interval
+ * (maybe unbounded) or empty (returns 0). Membership is decided by testing
+ * one interior point of every piece between the roots (which also rejects
+ * the mirror nappe). */
+static int FN(line_nappe)(R a, R b, const R *p, const R *d, R *lo, R *hi)
+{
+    R roots[2];
+    int nr = FN(nappe_roots)(a, b, p, d, roots);
     if (nr == 0) {
         if (FN(in_nappe)(a, b, p, d, 0)) { *lo = -INFINITY; *hi = INFINITY; return 1; }
         return 0;
@@ -189,13 +287,23 @@ static int FN(cap)(R *lo, R *hi, R a, R b)
     return *lo <= *hi;
 }
 
-/* Line intersected with the shape: up to two closed intervals, ascending.
+static int FN(line_segment)(int kind, const double *par, const R *p, const R *d, FN(ival) *out);
+
+/* Line intersected with the shape: closed intervals, ascending (at most
+ * OR_MAX_IVAL).
  * Box: the three slabs intersected (Kay-Kajiya).
  * Tube and cone: (z-slab  and  outer nappe solid)  minus  the open inner
- * nappe solid {r < rin(z)}, which is empty when both inner radii are 0.   */
+ * nappe solid {r < rin(z)}, which is empty when both inner radii are 0.
+ * Segments: see line_segment.                                              */
 static int FN(line_shape)(int kind, const double *par, const R *p, const R *d, FN(ival) *out)
 {
     R lo, hi, a, b;
+    int base;
+    R phi1, dphi;
+    if (FN(segment)(kind, par, &base, &phi1, &dphi))
+        return FN(line_segment)(kind, par, p, d, out);
+    if (kind == OR_TUBS || kind == OR_CONS)      /* uncut: the base solid */
+        kind = kind == OR_TUBS ? OR_TUBE : OR_CONE;
     if (kind == OR_BOX) {
         lo = -INFINITY; hi = INFINITY;
         for (int i = 0; i < 3; ++i) {
@@ -235,6 +343,70 @@ static int FN(line_shape)(int kind, const double *par, const R *p, const R *d, F
     return n;
 }
 
+/* A segment's boundary lies on the z planes, the outer and inner nappes and
+ * the two planes through the axis at azimuths phi1 and phi1 + dphi, so the
+ * line's intervals in the solid end at crossings of these surfaces. Split
+ * the line at every crossing, test membership (Contains) at one interior
+ * point of each open piece and at each crossing, and join neighbouring
+ * pieces that belong. Membership is constant on a piece, and the solid is
+ * closed: a crossing next to a piece that belongs belongs too. Crossings of
+ * a whole plane or of a mirror nappe only split a piece needlessly.       */
+static int FN(line_segment)(int kind, const double *par, const R *p, const R *d, FN(ival) *out)
+{
+    int base;
+    R phi1 = 0, dphi = 0, rin1 = 0, rout1 = 0, rin2 = 0, rout2 = 0, dz = 0;
+    FN(segment)(kind, par, &base, &phi1, &dphi);
+    FN(profile)(kind, par, &rin1, &rout1, &rin2, &rout2, &dz);
+    R t[8];
+    int m = 0;
+    if (d[2] != 0) {
+        t[m++] = (-dz - p[2]) / d[2];
+        t[m++] = (dz - p[2]) / d[2];
+    }
+    /* nappes r = a + b z through the profile's slanted edges */
+    R ao = (rout1 + rout2) / 2, bo = (rout2 - rout1) / (2 * dz);
+    R ai = (rin1 + rin2) / 2, bi = (rin2 - rin1) / (2 * dz);
+    m += FN(nappe_roots)(ao, bo, p, d, t + m);
+    if (!(rin1 == 0 && rin2 == 0)) m += FN(nappe_roots)(ai, bi, p, d, t + m);
+    for (int i = 0; i < 2; ++i) {
+        R ph = i == 0 ? phi1 : phi1 + dphi;
+        R nx = -sin(ph), ny = cos(ph);             /* normal of the plane at ph */
+        R nd = nx * d[0] + ny * d[1];
+        if (nd != 0) t[m++] = -(nx * p[0] + ny * p[1]) / nd;
+    }
+    /* sort ascending, drop repeats */
+    for (int i = 1; i < m; ++i)
+        for (int j = i; j > 0 && t[j] < t[j - 1]; --j) { R x = t[j]; t[j] = t[j - 1]; t[j - 1] = x; }
+    int u = 0;
+    for (int i = 0; i < m; ++i)
+        if (u == 0 || t[i] != t[u - 1]) t[u++] = t[i];
+    m = u;
+#define OR_IN_AT(tt) FN(contains)(kind, par, p[0] + (tt) * d[0], p[1] + (tt) * d[1], p[2] + (tt) * d[2])
+    if (m == 0) {
+        if (!OR_IN_AT(0)) return 0;
+        out[0].lo = -INFINITY; out[0].hi = INFINITY;
+        return 1;
+    }
+    /* open pieces 0..m (piece i lies between t[i-1] and t[i]) */
+    int piece[9];
+    piece[0] = OR_IN_AT(t[0] - (1 + fabs(t[0])));
+    for (int i = 1; i < m; ++i) piece[i] = OR_IN_AT(t[i - 1] + (t[i] - t[i - 1]) / 2);
+    piece[m] = OR_IN_AT(t[m - 1] + (1 + fabs(t[m - 1])));
+    /* walk the pieces and crossings in order; every run of members holds a
+     * crossing, so there are at most m runs */
+    int n = 0, open = piece[0];
+    if (open) out[0].lo = -INFINITY;
+    for (int i = 0; i < m; ++i) {                 /* crossing i, then piece i + 1 */
+        int at = open || piece[i + 1] || OR_IN_AT(t[i]);
+        if (at && !open) out[n].lo = t[i];
+        open = piece[i + 1];
+        if (at && !open) out[n++].hi = t[i];
+    }
+    if (open) out[n++].hi = INFINITY;
+#undef OR_IN_AT
+    return n;
+}
+
 /* -------------------------------------------- DistFromOutside / Inside
  * Distance along the line of flight to enter the shape / to leave it
  * (section 3.1). A point already inside has DistFromOutside 0; a point
@@ -242,7 +414,7 @@ static int FN(line_shape)(int kind, const double *par, const R *p, const R *d, F
 static R FN(dist_out)(int kind, const double *par, const R *p, const R *d)
 {
     if (FN(contains)(kind, par, p[0], p[1], p[2])) return 0;
-    FN(ival) iv[2];
+    FN(ival) iv[OR_MAX_IVAL];
     int n = FN(line_shape)(kind, par, p, d, iv);
     R best = OR_BIG;
     for (int i = 0; i < n; ++i) {
@@ -256,7 +428,7 @@ static R FN(dist_out)(int kind, const double *par, const R *p, const R *d)
 static R FN(dist_in)(int kind, const double *par, const R *p, const R *d)
 {
     if (!FN(contains)(kind, par, p[0], p[1], p[2])) return 0;
-    FN(ival) iv[2];
+    FN(ival) iv[OR_MAX_IVAL];
     int n = FN(line_shape)(kind, par, p, d, iv);
     for (int i = 0; i < n; ++i)
         if (iv[i].lo <= 0 && iv[i].hi >= 0) return iv[i].hi < OR_BIG ? iv[i].hi : OR_BIG;
@@ -293,10 +465,10 @@ void FN(or_shape_query)(int kind, const double *par, int query, int64_t n,
  * Also returns the gap between the two smallest candidates.              */
 typedef struct {
     int mother_kind;
-    const double *mother_par;     /* 5 */
+    const double *mother_par;     /* OR_NPAR */
     int nd;
     const int32_t *kinds;         /* nd */
-    const double *pars;           /* nd x 5 */
+    const double *pars;           /* nd x OR_NPAR */
     const double *rots;           /* nd x 9, row-major R */
     const double *trs;            /* nd x 3 */
 } FN(vol);
@@ -317,7 +489,7 @@ static R FN(navigate1)(const FN(vol) *v, const R *p, const R *d, const R *offs,
             pl[j] = (R)rm[0 + j] * w[0] + (R)rm[3 + j] * w[1] + (R)rm[6 + j] * w[2];
             dl[j] = (R)rm[0 + j] * d[0] + (R)rm[3 + j] * d[1] + (R)rm[6 + j] * d[2];
         }
-        R s = FN(dist_out)(v->kinds[k], v->pars + 5 * k, pl, dl);
+        R s = FN(dist_out)(v->kinds[k], v->pars + OR_NPAR * k, pl, dl);
         if (s < best) { second = best; best = s; h = k; }
         else if (s < second) second = s;
     }
@@ -447,7 +619,7 @@ void FN(or_navigate_safety)(int mother_kind, const double *mother_par, int nd,
         for (int k = 0; k < nd; ++k) {
             R pl[3];
             FN(local_point)(&v, k, p, offsets ? offs : 0, pl);
-            R s = FN(safety)(kinds[k], pars + 5 * k, pl[0], pl[1], pl[2]);
+            R s = FN(safety)(kinds[k], pars + OR_NPAR * k, pl[0], pl[1], pl[2]);
             if (s < best) best = s;
         }
         safety[i] = (double)best;
@@ -471,7 +643,7 @@ void FN(or_locate)(int mother_kind, const double *mother_par, int nd, const int3
             for (int k = 0; k < nd && w < 0; ++k) {
                 R pl[3];
                 FN(local_point)(&v, k, p, offsets ? offs : 0, pl);
-                if (FN(contains)(kinds[k], pars + 5 * k, pl[0], pl[1], pl[2])) w = k;
+                if (FN(contains)(kinds[k], pars + OR_NPAR * k, pl[0], pl[1], pl[2])) w = k;
             }
         }
         where[i] = w;

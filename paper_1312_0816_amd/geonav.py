@@ -25,6 +25,7 @@ GEO_BOX, GEO_TUBE, GEO_CONE = 0, 1, 2
 GEO_CONTAINS, GEO_SAFETY, GEO_DIST_IN, GEO_DIST_OUT = 0, 1, 2, 3
 GEO_BIG = 1e30
 GEO_MAX_DAUGHTERS = 1024
+NPAR = 7
 
 
 class GeoTracks(C.Structure):
@@ -34,7 +35,16 @@ class GeoTracks(C.Structure):
 
 
 class GeoShape(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("_pad", C.c_int32), ("par", C.c_double * 5)]
+    _fields_ = [("kind", C.c_int32), ("_pad", C.c_int32), ("par", C.c_double * NPAR)]
+
+
+def make_shape(kind: int, par) -> "GeoShape":
+    """GeoShape from a kind and up to NPAR parameters (zero-padded)."""
+    p = [float(v) for v in np.asarray(par, np.float64).reshape(-1)]
+    if len(p) > NPAR:
+        raise ValueError(f"at most {NPAR} shape parameters")
+    p += [0.0] * (NPAR - len(p))
+    return GeoShape(int(kind), 0, (C.c_double * NPAR)(*p))
 
 
 class GeoPlacement(C.Structure):
@@ -162,10 +172,7 @@ def geo_shape_query(kind: int, par, query: int, tracks: torch.Tensor, out: torch
     """One shape query (section 3.1) over every track of a (6, n) or (3, n)
     basket; returns uint8 (Contains) or float64."""
     lib = load_library()
-    par = [float(v) for v in par]
-    if len(par) < 5:
-        par = par + [0.0] * (5 - len(par))
-    shape = GeoShape(int(kind), 0, (C.c_double * 5)(*par))
+    shape = make_shape(kind, par)
     t = tracks_struct(tracks)
     if query in (GEO_DIST_IN, GEO_DIST_OUT) and tracks.shape[0] != 6:
         raise ValueError("distance queries need (6, n) tracks")
@@ -196,11 +203,10 @@ class Geometry:
             sh = (GeoShape * max(nd, 1))()
             pl = (GeoPlacement * max(nd, 1))()
             for k in range(nd):
-                sh[k] = GeoShape(int(v.kinds[k]), 0, (C.c_double * 5)(*map(float, v.pars[k])))
+                sh[k] = make_shape(v.kinds[k], v.pars[k])
                 pl[k] = GeoPlacement((C.c_double * 9)(*map(float, np.asarray(v.rots[k]).reshape(9))),
                                      (C.c_double * 3)(*map(float, v.trs[k])))
-            mp = [float(x) for x in v.mother_par] + [0.0] * (5 - len(v.mother_par))
-            descs[i].mother = GeoShape(int(v.mother_kind), 0, (C.c_double * 5)(*mp[:5]))
+            descs[i].mother = make_shape(v.mother_kind, v.mother_par)
             descs[i].ndaughters = nd
             descs[i].daughters = C.cast(sh, C.POINTER(GeoShape))
             descs[i].placements = C.cast(pl, C.POINTER(GeoPlacement))

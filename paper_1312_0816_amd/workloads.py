@@ -27,15 +27,36 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BOX, TUBE, CONE = 0, 1, 2
-KIND_NAMES = {BOX: "box", TUBE: "tube", CONE: "cone"}
+BOX, TUBE, CONE, TUBS, CONS = 0, 1, 2, 3, 4
+KIND_NAMES = {BOX: "box", TUBE: "tube", CONE: "cone", TUBS: "tube segment",
+              CONS: "cone segment"}
+NPAR = 7   # parameters per shape (zero-padded)
 
 # Shape-suite shapes (parameter order as above).
 SUITE_SHAPES = {
     BOX: np.array([10.0, 20.0, 30.0, 0.0, 0.0]),
     TUBE: np.array([5.0, 15.0, 20.0, 0.0, 0.0]),
     CONE: np.array([20.0, 0.0, 10.0, 5.0, 20.0]),
+    # 240-degree tube segment (a non-convex azimuth range) and a 150-degree
+    # cone segment with a hole that closes to 2 at the narrow end
+    TUBS: np.array([5.0, 15.0, 20.0, np.pi / 6, 4 * np.pi / 3]),
+    CONS: np.array([20.0, 2.0, 10.0, 5.0, 20.0, -np.pi / 4, 5 * np.pi / 6]),
 }
+
+# Further segments for the parity tests: narrow, right-angle, half and wide
+# ranges, ranges that wrap through phi = pi, solid (no hole) profiles whose
+# faces meet on the axis, and a range just short of a full turn.
+SEGMENT_VARIANTS = [
+    (TUBS, np.array([0.0, 10.0, 10.0, 0.0, np.pi / 2])),
+    (TUBS, np.array([2.0, 10.0, 5.0, np.pi / 2, 3 * np.pi / 2])),
+    (TUBS, np.array([4.0, 12.0, 8.0, 2.5, 0.3])),
+    (TUBS, np.array([0.0, 12.0, 8.0, -1.0, np.pi])),
+    (TUBS, np.array([3.0, 9.0, 6.0, 0.7, 2 * np.pi - 1e-3])),
+    (CONS, np.array([10.0, 0.0, 10.0, 0.0, 20.0, 0.0, np.pi])),
+    (CONS, np.array([5.0, 2.0, 4.0, 2.0, 4.0, -np.pi / 4, np.pi / 2])),
+    (CONS, np.array([12.0, 0.0, 3.0, 6.0, 14.0, 2.0, 4.0])),
+    (CONS, np.array([12.0, 1.0, 14.0, 0.0, 3.0, -3.0, 1.2])),
+]
 
 MOTHER_HALF = 200.0
 
@@ -57,9 +78,9 @@ class Volume:
     """A logical volume: mother shape plus placed daughters."""
 
     mother_kind: int
-    mother_par: np.ndarray                     # (5,)
+    mother_par: np.ndarray                     # (NPAR,) or shorter, zero-padded
     kinds: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))   # (nd,)
-    pars: np.ndarray = field(default_factory=lambda: np.zeros((0, 5)))       # (nd, 5)
+    pars: np.ndarray = field(default_factory=lambda: np.zeros((0, NPAR)))    # (nd, <= NPAR)
     rots: np.ndarray = field(default_factory=lambda: np.zeros((0, 9)))       # (nd, 9) row-major R
     trs: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))        # (nd, 3) T
     bound_r: np.ndarray = field(default_factory=lambda: np.zeros(0))         # (nd,) generator-side bounding radius
@@ -69,10 +90,16 @@ class Volume:
         return int(self.kinds.shape[0])
 
     def normalized(self) -> "Volume":
-        return Volume(int(self.mother_kind),
-                      np.ascontiguousarray(self.mother_par, np.float64).reshape(5),
+        mp = np.zeros(NPAR)
+        m = np.asarray(self.mother_par, np.float64).reshape(-1)
+        mp[:m.size] = m
+        pr = np.asarray(self.pars, np.float64)
+        pr = pr.reshape(pr.shape[0] if pr.ndim == 2 else 0, -1) if pr.size else np.zeros((0, NPAR))
+        pars = np.zeros((pr.shape[0], NPAR))
+        pars[:, :pr.shape[1]] = pr
+        return Volume(int(self.mother_kind), mp,
                       np.ascontiguousarray(self.kinds, np.int32).reshape(-1),
-                      np.ascontiguousarray(self.pars, np.float64).reshape(-1, 5),
+                      pars,
                       np.ascontiguousarray(self.rots, np.float64).reshape(-1, 9),
                       np.ascontiguousarray(self.trs, np.float64).reshape(-1, 3),
                       np.ascontiguousarray(self.bound_r, np.float64).reshape(-1))
@@ -93,17 +120,18 @@ def box_c0(seed: int = 1000, n: int = 1024):
 
 def _sample_in_shape(rng, kind, par, n):
     """Points uniformly distributed in the shape's volume, by construction
-    (not by a membership test)."""
+    (not by a membership test). Segments draw the azimuth in their range."""
+    par = np.asarray(par, np.float64).reshape(-1)
     if kind == BOX:
         return [rng.uniform(-par[i], par[i], n) for i in range(3)]
-    if kind == TUBE:
+    if kind in (TUBE, TUBS):
         rmin, rmax, dz = par[0], par[1], par[2]
         z = rng.uniform(-dz, dz, n)
         r = np.sqrt(rng.uniform(rmin * rmin, rmax * rmax, n))
-        ph = rng.uniform(0.0, 2.0 * np.pi, n)
+        ph = rng.uniform(0.0, 2.0 * np.pi, n) if kind == TUBE else par[3] + rng.uniform(0.0, par[4], n)
         return [r * np.cos(ph), r * np.sin(ph), z]
-    if kind == CONE:
-        dz, rmin1, rmax1, rmin2, rmax2 = par
+    if kind in (CONE, CONS):
+        dz, rmin1, rmax1, rmin2, rmax2 = par[:5]
         # Radii vary linearly between the end faces; the cross-section area
         # pi (ro^2 - ri^2) sets the z density. Sample z by acceptance against
         # the bound max(rmax1, rmax2)^2, then r^2 uniform in the annulus.
@@ -124,20 +152,21 @@ def _sample_in_shape(rng, kind, par, n):
         ro = rmax1 + (rmax2 - rmax1) * f
         ri = rmin1 + (rmin2 - rmin1) * f
         r = np.sqrt(rng.uniform(ri * ri, ro * ro))
-        ph = rng.uniform(0.0, 2.0 * np.pi, n)
+        ph = rng.uniform(0.0, 2.0 * np.pi, n) if kind == CONE else par[5] + rng.uniform(0.0, par[6], n)
         return [r * np.cos(ph), r * np.sin(ph), z]
     raise ValueError(kind)
 
 
-def shape_suite_c1(kind: int, n: int = 1 << 20, seed: int | None = None):
-    """Shape-suite workload for one shape: half the origins drawn inside the
-    shape, half uniform in the cube of half-size 50 around it (that half is
-    not filtered, so a few percent of it also lands inside), randomly
-    interleaved, isotropic directions. Returns (kind, par, tracks)."""
+def shape_suite_c1(kind: int, n: int = 1 << 20, seed: int | None = None, par=None):
+    """Shape-suite workload for one shape (SUITE_SHAPES[kind] unless `par` is
+    given): half the origins drawn inside the shape, half uniform in the cube
+    of half-size 50 around it (that half is not filtered, so a few percent of
+    it also lands inside), randomly interleaved, isotropic directions.
+    Returns (kind, par, tracks)."""
     if seed is None:
         seed = 1100 + kind
     rng = np.random.default_rng(seed)
-    par = SUITE_SHAPES[kind].copy()
+    par = (SUITE_SHAPES[kind] if par is None else np.asarray(par, np.float64)).copy()
     n_in = n // 2
     n_out = n - n_in
     pin = _sample_in_shape(rng, kind, par, n_in)
@@ -171,7 +200,7 @@ def _draw_daughter(rng, kind):
     with probability 1/4. Returns (par, bounding radius about the centre)."""
     if kind == BOX:
         d = rng.uniform(5.0, 20.0, 3)
-        return np.array([d[0], d[1], d[2], 0.0, 0.0]), float(np.sqrt((d * d).sum()))
+        return np.array([d[0], d[1], d[2], 0.0, 0.0, 0.0, 0.0]), float(np.sqrt((d * d).sum()))
 
     def inner(rmax):
         r = rng.uniform(0.0, 0.75) * rmax
@@ -196,7 +225,7 @@ def _draw_daughter(rng, kind):
 def _place_daughters(rng, centres, cell_half):
     nd = len(centres)
     kinds = np.array([i % 3 for i in range(nd)], np.int32)
-    pars = np.zeros((nd, 5))
+    pars = np.zeros((nd, NPAR))
     rots = np.zeros((nd, 9))
     trs = np.zeros((nd, 3))
     bound = np.zeros(nd)
@@ -205,7 +234,7 @@ def _place_daughters(rng, centres, cell_half):
         ang = rng.uniform(0.0, 1.0, 3) * np.array([2 * np.pi, np.pi, 2 * np.pi])
         jit = cell_half - rb
         assert jit > 0.0
-        pars[i] = par
+        pars[i, :par.size] = par
         rots[i] = euler_zxz(*ang)
         trs[i] = np.asarray(centres[i], float) + rng.uniform(-jit, jit, 3)
         bound[i] = rb

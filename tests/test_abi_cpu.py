@@ -52,7 +52,7 @@ def test_strerror(gv):
 
 def _bad_shape_call(gv, kind, par):
     lib = gv.load_library()
-    s = gv.GeoShape(kind, 0, (C.c_double * 5)(*par))
+    s = gv.make_shape(kind, par)
     t = gv.GeoTracks(None, None, None, None, None, None, 0)
     return lib.geo_shape_query(C.byref(s), 0, t, None, None)
 
@@ -67,7 +67,7 @@ def test_shape_validation_without_device(gv):
     assert _bad_shape_call(gv, 2, [20, 0, 10, 25, 20]) == -1        # rmin2 > rmax2
     assert _bad_shape_call(gv, 0, [np.nan, 1, 1, 0, 0]) == -1
     assert b"rmin" in lib.geo_strerror(_bad_shape_call(gv, 1, [16, 15, 20, 0, 0]))
-    s = gv.GeoShape(0, 0, (C.c_double * 5)(10, 20, 30, 0, 0))
+    s = gv.make_shape(0, [10, 20, 30])
     t = gv.GeoTracks(None, None, None, None, None, None, 5)          # NULL arrays with n > 0
     assert lib.geo_shape_query(C.byref(s), 0, t, None, None) == -1
     t = gv.GeoTracks(None, None, None, None, None, None, -1)

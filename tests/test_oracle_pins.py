@@ -15,6 +15,7 @@ from paper_1312_0816_amd import workloads as W
 from tests.util import BIG, fib_dirs, first_transition, load_closed_forms, rel_err, to_local
 
 CASES = load_closed_forms()
+ALL_KINDS = [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS]
 
 
 def _one(p, d):
@@ -38,11 +39,11 @@ def test_closed_forms(orc, prec):
     assert not bad, bad
 
 
-def _suite(kind, n, seed):
-    return W.shape_suite_c1(kind, n=n, seed=seed)
+def _suite(kind, n, seed, par=None):
+    return W.shape_suite_c1(kind, n=n, seed=seed, par=par)
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+@pytest.mark.parametrize("kind", ALL_KINDS)
 def test_constructed_inside_points_are_contained(orc, kind):
     """The generator draws half the suite inside the shape by construction
     (not by a membership test): Contains must agree except within 1e-9 of
@@ -56,12 +57,16 @@ def test_constructed_inside_points_are_contained(orc, kind):
     assert np.all((c == 1) | (s < 1e-9))
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+@pytest.mark.parametrize("kind", ALL_KINDS)
 def test_safety_is_min_over_directions(orc, kind):
     """Safety(p) = min over unit directions of DistFromInside (p inside) or
     DistFromOutside (p outside): a lower bound for every direction and
     attained along the direction to the nearest boundary point (C3)."""
     _, par, t = _suite(kind, 240, 4242 + kind)
+    _check_safety_variational(orc, kind, par, t)
+
+
+def _check_safety_variational(orc, kind, par, t):
     P = t.shape[1]
     ins = orc.contains(kind, par, t).astype(bool)
     saf = orc.safety(kind, par, t)
@@ -75,38 +80,44 @@ def test_safety_is_min_over_directions(orc, kind):
         return np.where(ins[:, None], din, dout)
 
     base = fib_dirs(4000)
-    dirs = np.repeat(base[:, None, :], P, axis=1)
-    dd = dist(dirs)
+    dd = dist(np.repeat(base[:, None, :], P, axis=1))
     # lower bound over every direction tried
     assert np.all(dd >= saf[:, None] * (1 - 1e-12) - 1e-12)
-    best_i = np.argmin(dd, axis=1)
-    best_d = base[:, best_i]               # (3, P)
-    best_v = dd[np.arange(P), best_i]
+    # local random search from the K best grid directions of each point (a
+    # nearest point on an edge or corner is reached by a thin set of
+    # directions, so one start can settle in the wrong basin)
+    K, m = 8, 100
+    order = np.argsort(dd, axis=1)[:, :K]
+    best_d = base[:, order]                                   # (3, P, K)
+    best_v = np.take_along_axis(dd, order, axis=1)            # (P, K)
     rng = np.random.default_rng(1)
     ang = 0.08
-    for _ in range(14):                     # local refinement around the best
-        m = 400
-        pert = rng.normal(size=(3, P, m)) * ang
-        cand = best_d[:, :, None] + pert
+    for _ in range(20):
+        cand = best_d[:, :, :, None] + rng.normal(size=(3, P, K, m)) * ang
         cand /= np.linalg.norm(cand, axis=0, keepdims=True)
-        v = dist(cand)
-        assert np.all(v >= saf[:, None] * (1 - 1e-12) - 1e-12)
-        j = np.argmin(v, axis=1)
-        better = v[np.arange(P), j] < best_v
-        best_v = np.where(better, v[np.arange(P), j], best_v)
-        best_d = np.where(better[None, :], cand[:, np.arange(P), j], best_d)
-        ang *= 0.6
-    err = (best_v - saf) / np.maximum(saf, 1e-6)
+        v = dist(cand.reshape(3, P, K * m)).reshape(P, K, m)
+        assert np.all(v >= saf[:, None, None] * (1 - 1e-12) - 1e-12)
+        j = np.argmin(v, axis=2)
+        vb = np.take_along_axis(v, j[:, :, None], axis=2)[:, :, 0]
+        db = np.take_along_axis(cand, j[None, :, :, None], axis=3)[..., 0]
+        better = vb < best_v
+        best_v = np.where(better, vb, best_v)
+        best_d = np.where(better[None], db, best_d)
+        ang *= 0.7
+    err = (best_v.min(axis=1) - saf) / np.maximum(saf, 1e-6)
     assert np.all(err >= -1e-12)
-    assert np.quantile(err, 0.99) < 1e-4, np.sort(err)[-5:]
-    assert np.max(err) < 2e-3, np.sort(err)[-5:]
+    assert np.max(err) < 1e-4, np.sort(err)[-5:]
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+@pytest.mark.parametrize("kind", ALL_KINDS)
 def test_distances_match_ray_marching(orc, kind):
     """DistFromOutside / DistFromInside against brute force: march the ray
     with the membership test (step 0.02) and bisect the first change."""
     _, par, t = _suite(kind, 160, 777 + kind)
+    _check_ray_marching(orc, kind, par, t)
+
+
+def _check_ray_marching(orc, kind, par, t):
     ins = orc.contains(kind, par, t).astype(bool)
     dout = orc.dist_out(kind, par, t)
     din = orc.dist_in(kind, par, t)
@@ -118,25 +129,22 @@ def test_distances_match_ray_marching(orc, kind):
     bad = []
     for i in range(t.shape[1]):
         p, d = t[:3, i], t[3:, i]
-        if ins[i]:
-            got = first_transition(pred, p, d, 130.0, 0.02, False)
-            ref = din[i]
-            assert dout[i] == 0.0
-        else:
-            got = first_transition(pred, p, d, 130.0, 0.02, True)
-            ref = dout[i]
-            assert din[i] == 0.0
-        if got is None:
-            if ref == BIG:
-                continue
-            # the coarse march may step over a chord shorter than 0.02:
-            # confirm the oracle's entry with a fine local march
-            got2 = first_transition(pred, p + (ref - 0.01) * d, d, 0.03, 1e-5, True)
-            if got2 is None or abs(ref - 0.01 + got2 - ref) > 1e-9:
-                bad.append((i, None, ref))
+        want = not ins[i]                     # leave from inside, enter from outside
+        got = first_transition(pred, p, d, 130.0, 0.02, want)
+        ref = din[i] if ins[i] else dout[i]
+        assert (dout[i] if ins[i] else din[i]) == 0.0
+        if got is None and ref == BIG:
             continue
-        if abs(got - ref) > 1e-9 * max(1.0, ref):
-            bad.append((i, got, ref))
+        if got is not None and abs(got - ref) <= 1e-9 * max(1.0, ref):
+            continue
+        if ref < BIG and (got is None or ref < got):
+            # the coarse march may step over a chord (or a slot) thinner than
+            # 0.02: confirm the oracle's transition with a fine local march
+            t0 = max(ref - 0.01, 0.0)
+            got2 = first_transition(pred, p + t0 * d, d, 0.03, 1e-5, want)
+            if got2 is not None and abs(t0 + got2 - ref) <= 1e-9 * max(1.0, ref):
+                continue
+        bad.append((i, got, ref))
     assert not bad, bad
 
 
@@ -156,7 +164,7 @@ def test_tube_is_cone_with_equal_radii(orc, prec):
             assert np.all(both_big | (rel_err(b, a) <= 1e-13))
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+@pytest.mark.parametrize("kind", ALL_KINDS)
 def test_direction_scaling(orc, kind):
     """Directions are not renormalised: scaling d by lam scales t by 1/lam (C6)."""
     _, par, t = _suite(kind, 5000, 55 + kind)
@@ -171,7 +179,7 @@ def test_direction_scaling(orc, kind):
             assert np.all(rel_err(b[fin] * lam, a[fin]) <= 1e-13)
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE])
+@pytest.mark.parametrize("kind", ALL_KINDS)
 def test_hit_point_on_surface_and_entry_exit(orc, kind):
     """The entry point p + t d lies on the surface (Safety there ~ 0, C17),
     and leaving from just inside the entry point is consistent."""
@@ -208,13 +216,105 @@ def test_convex_chord_reversibility(orc):
 def test_long_double_rerun_agrees(orc):
     """The double and long-double builds agree to 1e-12 except on a tiny
     fraction of ill-conditioned tracks (C15)."""
-    for kind in (W.BOX, W.TUBE, W.CONE):
+    for kind in ALL_KINDS:
         _, par, t = _suite(kind, 50000, 123 + kind)
         for q in (orc.SAFETY, orc.DIST_IN, orc.DIST_OUT):
             a = orc.shape_query(kind, par, q, t, "d")
             b = orc.shape_query(kind, par, q, t, "ld")
             e = rel_err(a, b)
             assert np.mean(e > 1e-12) < 1e-3
+
+
+# -------------------------------------------------------------- segments
+
+def _base(kind, par):
+    return (W.TUBE if kind == W.TUBS else W.CONE), np.asarray(par, float)[:5]
+
+
+def _with_azimuth(p, phi):
+    r = np.hypot(p[0], p[1])
+    return np.stack([r * np.cos(phi), r * np.sin(phi), p[2]])
+
+
+@pytest.mark.parametrize("v", range(len(W.SEGMENT_VARIANTS)))
+def test_segment_membership_by_construction(orc, v):
+    """Points of the base solid turned to an azimuth inside the range are
+    contained; turned into the complement of the range they are not
+    (azimuths kept 1e-5 rad from the faces, radii above 0.01)."""
+    kind, par = W.SEGMENT_VARIANTS[v]
+    bk, bpar = _base(kind, par)
+    phi1, dphi = par[-2], par[-1]
+    rng = np.random.default_rng(300 + v)
+    p = np.stack(W._sample_in_shape(rng, bk, bpar, 20000))
+    keep = np.hypot(p[0], p[1]) > 0.01
+    p = p[:, keep]
+    m = 1e-5
+    ph_in = phi1 + m + (dphi - 2 * m) * rng.uniform(size=p.shape[1])
+    ph_out = phi1 + dphi + m + (2 * np.pi - dphi - 2 * m) * rng.uniform(size=p.shape[1])
+    assert np.all(orc.contains(kind, par, _with_azimuth(p, ph_in)) == 1)
+    assert np.all(orc.contains(kind, par, _with_azimuth(p, ph_out)) == 0)
+    # whole turns of phi1 describe the same solid
+    for k in (-2, 1):
+        par2 = par.copy()
+        par2[-2] += 2 * np.pi * k
+        q = _with_azimuth(p, ph_in)
+        assert np.all(orc.contains(kind, par2, q) == 1)
+
+
+@pytest.mark.parametrize("v", range(len(W.SEGMENT_VARIANTS)))
+def test_segments_glue_into_the_base(orc, v):
+    """The base solid is the union of the segments [phi1, phi1 + a] and
+    [phi1 + a, phi1 + 2 pi]; entering a union is entering its first part,
+    and the distance to a union is the smaller one. So on every track
+    DistFromOutside(base) = min over the two segments, Contains(base) = OR of
+    theirs, and Safety(base) = min of theirs for points outside the base.
+    This ties the segments to the base tube and cone, which the closed forms
+    and the other pins fix. The same holds for the variant's own range split
+    in two."""
+    kind, par = W.SEGMENT_VARIANTS[v]
+    bk, bpar = _base(kind, par)
+    _, _, t = _suite(kind, 6000, 500 + v, par=par)
+    phi1, dphi = par[-2], par[-1]
+    for whole_k, whole, lo, span in ((bk, bpar, phi1, 2 * np.pi), (kind, par, phi1, dphi)):
+        a = 0.37 * span
+        s1 = par.copy(); s1[-2], s1[-1] = lo, a
+        s2 = par.copy(); s2[-2], s2[-1] = lo + a, span - a
+        c = orc.contains(whole_k, whole, t)
+        c1 = orc.contains(kind, s1, t)
+        c2 = orc.contains(kind, s2, t)
+        near = orc.safety(kind, s1, t) < 1e-9
+        near |= orc.safety(kind, s2, t) < 1e-9
+        assert np.array_equal(c[~near], (c1 | c2)[~near])
+        d = orc.dist_out(whole_k, whole, t)
+        d12 = np.minimum(orc.dist_out(kind, s1, t), orc.dist_out(kind, s2, t))
+        both_big = (d >= BIG) & (d12 >= BIG)
+        assert np.all(both_big | (np.abs(d - d12) <= 1e-9 * np.maximum(1, d)))
+        out = (c == 0) & ~near
+        sa = orc.safety(whole_k, whole, t)[out]
+        s12 = np.minimum(orc.safety(kind, s1, t), orc.safety(kind, s2, t))[out]
+        assert np.all(np.abs(sa - s12) <= 1e-12 * np.maximum(1, sa))
+
+
+def test_full_turn_segment_is_the_base(orc):
+    """dphi = 2 pi keeps the whole base solid: every query equals the base's."""
+    for kind in (W.TUBS, W.CONS):
+        par = W.SUITE_SHAPES[kind].copy()
+        par[-1] = 2 * np.pi
+        bk, bpar = _base(kind, par)
+        _, _, t = _suite(kind, 5000, 77)
+        for q in (orc.CONTAINS, orc.SAFETY, orc.DIST_IN, orc.DIST_OUT):
+            assert np.array_equal(orc.shape_query(kind, par, q, t), orc.shape_query(bk, bpar, q, t))
+
+
+@pytest.mark.parametrize("v", range(len(W.SEGMENT_VARIANTS)))
+def test_segment_variants_safety_and_ray_marching(orc, v):
+    """The variational Safety check and the ray-marching check above, on the
+    other segment variants (fewer tracks)."""
+    kind, par = W.SEGMENT_VARIANTS[v]
+    _, _, t = _suite(kind, 60, 900 + v, par=par)
+    _check_safety_variational(orc, kind, par, t)
+    _, _, t = _suite(kind, 60, 950 + v, par=par)
+    _check_ray_marching(orc, kind, par, t)
 
 
 # ------------------------------------------------------------- navigator

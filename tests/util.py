@@ -12,7 +12,13 @@ BIG = 1e30
 
 def load_closed_forms():
     """Rows of tests/golden/closed_forms.txt as
-    (kind, par[5], query, p[3], d[3], expected, text)."""
+    (kind, par[5 or 7], query, p[3], d[3], expected, text). The cone segment
+    (kind 4) has 7 parameters, every other kind 5."""
+    env = {"sqrt": math.sqrt, "min": min, "pi": math.pi}
+
+    def num(tok):
+        return float(eval(tok, {"__builtins__": {}}, env))
+
     out = []
     with open(os.path.join(GOLDEN_DIR, "closed_forms.txt")) as f:
         for raw in f:
@@ -21,15 +27,14 @@ def load_closed_forms():
                 continue
             tok = line.split()
             kind = int(tok[0])
-            par = [float(v) for v in tok[1:6]]
-            q = int(tok[6])
-            p = [float(v) for v in tok[7:10]]
-            d = [float(v) for v in tok[10:13]]
-            expr = "".join(tok[13:])
-            if expr == "BIG":
-                val = BIG
-            else:
-                val = float(eval(expr, {"__builtins__": {}}, {"sqrt": math.sqrt, "min": min}))
+            npar = 7 if kind == 4 else 5
+            par = [num(v) for v in tok[1:1 + npar]]
+            tok = tok[1 + npar:]
+            q = int(tok[0])
+            p = [num(v) for v in tok[1:4]]
+            d = [num(v) for v in tok[4:7]]
+            expr = "".join(tok[7:])
+            val = BIG if expr == "BIG" else num(expr)
             out.append((kind, par, q, p, d, val, raw.strip()))
     return out
 
