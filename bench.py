@@ -49,15 +49,20 @@ FLOPS_DIST_OUT = [               # census slot 2 * kind + hole
     21, 21,                      # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)
     28, 37,                      # tube: r^2, z planes (10), A, B, outer (9) [, inner (9)]
     40, 55,                      # cone: r^2, radii, squares, z planes, outer (15) [, inner (15)]
+    88, 107,                     # tube segment: tube + range tests of the start point and
+                                 # of each base hit (6 each, 4 more for a nappe hit point)
+                                 # + two face entries (19 each)
+    112, 137,                    # cone segment: likewise, face entries 25 each
 ]
 
 
 def census_flops(counts, cull: bool) -> float:
     """FP64 flops of one launch from its census counts."""
-    f = counts[7] * (FLOPS_MOTHER_BOX + (FLOPS_TRACK_CULL if cull else 0))
-    f += counts[6] * FLOPS_CULL_TEST
+    from paper_1312_0816_amd import geonav as gv
+    f = counts[gv.CENSUS_TRACKS] * (FLOPS_MOTHER_BOX + (FLOPS_TRACK_CULL if cull else 0))
+    f += counts[gv.CENSUS_CULL] * FLOPS_CULL_TEST
     per_eval_extra = FLOPS_ROTATION + (0 if cull else 3)   # with culling, w = p - T belongs to the test
-    for slot in range(6):
+    for slot in range(len(FLOPS_DIST_OUT)):
         f += counts[slot] * (per_eval_extra + FLOPS_DIST_OUT[slot])
     return float(f)
 
@@ -82,14 +87,15 @@ def measure_rows(gv, W, dev):
     """The other rows of the hot path, each on its own workload (not part of
     the step above): the shape queries on the shape-suite distribution tiled
     to 2^26 tracks (3.2 GB, far above the 256 MB last-level cache), the plain
-    navigator on the toy detector (2^22 tracks, 32 daughters) and the adjoint
+    navigator on the toy detector (2^22 tracks, 32 daughters) and on its
+    variant with tube and cone segments among the daughters, and the adjoint
     on the toy detector (2^20 tracks)."""
     import torch
     rows = {}
     qbytes = {0: 25, 1: 32, 2: 56, 3: 56}
     qname = {0: "contains", 1: "safety", 2: "dist_in", 3: "dist_out"}
     shapes = {}
-    for kind in (0, 1, 2):
+    for kind in (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS):
         _, par, tr = W.shape_suite_c1(kind)
         big = torch.from_numpy(tr).to(dev).repeat(1, 64).contiguous()   # 2^26 tracks
         n = big.shape[1]
@@ -121,7 +127,7 @@ def measure_rows(gv, W, dev):
     rows["navigator_toy_detector_2^22"] = {"ms": ms, "tracks_per_s": n / (ms * 1e-3),
                                           "TFLOPs": fl / (ms * 1e-3) / 1e12,
                                           "alu_frac": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                                          "evaluated_fraction": sum(counts[:6]) / max(1, counts[6])}
+                                          "evaluated_fraction": sum(counts[:10]) / max(1, counts[gv.CENSUS_CULL])}
     saf = torch.empty(n, dtype=torch.float64, device=dev)
     ms_s = _time_ms(lambda: gv._check(lib.geo_navigate_safety(g.handle, 0, trs, None, gv._ptr(saf), hs)))
     ms_l = _time_ms(lambda: gv._check(lib.geo_locate(g.handle, 0, trs, None, hp, hs)))
@@ -129,6 +135,26 @@ def measure_rows(gv, W, dev):
     rows["locate_toy_detector_2^22"] = {"ms": ms_l, "points_per_s": n / (ms_l * 1e-3)}
     g.close()
     del t, step, hit, saf
+
+    vol = W.segmented_detector_volume()
+    tr = W.tracks_in_mother(np.random.default_rng(1270), vol, 1 << 22)
+    g = gv.Geometry([vol])
+    t = torch.from_numpy(tr).to(dev)
+    n = t.shape[1]
+    step = torch.empty(n, dtype=torch.float64, device=dev)
+    hit = torch.empty(n, dtype=torch.int32, device=dev)
+    trs, sp, hp = gv.tracks_struct(t), gv._ptr(step), gv._ptr(hit)
+    lib, hs = g._lib, gv._stream()
+    ms = _time_ms(lambda: gv._check(lib.geo_navigate_basket(g.handle, 0, trs, None, sp, hp, None, hs)))
+    _, _, counts = gv.geo_navigate_batched_census(g, [0], [0], [n], t)
+    fl = census_flops(counts, True)
+    rows["navigator_segmented_detector_2^22"] = {
+        "ms": ms, "tracks_per_s": n / (ms * 1e-3), "TFLOPs": fl / (ms * 1e-3) / 1e12,
+        "alu_frac": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "evaluated_fraction": sum(counts[:10]) / max(1, counts[gv.CENSUS_CULL]),
+        "daughters": "32: box, tube, cone, tube segment, cone segment in turn"}
+    g.close()
+    del t, step, hit
 
     vol, tr, tgt = W.adjoint_c4()
     g = gv.Geometry([vol])
@@ -449,8 +475,9 @@ def main():
                                     "ms_per_step": nocull_ms, "flops_per_launch": flops_nocull,
                                     "achieved_TFLOPs": flops_nocull / (nocull_ms * 1e-3) / 1e12,
                                     "frac": flops_nocull / (nocull_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
-        "census": {"evaluations_by_kind_hole": counts[:6], "cull_tests": counts[6], "tracks": counts[7],
-                   "evaluations_without_culling": int(sum(counts_nocull[:6]))},
+        "census": {"evaluations_by_kind_hole": counts[:10], "cull_tests": counts[gv.CENSUS_CULL],
+                   "tracks": counts[gv.CENSUS_TRACKS],
+                   "evaluations_without_culling": int(sum(counts_nocull[:10]))},
         "batched_equals_plain_bitwise": same,
         "kernel_source": digest,
     }

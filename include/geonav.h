@@ -23,6 +23,12 @@
  *   GEO_TUBE par = {rmin, rmax, dz}                      rmin<=r<=rmax, |z|<=dz
  *   GEO_CONE par = {dz, rmin1, rmax1, rmin2, rmax2}      radii "1" at z=-dz and
  *            "2" at z=+dz, varying linearly in z
+ *   GEO_TUBS par = {rmin, rmax, dz, phi1, dphi}          the tube and cone cut to
+ *   GEO_CONS par = {dz, rmin1, rmax1, rmin2, rmax2, phi1, dphi}   the azimuths
+ *            [phi1, phi1 + dphi] (radians, 0 < dphi <= 2 pi), z axis included
+ *            (section 3.1 names the segmented forms of tube and cone); two
+ *            flat faces close the cut. dphi = 2 pi is the uncut base solid.
+ *   Parameters beyond those a kind reads are ignored.
  *   Shapes are closed sets. Directions are not renormalised: distances are
  *   the ray parameter t of p + t*d (the length when |d| = 1).
  *   A line that never reaches the boundary gives GEO_BIG.
@@ -39,8 +45,9 @@ extern "C" {
 
 #define GEO_BIG 1e30
 #define GEO_MAX_DAUGHTERS 1024
+#define GEO_CENSUS_SLOTS 12
 
-enum { GEO_BOX = 0, GEO_TUBE = 1, GEO_CONE = 2 };
+enum { GEO_BOX = 0, GEO_TUBE = 1, GEO_CONE = 2, GEO_TUBS = 3, GEO_CONS = 4 };
 
 /* Queries of section 3.1: inside/outside check, minimum distance to any
  * boundary, distance along the line of flight to leave / to enter. */
@@ -61,7 +68,7 @@ typedef struct {
 } geo_tracks;
 
 typedef struct {
-    int32_t kind; /* GEO_BOX, GEO_TUBE or GEO_CONE */
+    int32_t kind; /* GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS or GEO_CONS */
     int32_t _pad;
     double par[7];
 } geo_shape;
@@ -98,7 +105,7 @@ typedef struct geo_geometry geo_geometry;
 /* Copy nvol volumes to the current device and return a handle.
  * Validation: kinds known, parameters finite, box half-lengths > 0,
  * 0 <= rmin <= rmax with rmax > 0 (cone: at both ends, rmax1 + rmax2 > 0),
- * dz > 0, rotations proper to 1e-12. Errors: GEO_ERR_INVALID_ARG,
+ * dz > 0, segments 0 < dphi <= 2 pi, rotations proper to 1e-12. Errors: GEO_ERR_INVALID_ARG,
  * GEO_ERR_NOMEM, GEO_ERR_HIP; *out is NULL on error. */
 int geo_geometry_create(const geo_volume_desc *volumes, int32_t nvol, geo_geometry **out);
 
@@ -179,16 +186,18 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
 
 /* Instrumented run of geo_navigate_batched (same outputs, not for timing):
  * launches directly (no graph) a variant of the batched kernel that tallies
- * the work it does. counts (host uint64_t[8]):
+ * the work it does. counts (host uint64_t[GEO_CENSUS_SLOTS]):
  *   counts[2 * kind + hole]  lane-evaluations of DistFromOutside for daughters
- *                            of that kind (hole = 1 for a tube/cone with an
- *                            inner surface): every active lane of a
- *                            wavefront that evaluates the daughter,
- *   counts[6]                lane culling tests (0 with culling off),
- *   counts[7]                tracks navigated (mother DistFromInside).
+ *                            of that kind (kind 0..4, hole = 1 for a tube,
+ *                            cone or segment with an inner surface): every
+ *                            active lane of a wavefront that evaluates the
+ *                            daughter,
+ *   counts[10]               lane culling tests (0 with culling off),
+ *   counts[11]               tracks navigated (mother DistFromInside).
  * Synchronises the stream. */
 int geo_navigate_batched_census(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
-                                double *step, int32_t *hit, uint64_t counts[8], hipStream_t stream);
+                                double *step, int32_t *hit, uint64_t counts[GEO_CENSUS_SLOTS],
+                                hipStream_t stream);
 
 /* Time the candidate launch shapes of the batched kernel (tracks per lane
  * 1/2/4/8 x waves per SIMD 0/2/3/4/6/8) on these baskets and keep the fastest in the handle; also records

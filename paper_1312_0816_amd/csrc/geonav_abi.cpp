@@ -46,19 +46,23 @@ int hip_fail(hipError_t e, const char *where) {
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
-bool finite5(const double *p) {
-    for (int i = 0; i < 5; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
+// Parameters each kind reads (the rest of par[] is ignored).
+static_assert(GEO_CENSUS_SLOTS == kCensusSlots, "census layout");
+
+int nparams(int kind) {
+    switch (kind) {
+        case GEO_BOX:
+        case GEO_TUBE: return 3;
+        case GEO_CONE:
+        case GEO_TUBS: return 5;
+        case GEO_CONS: return 7;
+        default: return 0;
+    }
 }
 
-// Validate a shape and derive its device record.
-int make_shape(const geo_shape &s, ShapeRec &out, double *bound_r, const char *what) {
-    std::memset(&out, 0, sizeof out);
-    if (!finite5(s.par)) return fail(GEO_ERR_INVALID_ARG, "%s: non-finite shape parameter", what);
-    const double *p = s.par;
-    out.kind = s.kind;
-    switch (s.kind) {
+// Base solid of a shape record: box, tube or cone constants.
+int make_base(int kind, const double *p, ShapeRec &out, double *bound_r, const char *what) {
+    switch (kind) {
         case GEO_BOX:
             if (!(p[0] > 0 && p[1] > 0 && p[2] > 0))
                 return fail(GEO_ERR_INVALID_ARG, "%s: box half-lengths must be > 0", what);
@@ -79,7 +83,7 @@ int make_shape(const geo_shape &s, ShapeRec &out, double *bound_r, const char *w
             out.c[4] = p[1] * p[1];
             if (bound_r) *bound_r = std::sqrt(p[1] * p[1] + p[2] * p[2]);
             return GEO_OK;
-        case GEO_CONE: {
+        default: {  // GEO_CONE
             const double dz = p[0], rmin1 = p[1], rmax1 = p[2], rmin2 = p[3], rmax2 = p[4];
             if (!(dz > 0 && rmin1 >= 0 && rmin2 >= 0 && rmin1 <= rmax1 && rmin2 <= rmax2 &&
                   rmax1 + rmax2 > 0))
@@ -111,9 +115,41 @@ int make_shape(const geo_shape &s, ShapeRec &out, double *bound_r, const char *w
             }
             return GEO_OK;
         }
-        default:
-            return fail(GEO_ERR_INVALID_ARG, "%s: unknown shape kind %d", what, s.kind);
     }
+}
+
+// Validate a shape and derive its device record. A segment whose range is a
+// full turn (dphi == 2 pi) is stored as its base kind.
+int make_shape(const geo_shape &s, ShapeRec &out, double *bound_r, const char *what) {
+    std::memset(&out, 0, sizeof out);
+    const int np = nparams(s.kind);
+    if (np == 0) return fail(GEO_ERR_INVALID_ARG, "%s: unknown shape kind %d", what, s.kind);
+    for (int i = 0; i < np; ++i)
+        if (!std::isfinite(s.par[i])) return fail(GEO_ERR_INVALID_ARG, "%s: non-finite shape parameter", what);
+    const double *p = s.par;
+    const bool seg = s.kind == GEO_TUBS || s.kind == GEO_CONS;
+    const int base = s.kind == GEO_TUBS ? GEO_TUBE : s.kind == GEO_CONS ? GEO_CONE : s.kind;
+    const int rc = make_base(base, p, out, bound_r, what);
+    if (rc != GEO_OK || !seg) {
+        out.kind = base;
+        return rc;
+    }
+    const double two_pi = 2.0 * M_PI;
+    const double phi1 = p[np - 2], dphi = p[np - 1];
+    if (!(dphi > 0 && dphi <= two_pi))
+        return fail(GEO_ERR_INVALID_ARG, "%s: segment needs 0 < dphi <= 2 pi", what);
+    if (dphi == two_pi) {
+        out.kind = base;
+        return GEO_OK;
+    }
+    out.kind = s.kind;
+    out.convex = dphi <= M_PI ? 1 : 0;
+    const double phi2 = phi1 + dphi;
+    out.c[17] = std::cos(phi1);
+    out.c[18] = std::sin(phi1);
+    out.c[19] = std::cos(phi2);
+    out.c[20] = std::sin(phi2);
+    return GEO_OK;
 }
 
 int check_rotation(const double *r, const char *what) {
@@ -537,7 +573,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     void *pargs[] = {&pa.vols, &pa.dau, &pa.cul, &pa.tiles, &pa.ntiles, &pa.cursors, &pa.t, &pa.step,
                      &pa.hit, &pa.census};
     if (census) {  // instrumented run: direct launches, no graph
-        GN_HIP(hipMemsetAsync(census, 0, 8 * sizeof(unsigned long long), stream));
+        GN_HIP(hipMemsetAsync(census, 0, kCensusSlots * sizeof(unsigned long long), stream));
         GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));
         GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true), dim3(grid), dim3(kBlock), pargs, 0,
                                stream));
@@ -619,24 +655,24 @@ int geo_navigate_batched(geo_geometry *g, const geo_basket *b, int32_t nb, geo_t
 }
 
 int geo_navigate_batched_census(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks all,
-                                double *step, int32_t *hit, uint64_t counts[8], hipStream_t stream) {
+                                double *step, int32_t *hit, uint64_t counts[GEO_CENSUS_SLOTS], hipStream_t stream) {
     if (!counts) return fail(GEO_ERR_INVALID_ARG, "counts is NULL");
-    for (int i = 0; i < 8; ++i) counts[i] = 0;
+    for (int i = 0; i < GEO_CENSUS_SLOTS; ++i) counts[i] = 0;
     int rc = validate_batched(g, b, nb, all, step, hit, true);
     if (rc) return rc;
     if (nb == 0 || all.n == 0) return GEO_OK;
     if ((rc = check_device(g))) return rc;
     unsigned long long *d = nullptr;
-    if (hipMalloc(&d, 8 * sizeof(unsigned long long)) != hipSuccess)
+    if (hipMalloc(&d, kCensusSlots * sizeof(unsigned long long)) != hipSuccess)
         return fail(GEO_ERR_NOMEM, "census counter allocation failed");
     rc = launch_batched(g, b, nb, all, step, hit, stream, d);
     if (rc == GEO_OK) {
-        unsigned long long h[8];
+        unsigned long long h[kCensusSlots];
         hipError_t e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) rc = hip_fail(e, "census readback");
         else
-            for (int i = 0; i < 8; ++i) counts[i] = h[i];
+            for (int i = 0; i < kCensusSlots; ++i) counts[i] = h[i];
     }
     (void)hipFree(d);
     return rc;

@@ -3,8 +3,9 @@
 // One lane evaluates one track. Every algorithm is branch-free over lanes:
 // all candidate surfaces of a shape are evaluated and the valid smallest one
 // is kept with selects, so a wavefront never diverges inside a shape. The
-// only branches are on the shape kind and the hole flag, which are uniform
-// across a wavefront (the navigator walks the daughters in lockstep).
+// only branches are on the shape kind and the hole and convexity flags,
+// which are uniform across a wavefront (the navigator walks the daughters in
+// lockstep).
 //
 // Each distance query is a minimum over per-surface candidates (faces,
 // z-planes, the outer and inner cylinder/cone nappes): for DistFromOutside
@@ -20,7 +21,8 @@
 namespace gn {
 
 constexpr double kBig = 1e30;
-enum : int32_t { kBox = 0, kTube = 1, kCone = 2 };
+constexpr int kCensusSlots = 12, kCensusCull = 10, kCensusTracks = 11;
+enum : int32_t { kBox = 0, kTube = 1, kCone = 2, kTubs = 3, kCons = 4 };
 
 // Shape with host-derived constants.
 //   BOX  c0..2 = dx, dy, dz
@@ -29,12 +31,17 @@ enum : int32_t { kBox = 0, kTube = 1, kCone = 2 };
 //        c5..8 = rmin1, rmax1, rmin2, rmax2, c9..12 = their squares,
 //        c13 = 1/sqrt(1 + b_out^2), c14 = 1/sqrt(1 + b_in^2),
 //        c15 = 1/|outer edge|^2, c16 = 1/|inner edge|^2 (profile edges in (r, z))
+//   TUBS, CONS (segments: the tube or cone cut to the azimuths [phi1, phi2],
+//        phi2 = phi1 + dphi < phi1 + 2 pi, axis included): the base kind's
+//        constants, and c17, c18 = cos phi1, sin phi1; c19, c20 = cos phi2, sin phi2.
 struct alignas(16) ShapeRec {
     int32_t kind;
-    int32_t hole;  // tube/cone: an inner surface exists (not both inner radii 0)
-    double c[19];
+    int32_t hole;    // tube/cone: an inner surface exists (not both inner radii 0)
+    int32_t convex;  // segment: dphi <= pi (the azimuth range is convex)
+    int32_t pad;
+    double c[22];
 };
-static_assert(sizeof(ShapeRec) == 160, "ShapeRec layout");
+static_assert(sizeof(ShapeRec) == 192, "ShapeRec layout");
 
 // A placed daughter: mother-frame point = R * local + T.
 struct alignas(16) DaughterRec {
@@ -45,7 +52,7 @@ struct alignas(16) DaughterRec {
     double pad[2];
     ShapeRec shape;
 };
-static_assert(sizeof(DaughterRec) == 288, "DaughterRec layout");
+static_assert(sizeof(DaughterRec) == 320, "DaughterRec layout");
 
 // Culling record of a daughter, in its own compact array (32 B, so the
 // records of a whole volume stay in the scalar cache during the daughter
@@ -65,7 +72,7 @@ struct alignas(16) VolumeRec {
     int32_t first;  // index of daughter 0 in the daughter and culling tables
     int32_t pad[6];
 };
-static_assert(sizeof(VolumeRec) == 192, "VolumeRec layout");
+static_assert(sizeof(VolumeRec) == 224, "VolumeRec layout");
 
 struct TracksDev {
     const double *x, *y, *z, *ux, *uy, *uz;
@@ -214,12 +221,110 @@ __device__ __forceinline__ double tube_safety(const double *c, int hole, double 
     return m <= 0.0 ? -m : out;
 }
 
-__device__ __forceinline__ double tube_dist_out(const double *c, int hole, double x, double y,
-                                                double z, double ux, double uy, double uz,
-                                                int &sid) {
+// ------------------------------------------------------------ azimuth range
+// A segment keeps the azimuths [phi1, phi2] and the z axis. With the inward
+// normals of its two bounding half-planes, n1 = (-sin phi1, cos phi1) and
+// n2 = (sin phi2, -cos phi2), a point q is in the range when a = n1.q >= 0
+// and b = n2.q >= 0 if dphi <= pi (a convex range), and when a >= 0 or
+// b >= 0 if dphi > pi (the complement is then the open convex wedge a < 0,
+// b < 0). a and b are the signed distances from the two face planes.
+__device__ __forceinline__ double wedge_a(const double *c, double x, double y) {
+    return fma(c[17], y, -c[18] * x);
+}
+__device__ __forceinline__ double wedge_b(const double *c, double x, double y) {
+    return fma(c[20], x, -c[19] * y);
+}
+__device__ __forceinline__ bool wedge_in(const ShapeRec &s, double x, double y) {
+    const double a = wedge_a(s.c, x, y), b = wedge_b(s.c, x, y);
+    return s.convex ? (a >= 0.0 && b >= 0.0) : (a >= 0.0 || b >= 0.0);
+}
+
+// Leaving the range along the line (the point is in it). Convex range: the
+// first plane crossed outwards. Wider range: entering the open complement
+// {a < 0} and {b < 0}, which happens at the later of the starts of the two
+// half-lines {t : a(t) < 0}, {t : b(t) < 0}, provided neither has ended by
+// then. Surfaces 3 and 4.
+__device__ __forceinline__ void wedge_exit(const ShapeRec &s, double x, double y, double ux,
+                                           double uy, double &best, int &sid) {
+    const double a0 = wedge_a(s.c, x, y), da = wedge_a(s.c, ux, uy);
+    const double b0 = wedge_b(s.c, x, y), db = wedge_b(s.c, ux, uy);
+    const double ta = fdiv(-a0, da), tb = fdiv(-b0, db);
+    if (s.convex) {
+        take(da < 0.0, ta, 3, best, sid);
+        take(db < 0.0, tb, 4, best, sid);
+    } else {
+        // {t : a(t) < 0} is (ta, inf) for da < 0, (-inf, ta) for da > 0, and
+        // everything or nothing for da == 0
+        const double lo_a = da < 0.0 ? ta : ((da > 0.0 || a0 < 0.0) ? -kBig : kBig);
+        const double hi_a = da > 0.0 ? ta : ((da < 0.0 || a0 < 0.0) ? kBig : -kBig);
+        const double lo_b = db < 0.0 ? tb : ((db > 0.0 || b0 < 0.0) ? -kBig : kBig);
+        const double hi_b = db > 0.0 ? tb : ((db < 0.0 || b0 < 0.0) ? kBig : -kBig);
+        const double lo = fmax(lo_a, lo_b), hi = fmin(hi_a, hi_b);
+        take(lo < hi && hi > 0.0 && lo >= 0.0, lo, lo_a >= lo_b ? 3 : 4, best, sid);
+    }
+}
+
+__device__ __forceinline__ bool cone_contains(const double *c, int hole, double x, double y,
+                                              double z);
+
+template <int BASE>
+__device__ __forceinline__ bool base_contains(const ShapeRec &s, double x, double y, double z) {
+    if (BASE == kTube) return tube_contains(s.c, x, y, z);
+    return cone_contains(s.c, s.hole, x, y, z);
+}
+
+// Entering the range through a flat face, at a point inside the base solid
+// (surfaces 3 and 4). The line's parameters in the range follow from the
+// half-lines {t : a(t) >= 0} and {t : b(t) >= 0}: for a convex range their
+// intersection [w_lo, w_hi], entered at w_lo when the start is outside; for a
+// wider range their union, the complement of the open interval in which the
+// line crosses the wedge a < 0, b < 0, re-entered where that interval ends.
+// Taking the entry from these intervals, not from a point test on each
+// face's half-plane, keeps a line through the axis (both planes crossed at
+// one point) exact.
+template <int BASE>
+__device__ __forceinline__ void face_entries(const ShapeRec &s, double x, double y, double z,
+                                             double ux, double uy, double uz, double &best,
+                                             int &sid) {
+    const double a0 = wedge_a(s.c, x, y), da = wedge_a(s.c, ux, uy);
+    const double b0 = wedge_b(s.c, x, y), db = wedge_b(s.c, ux, uy);
+    const double ta = fdiv(-a0, da), tb = fdiv(-b0, db);
+    double t;
+    bool ok;
+    int id;
+    if (s.convex) {
+        // {a >= 0} is [ta, inf) for da > 0, (-inf, ta] for da < 0, all or nothing for da == 0
+        const double lo_a = da > 0.0 ? ta : ((da < 0.0 || a0 >= 0.0) ? -kBig : kBig);
+        const double hi_a = da < 0.0 ? ta : ((da > 0.0 || a0 >= 0.0) ? kBig : -kBig);
+        const double lo_b = db > 0.0 ? tb : ((db < 0.0 || b0 >= 0.0) ? -kBig : kBig);
+        const double hi_b = db < 0.0 ? tb : ((db > 0.0 || b0 >= 0.0) ? kBig : -kBig);
+        t = fmax(lo_a, lo_b);
+        ok = t <= fmin(hi_a, hi_b) && t >= 0.0;
+        id = lo_a >= lo_b ? 3 : 4;
+    } else {
+        // {a < 0} is (ta, inf) for da < 0, (-inf, ta) for da > 0
+        const double lo_a = da < 0.0 ? ta : ((da > 0.0 || a0 < 0.0) ? -kBig : kBig);
+        const double hi_a = da > 0.0 ? ta : ((da < 0.0 || a0 < 0.0) ? kBig : -kBig);
+        const double lo_b = db < 0.0 ? tb : ((db > 0.0 || b0 < 0.0) ? -kBig : kBig);
+        const double hi_b = db > 0.0 ? tb : ((db < 0.0 || b0 < 0.0) ? kBig : -kBig);
+        t = fmin(hi_a, hi_b);
+        ok = fmax(lo_a, lo_b) < t && t >= 0.0 && t < kBig;
+        id = hi_a <= hi_b ? 3 : 4;
+    }
+    const double xh = fma(t, ux, x), yh = fma(t, uy, y), zh = fma(t, uz, z);
+    take(ok && base_contains<BASE>(s, xh, yh, zh), t, id, best, sid);
+}
+
+// With SEG (a segment) an entry through a base surface counts only at a hit
+// point within the range, and the face entries join the candidates.
+template <bool SEG>
+__device__ __forceinline__ double tube_dist_out(const ShapeRec &S, double x, double y, double z,
+                                                double ux, double uy, double uz, int &sid) {
+    const double *c = S.c;
+    const int hole = S.hole;
     const double dz = c[2];
     const double rsq = x * x + y * y;
-    const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3];
+    const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3] && (!SEG || wedge_in(S, x, y));
     double best = kBig;
     sid = -1;
     {   // z planes: from beyond the slab, moving towards it, landing on the annulus
@@ -227,7 +332,8 @@ __device__ __forceinline__ double tube_dist_out(const double *c, int hole, doubl
         const double t = fdiv(az, fabs(uz));
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
-        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= c[3] && r2 <= c[4];
+        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= c[3] && r2 <= c[4] &&
+                        (!SEG || wedge_in(S, xh, yh));
         take(ok, t, 0, best, sid);
     }
     const double A = ux * ux + uy * uy;
@@ -237,7 +343,8 @@ __device__ __forceinline__ double tube_dist_out(const double *c, int hole, doubl
         const double disc = B * B - A * C;
         const double s = fsqrt(fmax(disc, 0.0));
         const double t = fdiv(C, s - B);
-        const bool ok = C > 0.0 && B < 0.0 && disc >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        const bool ok = C > 0.0 && B < 0.0 && disc >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
+                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 1, best, sid);
     }
     if (hole) {  // inner cylinder, left from inside the hole into the material
@@ -245,18 +352,23 @@ __device__ __forceinline__ double tube_dist_out(const double *c, int hole, doubl
         const double disc = B * B - A * C;
         const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_up(A, B, C, s);
-        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
+                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 2, best, sid);
     }
+    if (SEG) face_entries<kTube>(S, x, y, z, ux, uy, uz, best, sid);
     return inside ? 0.0 : best;
 }
 
-__device__ __forceinline__ double tube_dist_in(const double *c, int hole, double x, double y,
-                                               double z, double ux, double uy, double uz,
-                                               int &sid) {
+// With SEG the exit is the earlier of leaving the base and leaving the range.
+template <bool SEG>
+__device__ __forceinline__ double tube_dist_in(const ShapeRec &S, double x, double y, double z,
+                                               double ux, double uy, double uz, int &sid) {
+    const double *c = S.c;
+    const int hole = S.hole;
     const double dz = c[2];
     const double rsq = x * x + y * y;
-    const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3];
+    const bool inside = fabs(z) <= dz && rsq <= c[4] && rsq >= c[3] && (!SEG || wedge_in(S, x, y));
     double best = kBig;
     sid = -1;
     take(uz != 0.0, fdiv(dz - (uz > 0.0 ? z : -z), fabs(uz)), 0, best, sid);
@@ -276,6 +388,7 @@ __device__ __forceinline__ double tube_dist_in(const double *c, int hole, double
         const double t = root_down(A, B, C, s);
         take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
     }
+    if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);
     return inside ? best : 0.0;
 }
 
@@ -325,14 +438,17 @@ __device__ __forceinline__ double cone_safety(const double *c, int hole, double 
     return inside ? din : sqrt(d2);
 }
 
-__device__ __forceinline__ double cone_dist_out(const double *c, int hole, double x, double y,
-                                                double z, double ux, double uy, double uz,
-                                                int &sid) {
+template <bool SEG>
+__device__ __forceinline__ double cone_dist_out(const ShapeRec &S, double x, double y, double z,
+                                                double ux, double uy, double uz, int &sid) {
+    const double *c = S.c;
+    const int hole = S.hole;
     const double dz = c[0];
     const double rsq = x * x + y * y;
     const double wo = fma(c[2], z, c[1]);
     const double wi = fma(c[4], z, c[3]);
-    const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi);
+    const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi) &&
+                        (!SEG || wedge_in(S, x, y));
     double best = kBig;
     sid = -1;
     {   // z planes: the face's annulus depends on which end is hit
@@ -344,7 +460,8 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
         // stay uniform scalars)
         const bool on_bot = r2 >= c[9] && r2 <= c[10];
         const bool on_top = r2 >= c[11] && r2 <= c[12];
-        const bool ok = az > 0.0 && z * uz < 0.0 && (z > 0.0 ? on_top : on_bot);
+        const bool ok = az > 0.0 && z * uz < 0.0 && (z > 0.0 ? on_top : on_bot) &&
+                        (!SEG || wedge_in(S, xh, yh));
         take(ok, t, 0, best, sid);
     }
     const double A0 = ux * ux + uy * uy;
@@ -355,7 +472,8 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
         const double disc = B * B - A * C;
         const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_down(A, B, C, s);
-        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
+                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 1, best, sid);
     }
     if (hole) {  // inner nappe: left from the hole where f goes from - to +
@@ -364,20 +482,25 @@ __device__ __forceinline__ double cone_dist_out(const double *c, int hole, doubl
         const double disc = B * B - A * C;
         const double s = fsqrt(fmax(disc, 0.0));
         const double t = root_up(A, B, C, s);
-        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz;
+        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
+                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 2, best, sid);
     }
+    if (SEG) face_entries<kCone>(S, x, y, z, ux, uy, uz, best, sid);
     return inside ? 0.0 : best;
 }
 
-__device__ __forceinline__ double cone_dist_in(const double *c, int hole, double x, double y,
-                                               double z, double ux, double uy, double uz,
-                                               int &sid) {
+template <bool SEG>
+__device__ __forceinline__ double cone_dist_in(const ShapeRec &S, double x, double y, double z,
+                                               double ux, double uy, double uz, int &sid) {
+    const double *c = S.c;
+    const int hole = S.hole;
     const double dz = c[0];
     const double rsq = x * x + y * y;
     const double wo = fma(c[2], z, c[1]);
     const double wi = fma(c[4], z, c[3]);
-    const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi);
+    const bool inside = fabs(z) <= dz && rsq <= wo * wo && (!hole || rsq >= wi * wi) &&
+                        (!SEG || wedge_in(S, x, y));
     double best = kBig;
     sid = -1;
     take(uz != 0.0, fdiv(dz - (uz > 0.0 ? z : -z), fabs(uz)), 0, best, sid);
@@ -399,42 +522,144 @@ __device__ __forceinline__ double cone_dist_in(const double *c, int hole, double
         const double t = root_down(A, B, C, s);
         take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
     }
+    if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);
     return inside ? best : 0.0;
 }
 
+// ------------------------------------------------------ segment safety
+// Squared distance from (u, z) to a face, the profile polygon laid in the
+// half-plane at phi_i with u along e_i (0 on or inside the polygon). The
+// tube's profile is the rectangle [rmin, rmax] x [-dz, dz]; the cone's is the
+// trapezoid, its inner edge included even on the axis (there the two faces
+// meet).
+__device__ __forceinline__ double tube_face_d2(const double *c, double u, double z) {
+    const double du = fmax(fmax(c[0] - u, u - c[1]), 0.0);
+    const double dz = fmax(fabs(z) - c[2], 0.0);
+    return du * du + dz * dz;
+}
+
+__device__ __forceinline__ double cone_face_d2(const double *c, double u, double z) {
+    const double dz = c[0];
+    const double wo = fma(c[2], z, c[1]);
+    const double wi = fma(c[4], z, c[3]);
+    const bool in = fabs(z) <= dz && u <= wo && u >= wi;
+    const double rb = fmin(fmax(u, c[5]), c[6]);
+    const double rt = fmin(fmax(u, c[7]), c[8]);
+    double d2 = fmin(sq(u - rb) + sq(z + dz), sq(u - rt) + sq(z - dz));
+    d2 = fmin(d2, seg_d2(u, z, c[6], -dz, c[8] - c[6], 2.0 * dz, c[15]));
+    d2 = fmin(d2, seg_d2(u, z, c[5], -dz, c[7] - c[5], 2.0 * dz, c[16]));
+    return in ? 0.0 : d2;
+}
+
+// Safety of a segment: the boundary is the base's surfaces within the range
+// and the two faces.
+//   Outside the solid: the base's Safety if p is in the range (the nearest
+//   point of a surface of revolution has p's own azimuth), and the distance
+//   to each face, sqrt(v_i^2 + d2_i) with v_i the distance from the face's
+//   plane and d2_i that of (u_i, z) to the face polygon (this also covers
+//   the base surfaces' edges when p is out of the range).
+//   Inside: the base's Safety and, per face, |v_i| when the foot of the
+//   perpendicular lies on the face's half-plane (u_i >= 0) or else r. The
+//   foot can fall short of the face only into the hole, where the base's
+//   inner surface is nearer than |v_i|; off the half-plane the face is at
+//   least r away, exactly r where the profile reaches the axis, and with a
+//   hole the inner surface is nearer than r.
+template <int BASE>
+__device__ __forceinline__ double seg_safety(const ShapeRec &S, double x, double y, double z) {
+    const double *c = S.c;
+    const double base = BASE == kTube ? tube_safety(c, S.hole, x, y, z)
+                                      : cone_safety(c, S.hole, x, y, z);
+    const bool in_base = base_contains<BASE>(S, x, y, z);
+    const double a = wedge_a(c, x, y), b = wedge_b(c, x, y);
+    const bool in_range = S.convex ? (a >= 0.0 && b >= 0.0) : (a >= 0.0 || b >= 0.0);
+    const double u1 = fma(c[18], y, c[17] * x), u2 = fma(c[20], y, c[19] * x);
+    const double r = sqrt(x * x + y * y);
+    const double f_in = fmin(u1 >= 0.0 ? fabs(a) : r, u2 >= 0.0 ? fabs(b) : r);
+    const double d1 = BASE == kTube ? tube_face_d2(c, u1, z) : cone_face_d2(c, u1, z);
+    const double d2 = BASE == kTube ? tube_face_d2(c, u2, z) : cone_face_d2(c, u2, z);
+    const double f_out = sqrt(fmin(fma(a, a, d1), fma(b, b, d2)));
+    return (in_base && in_range) ? fmin(base, f_in) : fmin(in_range ? base : kBig, f_out);
+}
+
 // ------------------------------------------------------ dispatch on kind
+template <int KIND>
+__device__ __forceinline__ bool shape_contains(const ShapeRec &s, double x, double y, double z) {
+    if (KIND == kBox) return box_contains(s.c, x, y, z);
+    if (KIND == kTube) return tube_contains(s.c, x, y, z);
+    if (KIND == kCone) return cone_contains(s.c, s.hole, x, y, z);
+    if (KIND == kTubs) return tube_contains(s.c, x, y, z) && wedge_in(s, x, y);
+    return cone_contains(s.c, s.hole, x, y, z) && wedge_in(s, x, y);
+}
+
+template <int KIND>
+__device__ __forceinline__ double shape_safety(const ShapeRec &s, double x, double y, double z) {
+    if (KIND == kBox) return box_safety(s.c, x, y, z);
+    if (KIND == kTube) return tube_safety(s.c, s.hole, x, y, z);
+    if (KIND == kCone) return cone_safety(s.c, s.hole, x, y, z);
+    if (KIND == kTubs) return seg_safety<kTube>(s, x, y, z);
+    return seg_safety<kCone>(s, x, y, z);
+}
+
+template <int KIND>
+__device__ __forceinline__ double shape_dist_out(const ShapeRec &s, double x, double y, double z,
+                                                 double ux, double uy, double uz, int &sid) {
+    if (KIND == kBox) return box_dist_out(s.c, x, y, z, ux, uy, uz, sid);
+    if (KIND == kTube) return tube_dist_out<false>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kCone) return cone_dist_out<false>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kTubs) return tube_dist_out<true>(s, x, y, z, ux, uy, uz, sid);
+    return cone_dist_out<true>(s, x, y, z, ux, uy, uz, sid);
+}
+
+template <int KIND>
+__device__ __forceinline__ double shape_dist_in(const ShapeRec &s, double x, double y, double z,
+                                                double ux, double uy, double uz, int &sid) {
+    if (KIND == kBox) return box_dist_in(s.c, x, y, z, ux, uy, uz, sid);
+    if (KIND == kTube) return tube_dist_in<false>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kCone) return cone_dist_in<false>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kTubs) return tube_dist_in<true>(s, x, y, z, ux, uy, uz, sid);
+    return cone_dist_in<true>(s, x, y, z, ux, uy, uz, sid);
+}
+
 // `kind` is uniform across the wavefront wherever these are called.
 __device__ __forceinline__ bool any_contains(const ShapeRec &s, double x, double y, double z) {
     switch (s.kind) {
-        case kBox: return box_contains(s.c, x, y, z);
-        case kTube: return tube_contains(s.c, x, y, z);
-        default: return cone_contains(s.c, s.hole, x, y, z);
+        case kBox: return shape_contains<kBox>(s, x, y, z);
+        case kTube: return shape_contains<kTube>(s, x, y, z);
+        case kCone: return shape_contains<kCone>(s, x, y, z);
+        case kTubs: return shape_contains<kTubs>(s, x, y, z);
+        default: return shape_contains<kCons>(s, x, y, z);
     }
 }
 
 __device__ __forceinline__ double any_safety(const ShapeRec &s, double x, double y, double z) {
     switch (s.kind) {
-        case kBox: return box_safety(s.c, x, y, z);
-        case kTube: return tube_safety(s.c, s.hole, x, y, z);
-        default: return cone_safety(s.c, s.hole, x, y, z);
+        case kBox: return shape_safety<kBox>(s, x, y, z);
+        case kTube: return shape_safety<kTube>(s, x, y, z);
+        case kCone: return shape_safety<kCone>(s, x, y, z);
+        case kTubs: return shape_safety<kTubs>(s, x, y, z);
+        default: return shape_safety<kCons>(s, x, y, z);
     }
 }
 
 __device__ __forceinline__ double any_dist_out(const ShapeRec &s, double x, double y, double z,
                                                double ux, double uy, double uz, int &sid) {
     switch (s.kind) {
-        case kBox: return box_dist_out(s.c, x, y, z, ux, uy, uz, sid);
-        case kTube: return tube_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
-        default: return cone_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+        case kBox: return shape_dist_out<kBox>(s, x, y, z, ux, uy, uz, sid);
+        case kTube: return shape_dist_out<kTube>(s, x, y, z, ux, uy, uz, sid);
+        case kCone: return shape_dist_out<kCone>(s, x, y, z, ux, uy, uz, sid);
+        case kTubs: return shape_dist_out<kTubs>(s, x, y, z, ux, uy, uz, sid);
+        default: return shape_dist_out<kCons>(s, x, y, z, ux, uy, uz, sid);
     }
 }
 
 __device__ __forceinline__ double any_dist_in(const ShapeRec &s, double x, double y, double z,
                                               double ux, double uy, double uz, int &sid) {
     switch (s.kind) {
-        case kBox: return box_dist_in(s.c, x, y, z, ux, uy, uz, sid);
-        case kTube: return tube_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
-        default: return cone_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
+        case kBox: return shape_dist_in<kBox>(s, x, y, z, ux, uy, uz, sid);
+        case kTube: return shape_dist_in<kTube>(s, x, y, z, ux, uy, uz, sid);
+        case kCone: return shape_dist_in<kCone>(s, x, y, z, ux, uy, uz, sid);
+        case kTubs: return shape_dist_in<kTubs>(s, x, y, z, ux, uy, uz, sid);
+        default: return shape_dist_in<kCons>(s, x, y, z, ux, uy, uz, sid);
     }
 }
 
@@ -450,9 +675,19 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, doubl
     }
     if (sid == 0) { nz = 1.0; return; }
     if (sid < 0) return;
+    if (sid == 3) {  // segment face planes: n1, n2
+        nx = -s.c[18];
+        ny = s.c[17];
+        return;
+    }
+    if (sid == 4) {
+        nx = s.c[20];
+        ny = -s.c[19];
+        return;
+    }
     nx = hx;
     ny = hy;
-    if (s.kind == kCone) {
+    if (s.kind == kCone || s.kind == kCons) {
         const double a = sid == 1 ? s.c[1] : s.c[3];
         const double b = sid == 1 ? s.c[2] : s.c[4];
         nz = -b * fma(b, hz, a);
@@ -476,10 +711,10 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, doubl
 // to the point at parameter tau is |w|^2 + tau (2 w.d + tau |d|^2), smallest
 // over [0, best] at tau = clamp(-w.d / |d|^2, 0, best).
 //
-// With COUNT, the work done is tallied into census[8] (one atomic per
-// wavefront and event, adding the number of active lanes): slots
-// 2 * kind + hole count daughter evaluations, slot 6 culling tests, slot 7
-// tracks.
+// With COUNT, the work done is tallied into census[kCensusSlots] (one atomic
+// per wavefront and event, adding the number of active lanes): slots
+// 2 * kind + hole count daughter evaluations, slot kCensusCull culling
+// tests, slot kCensusTracks tracks.
 __device__ __forceinline__ void census_add(unsigned long long *census, int slot) {
     const unsigned long long act = __ballot(1);
     if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1)
@@ -494,7 +729,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
                                           int &hit, int &bsid,
                                           unsigned long long *census = nullptr) {
     int sid;
-    if (COUNT) census_add(census, 7);
+    if (COUNT) census_add(census, kCensusTracks);
     best = any_dist_in(v.mother, x, y, z, ux, uy, uz, sid);
     hit = -1;
     bsid = sid;
@@ -512,7 +747,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
             wz -= offs[3 * k + 2];
         }
         if (CULL) {
-            if (COUNT) census_add(census, 6);
+            if (COUNT) census_add(census, kCensusCull);
             const double b2 = fma(wz, uz2, fma(wy, uy2, wx * ux2));    // 2 w.d
             const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
             const double tau = fmax(fmin(-b2 * hdd, best), 0.0);

@@ -24,30 +24,17 @@ __global__ __launch_bounds__(kBlock) void k_shape_query(ShapeRec s, TracksDev t,
     if (i >= t.n) return;
     const double x = t.x[i], y = t.y[i], z = t.z[i];
     if (Q == 0) {
-        bool in;
-        if (KIND == kBox) in = box_contains(s.c, x, y, z);
-        else if (KIND == kTube) in = tube_contains(s.c, x, y, z);
-        else in = cone_contains(s.c, s.hole, x, y, z);
-        static_cast<uint8_t *>(out)[i] = in ? 1 : 0;
+        static_cast<uint8_t *>(out)[i] = shape_contains<KIND>(s, x, y, z) ? 1 : 0;
         return;
     }
     double r;
     if (Q == 1) {
-        if (KIND == kBox) r = box_safety(s.c, x, y, z);
-        else if (KIND == kTube) r = tube_safety(s.c, s.hole, x, y, z);
-        else r = cone_safety(s.c, s.hole, x, y, z);
+        r = shape_safety<KIND>(s, x, y, z);
     } else {
         const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
         int sid;
-        if (Q == 2) {
-            if (KIND == kBox) r = box_dist_in(s.c, x, y, z, ux, uy, uz, sid);
-            else if (KIND == kTube) r = tube_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
-            else r = cone_dist_in(s.c, s.hole, x, y, z, ux, uy, uz, sid);
-        } else {
-            if (KIND == kBox) r = box_dist_out(s.c, x, y, z, ux, uy, uz, sid);
-            else if (KIND == kTube) r = tube_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
-            else r = cone_dist_out(s.c, s.hole, x, y, z, ux, uy, uz, sid);
-        }
+        if (Q == 2) r = shape_dist_in<KIND>(s, x, y, z, ux, uy, uz, sid);
+        else r = shape_dist_out<KIND>(s, x, y, z, ux, uy, uz, sid);
     }
     static_cast<double *>(out)[i] = r;
 }
@@ -71,7 +58,9 @@ hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, 
     switch (s.kind) {
         case kBox: return launch_shape_kind<kBox>(s, query, t, out, st);
         case kTube: return launch_shape_kind<kTube>(s, query, t, out, st);
-        default: return launch_shape_kind<kCone>(s, query, t, out, st);
+        case kCone: return launch_shape_kind<kCone>(s, query, t, out, st);
+        case kTubs: return launch_shape_kind<kTubs>(s, query, t, out, st);
+        default: return launch_shape_kind<kCons>(s, query, t, out, st);
     }
 }
 

@@ -21,7 +21,8 @@ from . import build as _build
 
 LIB_PATH = _build.LIB
 
-GEO_BOX, GEO_TUBE, GEO_CONE = 0, 1, 2
+GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS, GEO_CONS = 0, 1, 2, 3, 4
+CENSUS_SLOTS, CENSUS_CULL, CENSUS_TRACKS = 12, 10, 11
 GEO_CONTAINS, GEO_SAFETY, GEO_DIST_IN, GEO_DIST_OUT = 0, 1, 2, 3
 GEO_BIG = 1e30
 GEO_MAX_DAUGHTERS = 1024
@@ -328,15 +329,15 @@ def geo_navigate_batched(g: Geometry, basket_volume, basket_offset, basket_n, tr
 
 def geo_navigate_batched_census(g: Geometry, basket_volume, basket_offset, basket_n,
                                 tracks: torch.Tensor, stream=None):
-    """Instrumented batched run. Returns (step, hit, counts[8]) with counts as
-    documented in geonav.h (lane-evaluations per kind/hole slot, culling
-    tests, tracks)."""
+    """Instrumented batched run. Returns (step, hit, counts[CENSUS_SLOTS])
+    with counts as documented in geonav.h: lane-evaluations per slot
+    2 * kind + hole, culling tests at CENSUS_CULL, tracks at CENSUS_TRACKS."""
     t = tracks_struct(tracks)
     n = t.n
     step = torch.empty(n, dtype=torch.float64, device=tracks.device)
     hit = torch.empty(n, dtype=torch.int32, device=tracks.device)
     arr, nb = _baskets(basket_volume, basket_offset, basket_n)
-    counts = (C.c_uint64 * 8)()
+    counts = (C.c_uint64 * CENSUS_SLOTS)()
     _check(g._lib.geo_navigate_batched_census(g.handle, arr, nb, t, _ptr(step), _ptr(hit), counts,
                                               _stream(stream)))
     return step, hit, [int(c) for c in counts]

@@ -118,6 +118,12 @@ def box_c0(seed: int = 1000, n: int = 1024):
     return BOX, SUITE_SHAPES[BOX].copy(), pack_tracks(p[0], p[1], p[2], *u)
 
 
+def segment_range(kind, par):
+    """(phi1, dphi) of a tube or cone segment's parameters (padded or not)."""
+    par = np.asarray(par, np.float64).reshape(-1)
+    return (float(par[3]), float(par[4])) if kind == TUBS else (float(par[5]), float(par[6]))
+
+
 def _sample_in_shape(rng, kind, par, n):
     """Points uniformly distributed in the shape's volume, by construction
     (not by a membership test). Segments draw the azimuth in their range."""
@@ -219,12 +225,17 @@ def _draw_daughter(rng, kind):
         rmin2 = inner(rmax2)
         return (np.array([dz, rmin1, rmax1, rmin2, rmax2]),
                 float(np.hypot(max(rmax1, rmax2), dz)))
+    if kind in (TUBS, CONS):
+        # the base drawn as above, cut to phi1 ~ U[0, 2 pi), dphi ~ U[0.3, 2 pi - 0.3]
+        par, rb = _draw_daughter(rng, TUBE if kind == TUBS else CONE)
+        ang = [rng.uniform(0.0, 2 * np.pi), rng.uniform(0.3, 2 * np.pi - 0.3)]
+        return np.concatenate([par[:3] if kind == TUBS else par[:5], ang]), rb
     raise ValueError(kind)
 
 
-def _place_daughters(rng, centres, cell_half):
+def _place_daughters(rng, centres, cell_half, kind_cycle=(BOX, TUBE, CONE)):
     nd = len(centres)
-    kinds = np.array([i % 3 for i in range(nd)], np.int32)
+    kinds = np.array([kind_cycle[i % len(kind_cycle)] for i in range(nd)], np.int32)
     pars = np.zeros((nd, NPAR))
     rots = np.zeros((nd, 9))
     trs = np.zeros((nd, 3))
@@ -251,6 +262,19 @@ def toy_detector_volume(seed: int = 1200) -> Volume:
     cs = [-150.0, -50.0, 50.0, 150.0]
     centres = [(x, y, z) for z in (-100.0, 100.0) for y in cs for x in cs]
     kinds, pars, rots, trs, bound = _place_daughters(rng, centres, 50.0)
+    return Volume(BOX, np.array([MOTHER_HALF] * 3 + [0.0, 0.0]), kinds, pars, rots, trs, bound)
+
+
+def segmented_detector_volume(seed: int = 1250) -> Volume:
+    """The toy detector's layout (mother box (200)^3, 32 daughters on the
+    4 x 4 x 2 grid of cells) with daughter i of kind i mod 5: box, tube,
+    cone, tube segment, cone segment; segments cut to phi1 ~ U[0, 2 pi),
+    dphi ~ U[0.3, 2 pi - 0.3] (convex and non-convex ranges)."""
+    rng = np.random.default_rng(seed)
+    cs = [-150.0, -50.0, 50.0, 150.0]
+    centres = [(x, y, z) for z in (-100.0, 100.0) for y in cs for x in cs]
+    kinds, pars, rots, trs, bound = _place_daughters(rng, centres, 50.0,
+                                                     (BOX, TUBE, CONE, TUBS, CONS))
     return Volume(BOX, np.array([MOTHER_HALF] * 3 + [0.0, 0.0]), kinds, pars, rots, trs, bound)
 
 

@@ -67,6 +67,14 @@ def test_shape_validation_without_device(gv):
     assert _bad_shape_call(gv, 2, [20, 0, 10, 25, 20]) == -1        # rmin2 > rmax2
     assert _bad_shape_call(gv, 0, [np.nan, 1, 1, 0, 0]) == -1
     assert b"rmin" in lib.geo_strerror(_bad_shape_call(gv, 1, [16, 15, 20, 0, 0]))
+    assert _bad_shape_call(gv, 3, [1, 2, 3, 0.5, 0.0]) == -1        # dphi = 0
+    assert _bad_shape_call(gv, 3, [1, 2, 3, 0.5, 6.3]) == -1        # dphi > 2 pi
+    assert _bad_shape_call(gv, 4, [3, 0, 2, 0, 2, 0.0, -1]) == -1   # dphi < 0
+    assert _bad_shape_call(gv, 4, [3, 0, 2, 0, 2, np.inf, 1]) == -1 # phi1 not finite
+    assert _bad_shape_call(gv, 3, [2, 1, 3, 0.0, 1.0]) == -1        # base: rmin > rmax
+    assert b"dphi" in lib.geo_strerror(_bad_shape_call(gv, 3, [1, 2, 3, 0.5, 0.0]))
+    assert _bad_shape_call(gv, 3, [1, 2, 3, 0.5, 2 * np.pi]) == 0   # full turn is valid
+    assert _bad_shape_call(gv, 0, [1, 2, 3, np.nan, np.nan]) == 0   # unread parameters ignored
     s = gv.make_shape(0, [10, 20, 30])
     t = gv.GeoTracks(None, None, None, None, None, None, 5)          # NULL arrays with n > 0
     assert lib.geo_shape_query(C.byref(s), 0, t, None, None) == -1

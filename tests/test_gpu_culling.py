@@ -90,7 +90,9 @@ def test_census_counts(gv):
     n = int(wl.basket_n.sum())
     pairs = int(sum(int(wl.basket_n[b]) * wl.volumes[int(wl.basket_volume[b])].nd
                     for b in range(len(wl.basket_n))))
-    assert c_on[7] == n and c_off[7] == n
-    assert sum(c_off[:6]) == pairs and c_off[6] == 0
-    assert c_on[6] == pairs and 0 < sum(c_on[:6]) < pairs
+    T, Q = gv.CENSUS_TRACKS, gv.CENSUS_CULL
+    assert len(c_on) == gv.CENSUS_SLOTS
+    assert c_on[T] == n and c_off[T] == n
+    assert sum(c_off[:10]) == pairs and c_off[Q] == 0
+    assert c_on[Q] == pairs and 0 < sum(c_on[:10]) < pairs
     g.close()

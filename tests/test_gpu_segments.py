@@ -1,0 +1,224 @@
+"""Parity of the segmented tube and cone (kinds 3 and 4) on the GPU: the
+shape queries on nine segment variants and on tracks lying in the face
+planes or crossing the axis, and every navigator entry point (basket,
+safety, locate, batched, adjoint) on a detector whose daughters include
+segments."""
+import numpy as np
+import pytest
+
+from paper_1312_0816_amd import workloads as W
+from tests.parity import check_values, rel_diff
+from tests.test_gpu_navigator import check_nav, run_nav
+from tests.test_gpu_shapes import compare, gpu_query
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gv():
+    import torch
+    from paper_1312_0816_amd import geonav
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    geonav.load_library()
+    return geonav
+
+
+def _bits(a):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    return a.view(np.int64) if a.dtype == np.float64 else a
+
+
+@pytest.mark.parametrize("v", range(len(W.SEGMENT_VARIANTS)))
+def test_segment_variants(gv, orc, v):
+    """Narrow, right-angle, half, wide and nearly full ranges, with and
+    without a hole: 20000 suite tracks each, all four queries."""
+    kind, par = W.SEGMENT_VARIANTS[v]
+    _, _, t = W.shape_suite_c1(kind, n=20000, seed=3100 + v, par=par)
+    print(compare(gv, orc, kind, par, t, f"variant {v}"))
+
+
+def _face_plane_tracks(rng, phi, n, span=30.0):
+    """Origins in the plane through the z axis at azimuth phi (both halves),
+    half of them moving within that plane, half isotropic."""
+    s = rng.uniform(-span, span, n)
+    z = rng.uniform(-span, span, n)
+    p = np.stack([s * np.cos(phi), s * np.sin(phi), z])
+    u = np.stack(W.isotropic(rng, n))
+    inplane = rng.uniform(size=n) < 0.5
+    a = rng.uniform(0, 2 * np.pi, n)
+    u_in = np.stack([np.cos(a) * np.cos(phi), np.cos(a) * np.sin(phi), np.sin(a)])
+    u = np.where(inplane[None, :], u_in, u)
+    return np.concatenate([p, u])
+
+
+def test_face_planes_and_axis(gv, orc):
+    """Tracks starting in a face's plane (on the face, on its mirror half, in
+    the hole's part), moving within the plane or not, and tracks through the
+    z axis (where the two face planes meet). Degenerate tracks are exempted
+    only by the parity rules (ill-conditioning, 1e-9 of the surface); origins
+    on a face are within 1e-9 of the surface by construction, so up to a
+    quarter of these tracks may be exempt."""
+    rng = np.random.default_rng(41)
+    for v in (0, 1, 3, 5, 6):
+        kind, par = W.SEGMENT_VARIANTS[v]
+        phi1, dphi = W.segment_range(kind, par)
+        parts = [_face_plane_tracks(rng, phi1, 3000), _face_plane_tracks(rng, phi1 + dphi, 3000)]
+        # through the axis: origin off-axis, aimed at an axis point
+        m = 3000
+        p = rng.uniform(-30, 30, (3, m))
+        target = np.stack([np.zeros(m), np.zeros(m), rng.uniform(-10, 10, m)])
+        u = target - p
+        u /= np.linalg.norm(u, axis=0)
+        parts.append(np.concatenate([p, u]))
+        t = np.ascontiguousarray(np.concatenate(parts, axis=1))
+        print(compare(gv, orc, kind, par, t, f"face planes variant {v}", max_exempt_frac=0.25))
+
+
+def test_full_turn_segment_is_the_base_on_gpu(gv):
+    """dphi = 2 pi is stored as the base kind: identical bits."""
+    for kind in (W.TUBS, W.CONS):
+        par = W.SUITE_SHAPES[kind].copy()
+        par[-1] = 2 * np.pi
+        base = W.TUBE if kind == W.TUBS else W.CONE
+        _, _, t = W.shape_suite_c1(kind, n=20000, seed=8)
+        for q in (0, 1, 2, 3):
+            a = gpu_query(gv, kind, par, q, t)
+            b = gpu_query(gv, base, par[:5], q, t)
+            assert np.array_equal(_bits(a), _bits(b))
+
+
+def test_segment_errors(gv):
+    import torch
+    t = torch.zeros((6, 8), dtype=torch.float64, device="cuda")
+    for kind, par in ((W.TUBS, [1, 2, 3, 0.0, 0.0]), (W.TUBS, [1, 2, 3, 0.0, 7.0]),
+                      (W.CONS, [3, 0, 2, 0, 2, np.nan, 1.0]), (W.CONS, [3, 0, 2, 0, 2, 0.0, -1.0])):
+        with pytest.raises(gv.GeoError, match="segment|non-finite"):
+            gv.geo_shape_query(kind, par, 0, t)
+
+
+# ----------------------------------------------------------- navigator
+@pytest.mark.parametrize("n", [1, 65, 4099])
+def test_segmented_detector_ragged(gv, orc, n):
+    vol = W.segmented_detector_volume()
+    t = W.tracks_in_mother(np.random.default_rng(1260 + n), vol, n)
+    step, hit = run_nav(gv, vol, t)
+    check_nav(orc, vol, t, step, hit, what=f"segmented n={n}")
+
+
+def test_segmented_detector_sampled(gv, orc):
+    """2^20 tracks in one launch; 12000 sampled tracks compared with the
+    oracle; every daughter, segments included, is hit."""
+    vol = W.segmented_detector_volume()
+    t = W.tracks_in_mother(np.random.default_rng(1261), vol, 1 << 20)
+    step, hit = run_nav(gv, vol, t)
+    assert not np.isnan(step).any() and np.all(step > 0)
+    assert len(np.unique(hit)) == vol.nd + 1
+    idx = np.sort(np.random.default_rng(5).choice(t.shape[1], size=12000, replace=False))
+    print(check_nav(orc, vol, np.ascontiguousarray(t[:, idx]), step[idx], hit[idx],
+                    what="segmented sampled"))
+
+
+def test_segmented_detector_aimed_at_faces(gv, orc):
+    """Tracks aimed at points of the segments' flat faces and cut edges, so
+    that face entries decide many steps."""
+    vol = W.segmented_detector_volume()
+    rng = np.random.default_rng(1262)
+    segs = [k for k in range(vol.nd) if vol.kinds[k] in (W.TUBS, W.CONS)]
+    origins, dirs = [], []
+    for k in segs:
+        par = vol.pars[k]
+        bk = W.TUBE if vol.kinds[k] == W.TUBS else W.CONE
+        q = np.stack(W._sample_in_shape(rng, bk, par[:5], 400))
+        phi1, dphi = W.segment_range(vol.kinds[k], par)
+        ph = phi1 + dphi * rng.integers(0, 2, 400)                  # onto one face
+        r = np.hypot(q[0], q[1])
+        q = np.stack([r * np.cos(ph), r * np.sin(ph), q[2]])
+        aim = vol.rots[k].reshape(3, 3) @ q + vol.trs[k][:, None]
+        o = W.tracks_in_mother(rng, vol, 400)[:3]
+        u = aim - o
+        u /= np.linalg.norm(u, axis=0)
+        origins.append(o)
+        dirs.append(u)
+    t = np.ascontiguousarray(np.concatenate([np.concatenate(origins, 1), np.concatenate(dirs, 1)]))
+    offs = rng.uniform(-1, 1, (vol.nd, 3))
+    step, hit = run_nav(gv, vol, t, offsets=offs)
+    print(check_nav(orc, vol, t, step, hit, offsets=offs, what="aimed at faces"))
+
+
+def test_segmented_safety_and_locate(gv, orc):
+    import torch
+    from tests.test_gpu_safety_locate import _points
+    vol = W.segmented_detector_volume()
+    p = _points(vol, 20000, 1263)
+    g = gv.Geometry([vol])
+    tp = torch.from_numpy(p).cuda()
+    s = gv.geo_navigate_safety(g, 0, tp).cpu().numpy()
+    w = gv.geo_locate(g, 0, tp).cpu().numpy()
+    ref = orc.navigate_safety(vol, p, None, "ld")
+    ill = rel_diff(orc.navigate_safety(vol, p, None, "d"), ref) > 1e-13
+    print(check_values(s, ref, ill, "segmented safety"))
+    near = ref < 1e-9
+    assert np.array_equal(w[~near], orc.locate(vol, p, None, "ld")[~near])
+    assert len(np.unique(w)) == vol.nd + 2
+    g.close()
+
+
+def test_segmented_batched_bit_identical(gv, orc):
+    """Batched navigation over segmented and plain volumes equals the
+    per-basket navigator bit for bit, and the oracle."""
+    import torch
+    vols = [W.segmented_detector_volume(1250 + i) for i in range(4)] + [W.toy_detector_volume()]
+    rng = np.random.default_rng(1264)
+    sizes = [37, 4099, 64, 1000, 2500, 1, 777]
+    parts, bv, bo, bn, off = [], [], [], [], 0
+    for i, n in enumerate(sizes):
+        v = i % len(vols)
+        parts.append(W.tracks_in_mother(rng, vols[v], n))
+        bv.append(v)
+        bo.append(off)
+        bn.append(n)
+        off += n
+    tr = np.ascontiguousarray(np.concatenate(parts, axis=1))
+    g = gv.Geometry(vols)
+    t = torch.from_numpy(tr).cuda()
+    sb, hb = gv.geo_navigate_batched(g, bv, bo, bn, t)
+    sb, hb = sb.cpu().numpy(), hb.cpu().numpy()
+    for b in range(len(sizes)):
+        sl = slice(bo[b], bo[b] + bn[b])
+        s1, h1 = gv.geo_navigate_basket(g, bv[b], t[:, sl].contiguous())
+        assert np.array_equal(_bits(s1), _bits(sb[sl])) and np.array_equal(h1.cpu().numpy(), hb[sl])
+        check_nav(orc, vols[bv[b]], np.ascontiguousarray(tr[:, sl]), sb[sl], hb[sl],
+                  what=f"batched basket {b}")
+    g.close()
+
+
+def test_segmented_adjoint_matches_fd(gv, orc):
+    """Gradients of L = sum |hit point - target|^2 through the segmented
+    detector (face planes among the surfaces that set steps) against the
+    oracle's central differences on smooth tracks."""
+    import torch
+    from tests.test_gpu_adjoint import _close, _oracle_upstream
+    vol = W.segmented_detector_volume()
+    rng = np.random.default_rng(1265)
+    tr = W.tracks_in_mother(rng, vol, 6000)
+    targets = rng.uniform(-200, 200, (3, tr.shape[1]))
+    offs = rng.uniform(-1, 1, (vol.nd, 3))
+    gh = _oracle_upstream(orc, vol, tr, targets, offs)
+    fd = orc.navigate_fd(vol, tr, offs, None, gh)
+    m = fd["mask"]
+    assert m.mean() > 0.9
+    sub = np.ascontiguousarray(tr[:, m])
+    ghs = np.ascontiguousarray(gh[:, m])
+    want = np.zeros((vol.nd, 3))
+    for k in range(vol.nd):
+        sel = fd["hit"][m] == k
+        want[k] = fd["g_off_hit"][:, m][:, sel].sum(axis=1)
+    g = gv.Geometry([vol])
+    o = torch.from_numpy(np.ascontiguousarray(sub[:3])).cuda()
+    d = torch.from_numpy(np.ascontiguousarray(sub[3:])).cuda()
+    go, gd, goff = gv.geo_navigate_backward(g, 0, o, d, torch.from_numpy(offs).cuda(), None,
+                                            torch.from_numpy(ghs).cuda())
+    _close(go.cpu().numpy(), fd["g_o"][:, m], "g_o")
+    _close(gd.cpu().numpy(), fd["g_d"][:, m], "g_d")
+    _close(goff.cpu().numpy(), want, "g_off")
+    g.close()
