@@ -216,17 +216,24 @@ struct geo_geometry {
     int waves_per_simd = 4;
     bool cull = true;               // wavefront bounding-sphere culling in the navigators
     // Basket lists are staged in a ring of mapped pinned host buffers that the
-    // tile-expansion kernel reads directly (no copy node); a buffer is reused
-    // once the graph launch that read it has completed.
+    // tile-expansion kernel reads directly (no copy node). The ring holds
+    // kGroups groups of kGroup buffers; one event, recorded after the launch
+    // that uses a group's last buffer, guards the whole group, so a call
+    // records an event only every kGroup calls (an event record costs about
+    // as much as 3% of a launch on the batched workload). Before a group is
+    // refilled the host waits for its event.
     struct Stage {
         void *host = nullptr;
         void *dev = nullptr;
         size_t cap = 0;
+    };
+    struct StageGroup {
         hipEvent_t done = nullptr;
         bool pending = false;
     };
-    static constexpr int kStages = 4;
+    static constexpr int kGroup = 4, kGroups = 4, kStages = kGroup * kGroups;
     Stage stage[kStages];
+    StageGroup group[kGroups];
     int stage_next = 0;
     Tile *d_tiles = nullptr;
     int64_t tiles_cap = 0;
@@ -354,8 +361,8 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         e = hipMemcpy(g->d_cull, cul.data(), sizeof(CullRec) * cul.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy culling records"));
     }
-    for (auto &st : g->stage) {
-        e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+    for (auto &gr : g->group) {
+        e = hipEventCreateWithFlags(&gr.done, hipEventDisableTiming);
         if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventCreate"));
     }
     *out = g;
@@ -369,10 +376,10 @@ int geo_geometry_destroy(geo_geometry *g) {
     if (dev != g->device) (void)hipSetDevice(g->device);
     (void)hipDeviceSynchronize();
     destroy_graph(g);
-    for (auto &st : g->stage) {
-        if (st.done) (void)hipEventDestroy(st.done);
+    for (auto &gr : g->group)
+        if (gr.done) (void)hipEventDestroy(gr.done);
+    for (auto &st : g->stage)
         if (st.host) (void)hipHostFree(st.host);
-    }
     (void)hipFree(g->d_vols);
     (void)hipFree(g->d_dau);
     (void)hipFree(g->d_cull);
@@ -489,9 +496,12 @@ namespace {
 // device tile buffer large enough for ntiles tiles.
 int ensure_capacity(geo_geometry *g, int nb, int64_t ntiles, hipStream_t stream) {
     const size_t need = sizeof(BasketRec) * (size_t)nb + sizeof(int64_t) * (size_t)(nb + 1);
+    if (g->stage_next % geo_geometry::kGroup == 0) {  // refilling a group: its last use is done
+        geo_geometry::StageGroup &gr = g->group[g->stage_next / geo_geometry::kGroup];
+        if (gr.pending) GN_HIP(hipEventSynchronize(gr.done));
+        gr.pending = false;
+    }
     geo_geometry::Stage &st = g->stage[g->stage_next];
-    if (st.pending) GN_HIP(hipEventSynchronize(st.done));
-    st.pending = false;
     if (need > st.cap) {
         if (st.host) (void)hipHostFree(st.host);
         st.host = st.dev = nullptr;
@@ -514,6 +524,18 @@ int ensure_capacity(geo_geometry *g, int nb, int64_t ntiles, hipStream_t stream)
             return fail(GEO_ERR_NOMEM, "device tile allocation failed");
         g->tiles_cap = cap;
     }
+    return GEO_OK;
+}
+
+// After a launch that read the current staging buffer: close its group with
+// an event when it was the group's last buffer, and move on.
+int advance_stage(geo_geometry *g, hipStream_t stream) {
+    if (g->stage_next % geo_geometry::kGroup == geo_geometry::kGroup - 1) {
+        geo_geometry::StageGroup &gr = g->group[g->stage_next / geo_geometry::kGroup];
+        GN_HIP(hipEventRecord(gr.done, stream));
+        gr.pending = true;
+    }
+    g->stage_next = (g->stage_next + 1) % geo_geometry::kStages;
     return GEO_OK;
 }
 
@@ -577,10 +599,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
         GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));
         GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true), dim3(grid), dim3(kBlock), pargs, 0,
                                stream));
-        GN_HIP(hipEventRecord(st.done, stream));
-        st.pending = true;
-        g->stage_next = (g->stage_next + 1) % geo_geometry::kStages;
-        return GEO_OK;
+        return advance_stage(g, stream);
     }
     hipKernelNodeParams kb = {};
     kb.func = const_cast<void *>(build_tiles_kernel());
@@ -615,10 +634,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     }
     g->graph_grid = grid;
     GN_HIP(hipGraphLaunch(g->exec, stream));
-    GN_HIP(hipEventRecord(st.done, stream));
-    st.pending = true;
-    g->stage_next = (g->stage_next + 1) % geo_geometry::kStages;
-    return GEO_OK;
+    return advance_stage(g, stream);
 }
 
 int validate_batched(const geo_geometry *g, const geo_basket *b, int32_t nb, const geo_tracks &all,
@@ -797,10 +813,16 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
         for (int W : Ws) {
             g->tracks_per_lane = U;
             g->waves_per_simd = W;
+            // steady state, as in a transport loop: the mean of kBurst
+            // back-to-back calls, best of two bursts after a warm-up call
+            // (which also builds the graph for this shape)
+            constexpr int kBurst = 6;
             float tmin = 1e30f;
-            for (int rep = 0; rep < 4 && rc == GEO_OK; ++rep) {
+            rc = launch_batched(g, b, nb, all, step, hit, stream);
+            for (int rep = 0; rep < 2 && rc == GEO_OK; ++rep) {
                 (void)hipEventRecord(e0, stream);
-                rc = launch_batched(g, b, nb, all, step, hit, stream);
+                for (int k = 0; k < kBurst && rc == GEO_OK; ++k)
+                    rc = launch_batched(g, b, nb, all, step, hit, stream);
                 (void)hipEventRecord(e1, stream);
                 if (rc) break;
                 if (hipEventSynchronize(e1) != hipSuccess) {
@@ -809,7 +831,7 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
                 }
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rep > 0) tmin = std::min(tmin, ms);  // first run warms up
+                tmin = std::min(tmin, ms / kBurst);
             }
             if (rc) break;
             if (tmin < best) {
