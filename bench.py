@@ -54,16 +54,30 @@ FLOPS_DIST_OUT = [               # census slot 2 * kind + hole
                                  # + two face entries (19 each)
     112, 137,                    # cone segment: likewise, face entries 25 each
 ]
+# polycone with ns sections (census slots 10..13: uncut, uncut with a hole,
+# cut, cut with a hole): r^2 and the two end planes (22), per section the
+# outer nappe entry (18) and, with a hole, the inner one (18); cut: range
+# tests (6 + 6 per section) and the face entries (15 + 8 per section)
+FLOPS_PCON_BASE, FLOPS_PCON_NAPPE = 22, 18
+FLOPS_PCON_CUT_BASE, FLOPS_PCON_CUT_SECTION = 21, 14
 
 
-def census_flops(counts, cull: bool) -> float:
-    """FP64 flops of one launch from its census counts."""
+def pcon_flops(ns: float, hole: bool, cut: bool) -> float:
+    f = FLOPS_PCON_BASE + FLOPS_PCON_NAPPE * ns * (2 if hole else 1)
+    return f + ((FLOPS_PCON_CUT_BASE + FLOPS_PCON_CUT_SECTION * ns) if cut else 0)
+
+
+def census_flops(counts, cull: bool, pcon_sections: float = 0.0) -> float:
+    """FP64 flops of one launch from its census counts; pcon_sections is the
+    mean number of sections of the polycones evaluated."""
     from paper_1312_0816_amd import geonav as gv
     f = counts[gv.CENSUS_TRACKS] * (FLOPS_MOTHER_BOX + (FLOPS_TRACK_CULL if cull else 0))
     f += counts[gv.CENSUS_CULL] * FLOPS_CULL_TEST
     per_eval_extra = FLOPS_ROTATION + (0 if cull else 3)   # with culling, w = p - T belongs to the test
     for slot in range(len(FLOPS_DIST_OUT)):
         f += counts[slot] * (per_eval_extra + FLOPS_DIST_OUT[slot])
+    for slot in range(10, 14):
+        f += counts[slot] * (per_eval_extra + pcon_flops(pcon_sections, slot % 2 == 1, slot >= 12))
     return float(f)
 
 
@@ -95,7 +109,7 @@ def measure_rows(gv, W, dev):
     qbytes = {0: 25, 1: 32, 2: 56, 3: 56}
     qname = {0: "contains", 1: "safety", 2: "dist_in", 3: "dist_out"}
     shapes = {}
-    for kind in (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS):
+    for kind in (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON):
         _, par, tr = W.shape_suite_c1(kind)
         big = torch.from_numpy(tr).to(dev).repeat(1, 64).contiguous()   # 2^26 tracks
         n = big.shape[1]
@@ -127,7 +141,7 @@ def measure_rows(gv, W, dev):
     rows["navigator_toy_detector_2^22"] = {"ms": ms, "tracks_per_s": n / (ms * 1e-3),
                                           "TFLOPs": fl / (ms * 1e-3) / 1e12,
                                           "alu_frac": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                                          "evaluated_fraction": sum(counts[:10]) / max(1, counts[gv.CENSUS_CULL])}
+                                          "evaluated_fraction": sum(counts[:14]) / max(1, counts[gv.CENSUS_CULL])}
     saf = torch.empty(n, dtype=torch.float64, device=dev)
     ms_s = _time_ms(lambda: gv._check(lib.geo_navigate_safety(g.handle, 0, trs, None, gv._ptr(saf), hs)))
     ms_l = _time_ms(lambda: gv._check(lib.geo_locate(g.handle, 0, trs, None, hp, hs)))
@@ -136,7 +150,7 @@ def measure_rows(gv, W, dev):
     g.close()
     del t, step, hit, saf
 
-    vol = W.segmented_detector_volume()
+    vol = W.mixed_detector_volume()
     tr = W.tracks_in_mother(np.random.default_rng(1270), vol, 1 << 22)
     g = gv.Geometry([vol])
     t = torch.from_numpy(tr).to(dev)
@@ -147,12 +161,13 @@ def measure_rows(gv, W, dev):
     lib, hs = g._lib, gv._stream()
     ms = _time_ms(lambda: gv._check(lib.geo_navigate_basket(g.handle, 0, trs, None, sp, hp, None, hs)))
     _, _, counts = gv.geo_navigate_batched_census(g, [0], [0], [n], t)
-    fl = census_flops(counts, True)
-    rows["navigator_segmented_detector_2^22"] = {
+    ns = [int(vol.pars[k][2]) - 1 for k in range(vol.nd) if vol.kinds[k] == W.PCON]
+    fl = census_flops(counts, True, float(np.mean(ns)) if ns else 0.0)
+    rows["navigator_mixed_detector_2^22"] = {
         "ms": ms, "tracks_per_s": n / (ms * 1e-3), "TFLOPs": fl / (ms * 1e-3) / 1e12,
         "alu_frac": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-        "evaluated_fraction": sum(counts[:10]) / max(1, counts[gv.CENSUS_CULL]),
-        "daughters": "32: box, tube, cone, tube segment, cone segment in turn"}
+        "evaluated_fraction": sum(counts[:14]) / max(1, counts[gv.CENSUS_CULL]),
+        "daughters": "32: box, tube, cone, tube segment, cone segment, polycone in turn"}
     g.close()
     del t, step, hit
 
@@ -475,9 +490,9 @@ def main():
                                     "ms_per_step": nocull_ms, "flops_per_launch": flops_nocull,
                                     "achieved_TFLOPs": flops_nocull / (nocull_ms * 1e-3) / 1e12,
                                     "frac": flops_nocull / (nocull_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
-        "census": {"evaluations_by_kind_hole": counts[:10], "cull_tests": counts[gv.CENSUS_CULL],
+        "census": {"evaluations_by_kind_hole": counts[:14], "cull_tests": counts[gv.CENSUS_CULL],
                    "tracks": counts[gv.CENSUS_TRACKS],
-                   "evaluations_without_culling": int(sum(counts_nocull[:10]))},
+                   "evaluations_without_culling": int(sum(counts_nocull[:14]))},
         "batched_equals_plain_bitwise": same,
         "kernel_source": digest,
     }

@@ -28,6 +28,13 @@
  *            [phi1, phi1 + dphi] (radians, 0 < dphi <= 2 pi), z axis included
  *            (section 3.1 names the segmented forms of tube and cone); two
  *            flat faces close the cut. dphi = 2 pi is the uncut base solid.
+ *   GEO_PCON par = {phi1, dphi, nz, z_0, rmin_0, rmax_0, ..., z_{nz-1},
+ *            rmin_{nz-1}, rmax_{nz-1}}   the polycone (section 3.1: a sequence
+ *            of connected cone and tube sections, "few z segments"): nz planes,
+ *            2 <= nz <= GEO_PCON_MAX_PLANES (an integral value), z strictly
+ *            increasing, 0 <= rmin <= rmax at each plane; between consecutive
+ *            planes both radii vary linearly in z. Cut to [phi1, phi1 + dphi]
+ *            like the segments (dphi = 2 pi: uncut).
  *   Parameters beyond those a kind reads are ignored.
  *   Shapes are closed sets. Directions are not renormalised: distances are
  *   the ray parameter t of p + t*d (the length when |d| = 1).
@@ -45,9 +52,11 @@ extern "C" {
 
 #define GEO_BIG 1e30
 #define GEO_MAX_DAUGHTERS 1024
-#define GEO_CENSUS_SLOTS 12
+#define GEO_CENSUS_SLOTS 16
+#define GEO_PCON_MAX_PLANES 8
+#define GEO_NPAR (3 + 3 * GEO_PCON_MAX_PLANES) /* parameters per shape */
 
-enum { GEO_BOX = 0, GEO_TUBE = 1, GEO_CONE = 2, GEO_TUBS = 3, GEO_CONS = 4 };
+enum { GEO_BOX = 0, GEO_TUBE = 1, GEO_CONE = 2, GEO_TUBS = 3, GEO_CONS = 4, GEO_PCON = 5 };
 
 /* Queries of section 3.1: inside/outside check, minimum distance to any
  * boundary, distance along the line of flight to leave / to enter. */
@@ -68,9 +77,9 @@ typedef struct {
 } geo_tracks;
 
 typedef struct {
-    int32_t kind; /* GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS or GEO_CONS */
+    int32_t kind; /* GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS, GEO_CONS or GEO_PCON */
     int32_t _pad;
-    double par[7];
+    double par[GEO_NPAR];
 } geo_shape;
 
 /* Placement of a daughter in its mother (the coordinate transformations of
@@ -105,7 +114,9 @@ typedef struct geo_geometry geo_geometry;
 /* Copy nvol volumes to the current device and return a handle.
  * Validation: kinds known, parameters finite, box half-lengths > 0,
  * 0 <= rmin <= rmax with rmax > 0 (cone: at both ends, rmax1 + rmax2 > 0),
- * dz > 0, segments 0 < dphi <= 2 pi, rotations proper to 1e-12. Errors: GEO_ERR_INVALID_ARG,
+ * dz > 0, segments and polycones 0 < dphi <= 2 pi, polycone planes as
+ * above (each section with rmax > 0 at one of its planes at least),
+ * rotations proper to 1e-12. Errors: GEO_ERR_INVALID_ARG,
  * GEO_ERR_NOMEM, GEO_ERR_HIP; *out is NULL on error. */
 int geo_geometry_create(const geo_volume_desc *volumes, int32_t nvol, geo_geometry **out);
 
@@ -188,19 +199,20 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
  * launches directly (no graph) a variant of the batched kernel that tallies
  * the work it does. counts (host uint64_t[GEO_CENSUS_SLOTS]):
  *   counts[2 * kind + hole]  lane-evaluations of DistFromOutside for daughters
- *                            of that kind (kind 0..4, hole = 1 for a tube,
- *                            cone or segment with an inner surface): every
- *                            active lane of a wavefront that evaluates the
- *                            daughter,
- *   counts[10]               lane culling tests (0 with culling off),
- *   counts[11]               tracks navigated (mother DistFromInside).
+ *                            of that kind (kind 0..4 as above, 5 an uncut
+ *                            polycone, 6 a cut one; hole = 1 for a shape with
+ *                            an inner surface): every active lane of a
+ *                            wavefront that evaluates the daughter,
+ *   counts[14]               lane culling tests (0 with culling off),
+ *   counts[15]               tracks navigated (mother DistFromInside).
  * Synchronises the stream. */
 int geo_navigate_batched_census(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
                                 double *step, int32_t *hit, uint64_t counts[GEO_CENSUS_SLOTS],
                                 hipStream_t stream);
 
 /* Time the candidate launch shapes of the batched kernel (tracks per lane
- * 1/2/4/8 x waves per SIMD 0/2/3/4/6/8) on these baskets and keep the fastest in the handle; also records
+ * 1/2/4/8 x waves per SIMD 0/2/3/4/6/8) on these baskets, as bursts of
+ * back-to-back calls after a warm-up, and keep the fastest in the handle; also records
  * it in the JSON cache named by the GEONAV_AUTOTUNE_CACHE environment
  * variable, if set. Writes step/hit scratch internally; synchronises the
  * stream. */

@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle_body.h")]
 
-BOX, TUBE, CONE, TUBS, CONS = 0, 1, 2, 3, 4
+BOX, TUBE, CONE, TUBS, CONS, PCON = 0, 1, 2, 3, 4, 5
 CONTAINS, SAFETY, DIST_IN, DIST_OUT = 0, 1, 2, 3
 BIG = 1e30
 
@@ -80,11 +80,11 @@ def _f64(a, shape=None):
     return a
 
 
-NPAR = 7
+NPAR = 27      # 3 + 3 x 8 polycone planes
 
 
-def _par7(par):
-    """Shape parameters padded with zeros to the 7 the library reads."""
+def _parn(par):
+    """Shape parameters padded with zeros to the NPAR the library reads."""
     p = np.zeros(NPAR)
     v = np.asarray(par, np.float64).reshape(-1)
     p[:v.size] = v
@@ -105,7 +105,7 @@ def shape_query(kind: int, par, query: int, tracks, prec: str = "d"):
     lib = _load()
     t = _tracks(tracks)
     n = t.shape[1]
-    par = _par7(par)
+    par = _parn(par)
     vals = np.zeros(n, np.float64)
     ins = np.zeros(n, np.uint8)
     rows = [t[i] for i in range(6)]

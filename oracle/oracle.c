@@ -1,8 +1,8 @@
 /*
  * CPU oracle for the basket shape queries and the simple navigator of
  * "Vectorising the detector geometry to optimize particle transport"
- * (section 3, Fig. 1, and section 3.1): box, tube, cone and the segmented
- * tube and cone.
+ * (section 3, Fig. 1, and section 3.1): box, tube, cone, the segmented
+ * tube and cone, and the polycone with few z sections.
  *
  * TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the CPU
  * baseline of the benchmark load this library; the product path (the HIP
@@ -37,6 +37,7 @@
 #define OR_CONE 2
 #define OR_TUBS 3
 #define OR_CONS 4
+#define OR_PCON 5
 
 #define OR_CONTAINS 0
 #define OR_SAFETY 1
@@ -44,9 +45,10 @@
 #define OR_DIST_OUT 3
 
 #define OR_BIG 1e30
-#define OR_NPAR 7                /* parameters per shape */
+#define OR_PCON_MAX 8            /* z planes of a polycone */
+#define OR_NPAR (3 + 3 * OR_PCON_MAX)   /* parameters per shape */
 #define OR_MAX_DAUGHTERS 1024
-#define OR_MAX_IVAL 8            /* line intervals of one shape */
+#define OR_MAX_IVAL (5 * OR_PCON_MAX)   /* line intervals of one shape */
 #define OR_TWO_PI 6.283185307179586476925286766559005768L
 #define OR_FULL_TURN ((double)OR_TWO_PI)   /* dphi at or above: uncut */
 

@@ -13,15 +13,16 @@
  * Closed-set membership test ("inside/outside checks", section 3.1).      */
 static int FN(in_wedge)(R phi1, R dphi, R x, R y);
 static int FN(segment)(int kind, const double *par, int *base, R *phi1, R *dphi);
+static int FN(pcon_in_profile)(const double *par, R r, R z);
 
 static int FN(contains)(int kind, const double *par, R x, R y, R z)
 {
     int base;
     R phi1, dphi;
-    if (FN(segment)(kind, par, &base, &phi1, &dphi))
-        return FN(contains)(base, par, x, y, z) && FN(in_wedge)(phi1, dphi, x, y);
-    if (kind == OR_TUBS || kind == OR_CONS)      /* uncut: the base solid */
-        return FN(contains)(kind == OR_TUBS ? OR_TUBE : OR_CONE, par, x, y, z);
+    if (FN(segment)(kind, par, &base, &phi1, &dphi) && !FN(in_wedge)(phi1, dphi, x, y)) return 0;
+    if (kind == OR_TUBS) kind = OR_TUBE;           /* in the range (or uncut): the base solid */
+    if (kind == OR_CONS) kind = OR_CONE;
+    if (kind == OR_PCON) return FN(pcon_in_profile)(par, sqrt(x * x + y * y), z);
     if (kind == OR_BOX)
         return fabs(x) <= (R)par[0] && fabs(y) <= (R)par[1] && fabs(z) <= (R)par[2];
     if (kind == OR_TUBE) {
@@ -41,18 +42,52 @@ static int FN(contains)(int kind, const double *par, R x, R y, R z)
 }
 
 /* -------------------------------------------------------------- Segments
- * The segmented tube and cone (section 3.1 lists the shapes "with their
- * segmented forms"): the base solid of revolution cut to the azimuth range
- * [phi1, phi1 + dphi], the z axis included. The leading parameters are the
- * base kind's (TUBS: rmin rmax dz phi1 dphi; CONS: dz rmin1 rmax1 rmin2 rmax2
- * phi1 dphi), angles in radians. dphi at or above 2 pi (as a double) leaves
- * the base uncut. Returns 1 for a cut segment, with the base kind.          */
+ * The segmented tube and cone (section 3.1 names the segmented forms of tube
+ * and cone among the shapes ported) and the polycone: a solid of revolution
+ * cut to the azimuth range [phi1, phi1 + dphi], the z axis included. The
+ * leading parameters of TUBS and CONS are the base kind's (TUBS: rmin rmax
+ * dz phi1 dphi; CONS: dz rmin1 rmax1 rmin2 rmax2 phi1 dphi); the polycone's
+ * range leads its parameters. Angles in radians. dphi at or above 2 pi (as
+ * a double) leaves the solid uncut. Returns 1 for a cut solid, with the
+ * kind of its uncut base.                                                  */
 static int FN(segment)(int kind, const double *par, int *base, R *phi1, R *dphi)
 {
     if (kind == OR_TUBS) { *base = OR_TUBE; *phi1 = par[3]; *dphi = par[4]; }
     else if (kind == OR_CONS) { *base = OR_CONE; *phi1 = par[5]; *dphi = par[6]; }
+    else if (kind == OR_PCON) { *base = OR_PCON; *phi1 = par[0]; *dphi = par[1]; }
     else return 0;
     return *dphi < (R)OR_FULL_TURN;
+}
+
+/* -------------------------------------------------------------- Polycone
+ * A sequence of connected cone and tube sections (section 3.1):
+ * par = {phi1, dphi, nz, z_0, rmin_0, rmax_0, ..., z_{nz-1}, rmin_{nz-1},
+ * rmax_{nz-1}}, 2 <= nz <= OR_PCON_MAX, z strictly increasing; between two
+ * consecutive planes both radii vary linearly in z. In its (r, z) half-plane
+ * the solid's profile is the polygon up the outer radii and back down the
+ * inner ones.                                                             */
+static int FN(pcon_planes)(const double *par, R *z, R *rin, R *rout)
+{
+    int n = (int)par[2];
+    for (int j = 0; j < n; ++j) {
+        z[j] = par[3 + 3 * j];
+        rin[j] = par[4 + 3 * j];
+        rout[j] = par[5 + 3 * j];
+    }
+    return n;
+}
+
+static int FN(pcon_in_profile)(const double *par, R r, R zz)
+{
+    R z[OR_PCON_MAX], rin[OR_PCON_MAX], rout[OR_PCON_MAX];
+    int n = FN(pcon_planes)(par, z, rin, rout);
+    for (int j = 0; j + 1 < n; ++j) {
+        if (zz < z[j] || zz > z[j + 1]) continue;
+        R f = (zz - z[j]) / (z[j + 1] - z[j]);
+        if (r >= rin[j] + (rin[j + 1] - rin[j]) * f && r <= rout[j] + (rout[j + 1] - rout[j]) * f)
+            return 1;
+    }
+    return 0;
 }
 
 /* Azimuth of (x, y) in the closed range [phi1, phi1 + dphi] modulo 2 pi;
@@ -121,17 +156,44 @@ static R FN(quad_dist)(R u, R z, R rin1, R rout1, R rin2, R rout2, R dz)
     return best;
 }
 
+/* Polycone profile: the smallest distance from (u, z) to its edges (the two
+ * end edges, the outer edges and the inner edges; with `axis` 0 an inner
+ * edge lying on the axis is skipped, as it bounds no surface of the uncut
+ * solid), and 0 for a point of the polygon when `solid` is set. */
+static R FN(pcon_edges_dist)(const double *par, R u, R zz, int axis, int solid)
+{
+    if (solid && FN(pcon_in_profile)(par, u, zz)) return 0;
+    R z[OR_PCON_MAX], rin[OR_PCON_MAX], rout[OR_PCON_MAX];
+    int n = FN(pcon_planes)(par, z, rin, rout);
+    R best = FN(seg_dist)(u, zz, rin[0], z[0], rout[0], z[0]);
+    R s = FN(seg_dist)(u, zz, rin[n - 1], z[n - 1], rout[n - 1], z[n - 1]);
+    if (s < best) best = s;
+    for (int j = 0; j + 1 < n; ++j) {
+        s = FN(seg_dist)(u, zz, rout[j], z[j], rout[j + 1], z[j + 1]);
+        if (s < best) best = s;
+        if (!axis && rin[j] == 0 && rin[j + 1] == 0) continue;
+        s = FN(seg_dist)(u, zz, rin[j], z[j], rin[j + 1], z[j + 1]);
+        if (s < best) best = s;
+    }
+    return best;
+}
+
 /* Distance from p to the flat face of a segment at azimuth phi: the profile
- * quadrilateral laid in the half-plane at that azimuth. With u the
- * coordinate along the half-plane's direction (cos phi, sin phi, 0) and v the
- * distance from its plane, it is sqrt(v^2 + dist((u, z), quadrilateral)^2). */
+ * polygon laid in the half-plane at that azimuth. With u the coordinate
+ * along the half-plane's direction (cos phi, sin phi, 0) and v the distance
+ * from its plane, it is sqrt(v^2 + dist((u, z), polygon)^2). */
 static R FN(face_dist)(int kind, const double *par, R phi, R x, R y, R z)
 {
-    R rin1 = 0, rout1 = 0, rin2 = 0, rout2 = 0, dz = 0;
-    FN(profile)(kind, par, &rin1, &rout1, &rin2, &rout2, &dz);
     R c = cos(phi), sn = sin(phi);
     R u = c * x + sn * y, v = -sn * x + c * y;
-    R q = FN(quad_dist)(u, z, rin1, rout1, rin2, rout2, dz);
+    R q;
+    if (kind == OR_PCON) {
+        q = FN(pcon_edges_dist)(par, u, z, 1, 1);
+    } else {
+        R rin1 = 0, rout1 = 0, rin2 = 0, rout2 = 0, dz = 0;
+        FN(profile)(kind, par, &rin1, &rout1, &rin2, &rout2, &dz);
+        q = FN(quad_dist)(u, z, rin1, rout1, rin2, rout2, dz);
+    }
     return sqrt(v * v + q * q);
 }
 
@@ -146,13 +208,18 @@ static R FN(safety)(int kind, const double *par, R x, R y, R z)
          * outside the range it lies on the edge of a face (the face distance
          * covers it). */
         R best = INFINITY;
-        if (FN(in_wedge)(phi1, dphi, x, y)) best = FN(safety)(base, par, x, y, z);
+        if (FN(in_wedge)(phi1, dphi, x, y))
+            best = base == OR_PCON ? FN(pcon_edges_dist)(par, sqrt(x * x + y * y), z, 0, 0)
+                                   : FN(safety)(base, par, x, y, z);
         R s = FN(face_dist)(kind, par, phi1, x, y, z);
         if (s < best) best = s;
         s = FN(face_dist)(kind, par, phi1 + dphi, x, y, z);
         if (s < best) best = s;
         return best;
     }
+    /* uncut polycone: a solid of revolution, so as for tube and cone the
+     * planar distance from (r, z) to the profile's edges */
+    if (kind == OR_PCON) return FN(pcon_edges_dist)(par, sqrt(x * x + y * y), z, 0, 0);
     if (kind == OR_BOX) {
         R ax = fabs(x), ay = fabs(y), az = fabs(z);
         R dx = par[0], dy = par[1], dz = par[2];
@@ -294,13 +361,13 @@ static int FN(line_segment)(int kind, const double *par, const R *p, const R *d,
  * Box: the three slabs intersected (Kay-Kajiya).
  * Tube and cone: (z-slab  and  outer nappe solid)  minus  the open inner
  * nappe solid {r < rin(z)}, which is empty when both inner radii are 0.
- * Segments: see line_segment.                                              */
+ * Segments and polycones: see line_segment.                                */
 static int FN(line_shape)(int kind, const double *par, const R *p, const R *d, FN(ival) *out)
 {
     R lo, hi, a, b;
     int base;
     R phi1, dphi;
-    if (FN(segment)(kind, par, &base, &phi1, &dphi))
+    if (FN(segment)(kind, par, &base, &phi1, &dphi) || kind == OR_PCON)
         return FN(line_segment)(kind, par, p, d, out);
     if (kind == OR_TUBS || kind == OR_CONS)      /* uncut: the base solid */
         kind = kind == OR_TUBS ? OR_TUBE : OR_CONE;
@@ -343,32 +410,44 @@ static int FN(line_shape)(int kind, const double *par, const R *p, const R *d, F
     return n;
 }
 
-/* A segment's boundary lies on the z planes, the outer and inner nappes and
- * the two planes through the axis at azimuths phi1 and phi1 + dphi, so the
- * line's intervals in the solid end at crossings of these surfaces. Split
- * the line at every crossing, test membership (Contains) at one interior
- * point of each open piece and at each crossing, and join neighbouring
- * pieces that belong. Membership is constant on a piece, and the solid is
- * closed: a crossing next to a piece that belongs belongs too. Crossings of
- * a whole plane or of a mirror nappe only split a piece needlessly.       */
+/* A segment's or polycone's boundary lies on its z planes, on the nappes
+ * through the profile's slanted edges and (when cut) on the two planes
+ * through the axis at azimuths phi1 and phi1 + dphi, so the line's intervals
+ * in the solid end at crossings of these surfaces. Split the line at every
+ * crossing, test membership (Contains) at one interior point of each open
+ * piece and at each crossing, and join neighbouring pieces that belong.
+ * Membership is constant on a piece, and the solid is closed: a crossing
+ * next to a piece that belongs belongs too. Crossings of a whole plane, of
+ * a nappe beyond its section or of a mirror nappe only split a piece
+ * needlessly.                                                             */
 static int FN(line_segment)(int kind, const double *par, const R *p, const R *d, FN(ival) *out)
 {
     int base;
-    R phi1 = 0, dphi = 0, rin1 = 0, rout1 = 0, rin2 = 0, rout2 = 0, dz = 0;
-    FN(segment)(kind, par, &base, &phi1, &dphi);
-    FN(profile)(kind, par, &rin1, &rout1, &rin2, &rout2, &dz);
-    R t[8];
-    int m = 0;
-    if (d[2] != 0) {
-        t[m++] = (-dz - p[2]) / d[2];
-        t[m++] = (dz - p[2]) / d[2];
+    R phi1 = 0, dphi = 0;
+    int cut = FN(segment)(kind, par, &base, &phi1, &dphi);
+    /* the profile as a list of planes (z, rin, rout) */
+    R z[OR_PCON_MAX], rin[OR_PCON_MAX], rout[OR_PCON_MAX];
+    int np = 2;
+    if (kind == OR_PCON) {
+        np = FN(pcon_planes)(par, z, rin, rout);
+    } else {
+        R dz = 0;
+        FN(profile)(kind, par, &rin[0], &rout[0], &rin[1], &rout[1], &dz);
+        z[0] = -dz;
+        z[1] = dz;
     }
-    /* nappes r = a + b z through the profile's slanted edges */
-    R ao = (rout1 + rout2) / 2, bo = (rout2 - rout1) / (2 * dz);
-    R ai = (rin1 + rin2) / 2, bi = (rin2 - rin1) / (2 * dz);
-    m += FN(nappe_roots)(ao, bo, p, d, t + m);
-    if (!(rin1 == 0 && rin2 == 0)) m += FN(nappe_roots)(ai, bi, p, d, t + m);
-    for (int i = 0; i < 2; ++i) {
+    R t[5 * OR_PCON_MAX];                       /* np planes + 4 per section + 2 */
+    int m = 0;
+    if (d[2] != 0)
+        for (int j = 0; j < np; ++j) t[m++] = (z[j] - p[2]) / d[2];
+    /* nappes r = a + b z through each section's slanted edges */
+    for (int j = 0; j + 1 < np; ++j) {
+        R h = z[j + 1] - z[j];
+        R bo = (rout[j + 1] - rout[j]) / h, bi = (rin[j + 1] - rin[j]) / h;
+        m += FN(nappe_roots)(rout[j] - bo * z[j], bo, p, d, t + m);
+        if (!(rin[j] == 0 && rin[j + 1] == 0)) m += FN(nappe_roots)(rin[j] - bi * z[j], bi, p, d, t + m);
+    }
+    for (int i = 0; cut && i < 2; ++i) {
         R ph = i == 0 ? phi1 : phi1 + dphi;
         R nx = -sin(ph), ny = cos(ph);             /* normal of the plane at ph */
         R nd = nx * d[0] + ny * d[1];
@@ -388,7 +467,7 @@ static int FN(line_segment)(int kind, const double *par, const R *p, const R *d,
         return 1;
     }
     /* open pieces 0..m (piece i lies between t[i-1] and t[i]) */
-    int piece[9];
+    int piece[5 * OR_PCON_MAX + 1];
     piece[0] = OR_IN_AT(t[0] - (1 + fabs(t[0])));
     for (int i = 1; i < m; ++i) piece[i] = OR_IN_AT(t[i - 1] + (t[i] - t[i - 1]) / 2);
     piece[m] = OR_IN_AT(t[m - 1] + (1 + fabs(t[m - 1])));

@@ -49,15 +49,62 @@ int hip_fail(hipError_t e, const char *where) {
 // Parameters each kind reads (the rest of par[] is ignored).
 static_assert(GEO_CENSUS_SLOTS == kCensusSlots, "census layout");
 
-int nparams(int kind) {
-    switch (kind) {
+int nparams(const geo_shape &s) {
+    switch (s.kind) {
         case GEO_BOX:
         case GEO_TUBE: return 3;
         case GEO_CONE:
         case GEO_TUBS: return 5;
         case GEO_CONS: return 7;
+        case GEO_PCON: {
+            const double nz = s.par[2];
+            if (!(nz >= 2 && nz <= GEO_PCON_MAX_PLANES && nz == std::floor(nz))) return -1;
+            return 3 + 3 * (int)nz;
+        }
         default: return 0;
     }
+}
+
+// Polycone sections: planes (z, rmin, rmax) from par[3..], validated.
+int make_pcon(const double *p, PconRec &pc, double *bound_r, const char *what) {
+    std::memset(&pc, 0, sizeof pc);
+    const int nz = (int)p[2];
+    pc.nz = nz;
+    double rm = 0;
+    for (int j = 0; j < nz; ++j) {
+        pc.z[j] = p[3 + 3 * j];
+        pc.rin[j] = p[4 + 3 * j];
+        pc.rout[j] = p[5 + 3 * j];
+        if (!(pc.rin[j] >= 0 && pc.rin[j] <= pc.rout[j]))
+            return fail(GEO_ERR_INVALID_ARG, "%s: polycone plane %d needs 0 <= rmin <= rmax", what, j);
+        if (j > 0 && !(pc.z[j] > pc.z[j - 1]))
+            return fail(GEO_ERR_INVALID_ARG, "%s: polycone z must increase strictly (plane %d)", what, j);
+        rm = std::max(rm, pc.rout[j]);
+    }
+    for (int j = 0; j + 1 < nz; ++j) {
+        if (!(pc.rout[j] + pc.rout[j + 1] > 0))
+            return fail(GEO_ERR_INVALID_ARG, "%s: polycone section %d has rmax 0 at both planes", what, j);
+        const double h = pc.z[j + 1] - pc.z[j];
+        const double bo = (pc.rout[j + 1] - pc.rout[j]) / h;
+        const double bi = (pc.rin[j + 1] - pc.rin[j]) / h;
+        pc.bo[j] = bo;
+        pc.ao[j] = pc.rout[j] - bo * pc.z[j];
+        if (pc.rin[j] > 0 || pc.rin[j + 1] > 0) {
+            pc.hole_mask |= 1 << j;
+            pc.bi[j] = bi;
+            pc.ai[j] = pc.rin[j] - bi * pc.z[j];
+        }
+        pc.inv_eo[j] = 1.0 / ((pc.rout[j + 1] - pc.rout[j]) * (pc.rout[j + 1] - pc.rout[j]) + h * h);
+        pc.inv_ei[j] = 1.0 / ((pc.rin[j + 1] - pc.rin[j]) * (pc.rin[j + 1] - pc.rin[j]) + h * h);
+    }
+    pc.rin2_0 = pc.rin[0] * pc.rin[0];
+    pc.rout2_0 = pc.rout[0] * pc.rout[0];
+    pc.rin2_l = pc.rin[nz - 1] * pc.rin[nz - 1];
+    pc.rout2_l = pc.rout[nz - 1] * pc.rout[nz - 1];
+    const double zm = std::max(std::fabs(pc.z[0]), std::fabs(pc.z[nz - 1]));
+    pc.eps = 1e-12 * (zm + rm);
+    if (bound_r) *bound_r = std::sqrt(rm * rm + zm * zm);
+    return GEO_OK;
 }
 
 // Base solid of a shape record: box, tube or cone constants.
@@ -118,31 +165,43 @@ int make_base(int kind, const double *p, ShapeRec &out, double *bound_r, const c
     }
 }
 
-// Validate a shape and derive its device record. A segment whose range is a
-// full turn (dphi == 2 pi) is stored as its base kind.
-int make_shape(const geo_shape &s, ShapeRec &out, double *bound_r, const char *what) {
+// Validate a shape and derive its device record (and, for a polycone, its
+// sections in *pc, which must then be non-NULL). A segment or polycone whose
+// range is a full turn (dphi == 2 pi) is stored uncut.
+int make_shape(const geo_shape &s, ShapeRec &out, PconRec *pc, double *bound_r, const char *what) {
     std::memset(&out, 0, sizeof out);
-    const int np = nparams(s.kind);
+    const int np = nparams(s);
     if (np == 0) return fail(GEO_ERR_INVALID_ARG, "%s: unknown shape kind %d", what, s.kind);
+    if (np < 0)
+        return fail(GEO_ERR_INVALID_ARG, "%s: polycone needs an integral nz in 2..%d", what,
+                    GEO_PCON_MAX_PLANES);
     for (int i = 0; i < np; ++i)
         if (!std::isfinite(s.par[i])) return fail(GEO_ERR_INVALID_ARG, "%s: non-finite shape parameter", what);
     const double *p = s.par;
-    const bool seg = s.kind == GEO_TUBS || s.kind == GEO_CONS;
+    const bool pcon = s.kind == GEO_PCON;
+    const bool seg = s.kind == GEO_TUBS || s.kind == GEO_CONS || pcon;
     const int base = s.kind == GEO_TUBS ? GEO_TUBE : s.kind == GEO_CONS ? GEO_CONE : s.kind;
-    const int rc = make_base(base, p, out, bound_r, what);
+    int rc;
+    if (pcon) {
+        if (!pc) return fail(GEO_ERR_INVALID_ARG, "%s: internal: no polycone record", what);
+        rc = make_pcon(p, *pc, bound_r, what);
+        out.hole = pc->hole_mask != 0;
+    } else {
+        rc = make_base(base, p, out, bound_r, what);
+    }
     if (rc != GEO_OK || !seg) {
         out.kind = base;
         return rc;
     }
     const double two_pi = 2.0 * M_PI;
-    const double phi1 = p[np - 2], dphi = p[np - 1];
+    const double phi1 = pcon ? p[0] : p[np - 2], dphi = pcon ? p[1] : p[np - 1];
     if (!(dphi > 0 && dphi <= two_pi))
         return fail(GEO_ERR_INVALID_ARG, "%s: segment needs 0 < dphi <= 2 pi", what);
     if (dphi == two_pi) {
-        out.kind = base;
+        out.kind = pcon ? kPcon : base;
         return GEO_OK;
     }
-    out.kind = s.kind;
+    out.kind = pcon ? kPcons : s.kind;
     out.convex = dphi <= M_PI ? 1 : 0;
     const double phi2 = phi1 + dphi;
     out.c[17] = std::cos(phi1);
@@ -209,6 +268,11 @@ struct geo_geometry {
     VolumeRec *d_vols = nullptr;
     DaughterRec *d_dau = nullptr;
     CullRec *d_cull = nullptr;
+    PconRec *d_pcon = nullptr;       // polycone sections of mothers and daughters
+    // kinds each volume holds (kSetBasic, kSetSeg, kSetAll) and their union:
+    // the navigator kernels are specialised to carry only those
+    std::vector<int> vol_kset;
+    int kset = kSetBasic;
     // adjoint partial sums: kBackwardMaxBlocks x 3 x max_nd
     double *d_partial = nullptr;
     // batched state
@@ -288,6 +352,14 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
     std::vector<VolumeRec> vols(nvol);
     std::vector<DaughterRec> dau;
     std::vector<CullRec> cul;
+    // polycone sections, and which record points at each: volume index
+    // (mother) or -1 - daughter index
+    std::vector<PconRec> pcons;
+    std::vector<int64_t> pcon_owner;
+    std::vector<int> vol_kset(nvol, kSetBasic);
+    auto kind_set = [](int kind) -> int {
+        return kind == kTubs || kind == kCons ? kSetSeg : (kind == kPcon || kind == kPcons ? kSetAll : kSetBasic);
+    };
     int max_nd = 0;
     for (int iv = 0; iv < nvol; ++iv) {
         const geo_volume_desc &d = v[iv];
@@ -295,8 +367,14 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         std::memset(&r, 0, sizeof r);
         char what[64];
         snprintf(what, sizeof what, "volume %d mother", iv);
-        int rc = make_shape(d.mother, r.mother, nullptr, what);
+        PconRec pc;
+        int rc = make_shape(d.mother, r.mother, &pc, nullptr, what);
         if (rc) return rc;
+        if (r.mother.kind == kPcon || r.mother.kind == kPcons) {
+            pcons.push_back(pc);
+            pcon_owner.push_back(iv);
+        }
+        vol_kset[iv] = kind_set(r.mother.kind);
         if (d.ndaughters < 0 || d.ndaughters > GEO_MAX_DAUGHTERS)
             return fail(GEO_ERR_INVALID_ARG, "volume %d: ndaughters %d outside 0..%d", iv, d.ndaughters,
                         GEO_MAX_DAUGHTERS);
@@ -309,8 +387,13 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             DaughterRec dr;
             std::memset(&dr, 0, sizeof dr);
             snprintf(what, sizeof what, "volume %d daughter %d", iv, k);
-            rc = make_shape(d.daughters[k], dr.shape, &dr.bound_r, what);
+            rc = make_shape(d.daughters[k], dr.shape, &pc, &dr.bound_r, what);
             if (rc) return rc;
+            if (dr.shape.kind == kPcon || dr.shape.kind == kPcons) {
+                pcons.push_back(pc);
+                pcon_owner.push_back(-1 - (int64_t)dau.size());
+            }
+            vol_kset[iv] = std::max(vol_kset[iv], kind_set(dr.shape.kind));
             {
                 const double rc2 = dr.bound_r * (1.0 + 1e-6) + 1e-6;
                 dr.cull_r2 = rc2 * rc2;
@@ -342,6 +425,8 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
     g->nvol = nvol;
     g->max_nd = max_nd;
     g->h_vols = vols;
+    g->vol_kset = vol_kset;
+    g->kset = *std::max_element(vol_kset.begin(), vol_kset.end());
     if (hipMalloc(&g->d_vols, sizeof(VolumeRec) * nvol) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of volumes failed"));
     if (!dau.empty() && hipMalloc(&g->d_dau, sizeof(DaughterRec) * dau.size()) != hipSuccess)
@@ -353,6 +438,17 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of adjoint partials failed"));
     if (hipMalloc(&g->d_cursors, sizeof(unsigned int) * kQueues * kQueueStride) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of the queue cursors failed"));
+    if (!pcons.empty()) {
+        if (hipMalloc(&g->d_pcon, sizeof(PconRec) * pcons.size()) != hipSuccess)
+            return cleanup(fail(GEO_ERR_NOMEM, "device allocation of polycone sections failed"));
+        for (size_t i = 0; i < pcons.size(); ++i) {
+            const int64_t o = pcon_owner[i];
+            if (o >= 0) vols[o].pcon = g->d_pcon + i;
+            else dau[-1 - o].pcon = g->d_pcon + i;
+        }
+        e = hipMemcpy(g->d_pcon, pcons.data(), sizeof(PconRec) * pcons.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy polycone sections"));
+    }
     e = hipMemcpy(g->d_vols, vols.data(), sizeof(VolumeRec) * nvol, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemcpy volumes"));
     if (!dau.empty()) {
@@ -380,6 +476,7 @@ int geo_geometry_destroy(geo_geometry *g) {
         if (gr.done) (void)hipEventDestroy(gr.done);
     for (auto &st : g->stage)
         if (st.host) (void)hipHostFree(st.host);
+    (void)hipFree(g->d_pcon);
     (void)hipFree(g->d_vols);
     (void)hipFree(g->d_dau);
     (void)hipFree(g->d_cull);
@@ -395,14 +492,16 @@ int geo_shape_query(const geo_shape *s, int32_t query, geo_tracks t, void *out, 
     if (!s) return fail(GEO_ERR_INVALID_ARG, "shape is NULL");
     if (query < GEO_CONTAINS || query > GEO_DIST_OUT) return fail(GEO_ERR_INVALID_ARG, "unknown query %d", query);
     ShapeRec rec;
-    int rc = make_shape(*s, rec, nullptr, "shape");
+    PconRec pc;
+    std::memset(&pc, 0, sizeof pc);
+    int rc = make_shape(*s, rec, &pc, nullptr, "shape");
     if (rc) return rc;
     rc = check_tracks(t, query >= GEO_DIST_IN, "tracks");
     if (rc) return rc;
     if (t.n == 0) return GEO_OK;
     rc = check_out(out, query == GEO_CONTAINS ? 1 : 8, "out");
     if (rc) return rc;
-    hipError_t e = launch_shape_query(rec, query, to_dev(t), out, stream);
+    hipError_t e = launch_shape_query(rec, pc, query, to_dev(t), out, stream);
     if (e != hipSuccess) return hip_fail(e, "shape query launch");
     return GEO_OK;
 }
@@ -422,7 +521,7 @@ int geo_navigate_basket(const geo_geometry *g, int32_t volume, geo_tracks t, con
     hipError_t e = launch_nav_basket(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
                                      g->d_cull ? g->d_cull + first : nullptr, to_dev(t),
                                      g->h_vols[volume].nd > 0 ? offsets : nullptr, step, hit, hitpt, g->cull,
-                                     stream);
+                                     g->vol_kset[volume], stream);
     if (e != hipSuccess) return hip_fail(e, "navigator launch");
     return GEO_OK;
 }
@@ -445,7 +544,7 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
     hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
                                    g->d_cull ? g->d_cull + first : nullptr, nd, to_dev(t),
                                    nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, g->d_partial,
-                                   nd > 0 ? g_off : nullptr, g->cull, stream);
+                                   nd > 0 ? g_off : nullptr, g->cull, g->vol_kset[volume], stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     return GEO_OK;
 }
@@ -472,7 +571,8 @@ int geo_navigate_safety(const geo_geometry *g, int32_t volume, geo_tracks t, con
     const int first = g->h_vols[volume].first;
     hipError_t e = launch_nav_safety(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
                                      g->d_cull ? g->d_cull + first : nullptr, to_dev(t),
-                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, safety, g->cull, stream);
+                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, safety, g->cull,
+                                     g->vol_kset[volume], stream);
     if (e != hipSuccess) return hip_fail(e, "safety launch");
     return GEO_OK;
 }
@@ -484,7 +584,8 @@ int geo_locate(const geo_geometry *g, int32_t volume, geo_tracks t, const double
     const int first = g->h_vols[volume].first;
     hipError_t e = launch_nav_locate(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
                                      g->d_cull ? g->d_cull + first : nullptr, to_dev(t),
-                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, where, g->cull, stream);
+                                     g->h_vols[volume].nd > 0 ? offsets : nullptr, where, g->cull,
+                                     g->vol_kset[volume], stream);
     if (e != hipSuccess) return hip_fail(e, "locate launch");
     return GEO_OK;
 }
@@ -597,7 +698,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     if (census) {  // instrumented run: direct launches, no graph
         GN_HIP(hipMemsetAsync(census, 0, kCensusSlots * sizeof(unsigned long long), stream));
         GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));
-        GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true), dim3(grid), dim3(kBlock), pargs, 0,
+        GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true, g->kset), dim3(grid), dim3(kBlock), pargs, 0,
                                stream));
         return advance_stage(g, stream);
     }
@@ -607,7 +708,7 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     kb.blockDim = dim3(kBlock);
     kb.kernelParams = bargs;
     hipKernelNodeParams kn = {};
-    kn.func = const_cast<void *>(batched_kernel(U, g->cull, persistent, false));
+    kn.func = const_cast<void *>(batched_kernel(U, g->cull, persistent, false, g->kset));
     kn.gridDim = dim3(grid);
     kn.blockDim = dim3(kBlock);
     kn.kernelParams = pargs;
@@ -806,20 +907,26 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
     (void)hipEventCreate(&e1);
     const int Us[] = {1, 2, 4, 8};
     const int Ws[] = {0, 2, 3, 4, 6, 8};
+    constexpr int kNU = 4, kNW = 6;
     int bestU = g->tracks_per_lane, bestW = g->waves_per_simd;
-    float best = 1e30f;
+    float tbest[kNU][kNW];
+    for (auto &row : tbest)
+        for (float &v : row) v = 1e30f;
     rc = GEO_OK;
-    for (int U : Us) {
-        for (int W : Ws) {
-            g->tracks_per_lane = U;
-            g->waves_per_simd = W;
-            // steady state, as in a transport loop: the mean of kBurst
-            // back-to-back calls, best of two bursts after a warm-up call
-            // (which also builds the graph for this shape)
-            constexpr int kBurst = 6;
-            float tmin = 1e30f;
-            rc = launch_batched(g, b, nb, all, step, hit, stream);
-            for (int rep = 0; rep < 2 && rc == GEO_OK; ++rep) {
+    // bring the clocks up first (an idle GPU starts slow, which would favour
+    // the shapes timed last), then time every shape in two passes and keep
+    // each shape's best
+    for (int k = 0; k < 16 && rc == GEO_OK; ++k) rc = launch_batched(g, b, nb, all, step, hit, stream);
+    for (int pass = 0; pass < 2 && rc == GEO_OK; ++pass) {
+        for (int iu = 0; iu < kNU && rc == GEO_OK; ++iu) {
+            for (int iw = 0; iw < kNW && rc == GEO_OK; ++iw) {
+                g->tracks_per_lane = Us[iu];
+                g->waves_per_simd = Ws[iw];
+                // steady state, as in a transport loop: the mean of kBurst
+                // back-to-back calls after a warm-up call (which also builds
+                // the graph for this shape)
+                constexpr int kBurst = 6;
+                rc = launch_batched(g, b, nb, all, step, hit, stream);
                 (void)hipEventRecord(e0, stream);
                 for (int k = 0; k < kBurst && rc == GEO_OK; ++k)
                     rc = launch_batched(g, b, nb, all, step, hit, stream);
@@ -831,17 +938,18 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
                 }
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
-                tmin = std::min(tmin, ms / kBurst);
-            }
-            if (rc) break;
-            if (tmin < best) {
-                best = tmin;
-                bestU = U;
-                bestW = W;
+                tbest[iu][iw] = std::min(tbest[iu][iw], ms / kBurst);
             }
         }
-        if (rc) break;
     }
+    float best = 1e30f;
+    for (int iu = 0; iu < kNU; ++iu)
+        for (int iw = 0; iw < kNW; ++iw)
+            if (tbest[iu][iw] < best) {
+                best = tbest[iu][iw];
+                bestU = Us[iu];
+                bestW = Ws[iw];
+            }
     (void)hipStreamSynchronize(stream);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

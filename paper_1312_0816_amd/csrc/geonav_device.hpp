@@ -21,8 +21,9 @@
 namespace gn {
 
 constexpr double kBig = 1e30;
-constexpr int kCensusSlots = 12, kCensusCull = 10, kCensusTracks = 11;
-enum : int32_t { kBox = 0, kTube = 1, kCone = 2, kTubs = 3, kCons = 4 };
+constexpr int kCensusSlots = 16, kCensusCull = 14, kCensusTracks = 15;
+// kPcon is an uncut polycone, kPcons one cut to an azimuth range.
+enum : int32_t { kBox = 0, kTube = 1, kCone = 2, kTubs = 3, kCons = 4, kPcon = 5, kPcons = 6 };
 
 // Shape with host-derived constants.
 //   BOX  c0..2 = dx, dy, dz
@@ -34,6 +35,8 @@ enum : int32_t { kBox = 0, kTube = 1, kCone = 2, kTubs = 3, kCons = 4 };
 //   TUBS, CONS (segments: the tube or cone cut to the azimuths [phi1, phi2],
 //        phi2 = phi1 + dphi < phi1 + 2 pi, axis included): the base kind's
 //        constants, and c17, c18 = cos phi1, sin phi1; c19, c20 = cos phi2, sin phi2.
+//   PCON, PCONS (polycone, uncut or cut): its sections live in a PconRec
+//        (see below); PCONS keeps the azimuth range in c17..c20.
 struct alignas(16) ShapeRec {
     int32_t kind;
     int32_t hole;    // tube/cone: an inner surface exists (not both inner radii 0)
@@ -43,13 +46,32 @@ struct alignas(16) ShapeRec {
 };
 static_assert(sizeof(ShapeRec) == 192, "ShapeRec layout");
 
+// Polycone: nz planes z_0 < ... < z_{nz-1} (nz <= kPconMax) with radii
+// rin/rout at each; between two planes the radii are linear in z, section
+// j's nappes being r = ao[j] + bo[j] z (outer) and ai[j] + bi[j] z (inner,
+// present when bit j of hole_mask is set: not both inner radii 0).
+constexpr int kPconMax = 8;
+struct alignas(16) PconRec {
+    int32_t nz;
+    int32_t hole_mask;
+    int32_t pad[2];
+    double z[kPconMax], rin[kPconMax], rout[kPconMax];
+    double rin2_0, rout2_0, rin2_l, rout2_l;             // squared radii at the end planes
+    double ao[kPconMax - 1], bo[kPconMax - 1], ai[kPconMax - 1], bi[kPconMax - 1];
+    double inv_eo[kPconMax - 1], inv_ei[kPconMax - 1];   // 1 / |profile edge|^2, outer and inner
+    double eps;  // slack of the section z-range tests: 1e-12 x (max |z| + max rmax)
+    double pad2;
+};
+static_assert(sizeof(PconRec) == 592, "PconRec layout");
+
 // A placed daughter: mother-frame point = R * local + T.
 struct alignas(16) DaughterRec {
     double rot[9];   // R, row-major
     double tr[3];    // T
     double bound_r;  // radius of a sphere about the local origin holding the shape
     double cull_r2;  // square of bound_r enlarged by 1e-6 relative + 1e-6 (culling test)
-    double pad[2];
+    const PconRec *pcon;  // the polycone's sections (device), or NULL
+    double pad;
     ShapeRec shape;
 };
 static_assert(sizeof(DaughterRec) == 320, "DaughterRec layout");
@@ -70,7 +92,8 @@ struct alignas(16) VolumeRec {
     ShapeRec mother;
     int32_t nd;     // number of daughters
     int32_t first;  // index of daughter 0 in the daughter and culling tables
-    int32_t pad[6];
+    const PconRec *pcon;  // the mother's polycone sections (device), or NULL
+    int32_t pad[2];
 };
 static_assert(sizeof(VolumeRec) == 224, "VolumeRec layout");
 
@@ -266,11 +289,14 @@ __device__ __forceinline__ void wedge_exit(const ShapeRec &s, double x, double y
 
 __device__ __forceinline__ bool cone_contains(const double *c, int hole, double x, double y,
                                               double z);
+__device__ __forceinline__ bool pcon_contains(const PconRec &P, double x, double y, double z);
 
 template <int BASE>
-__device__ __forceinline__ bool base_contains(const ShapeRec &s, double x, double y, double z) {
+__device__ __forceinline__ bool base_contains(const ShapeRec &s, const PconRec *pc, double x,
+                                              double y, double z) {
     if (BASE == kTube) return tube_contains(s.c, x, y, z);
-    return cone_contains(s.c, s.hole, x, y, z);
+    if (BASE == kCone) return cone_contains(s.c, s.hole, x, y, z);
+    return pcon_contains(*pc, x, y, z);
 }
 
 // Entering the range through a flat face, at a point inside the base solid
@@ -283,9 +309,9 @@ __device__ __forceinline__ bool base_contains(const ShapeRec &s, double x, doubl
 // face's half-plane, keeps a line through the axis (both planes crossed at
 // one point) exact.
 template <int BASE>
-__device__ __forceinline__ void face_entries(const ShapeRec &s, double x, double y, double z,
-                                             double ux, double uy, double uz, double &best,
-                                             int &sid) {
+__device__ __forceinline__ void face_entries(const ShapeRec &s, const PconRec *pc, double x,
+                                             double y, double z, double ux, double uy, double uz,
+                                             double &best, int &sid) {
     const double a0 = wedge_a(s.c, x, y), da = wedge_a(s.c, ux, uy);
     const double b0 = wedge_b(s.c, x, y), db = wedge_b(s.c, ux, uy);
     const double ta = fdiv(-a0, da), tb = fdiv(-b0, db);
@@ -312,7 +338,7 @@ __device__ __forceinline__ void face_entries(const ShapeRec &s, double x, double
         id = hi_a <= hi_b ? 3 : 4;
     }
     const double xh = fma(t, ux, x), yh = fma(t, uy, y), zh = fma(t, uz, z);
-    take(ok && base_contains<BASE>(s, xh, yh, zh), t, id, best, sid);
+    take(ok && base_contains<BASE>(s, pc, xh, yh, zh), t, id, best, sid);
 }
 
 // With SEG (a segment) an entry through a base surface counts only at a hit
@@ -356,7 +382,7 @@ __device__ __forceinline__ double tube_dist_out(const ShapeRec &S, double x, dou
                         (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 2, best, sid);
     }
-    if (SEG) face_entries<kTube>(S, x, y, z, ux, uy, uz, best, sid);
+    if (SEG) face_entries<kTube>(S, nullptr, x, y, z, ux, uy, uz, best, sid);
     return inside ? 0.0 : best;
 }
 
@@ -486,7 +512,7 @@ __device__ __forceinline__ double cone_dist_out(const ShapeRec &S, double x, dou
                         (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 2, best, sid);
     }
-    if (SEG) face_entries<kCone>(S, x, y, z, ux, uy, uz, best, sid);
+    if (SEG) face_entries<kCone>(S, nullptr, x, y, z, ux, uy, uz, best, sid);
     return inside ? 0.0 : best;
 }
 
@@ -524,6 +550,169 @@ __device__ __forceinline__ double cone_dist_in(const ShapeRec &S, double x, doub
     }
     if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);
     return inside ? best : 0.0;
+}
+
+// ----------------------------------------------------------------- polycone
+// A sequence of connected cone sections (section 3.1). The radii are
+// continuous across the planes inside, so those planes bound nothing: the
+// surfaces are the two end planes (surface 0) and, per section j, its outer
+// nappe (surface 5 + 2 j) and inner nappe (6 + 2 j), each a boundary only for
+// z in [z_j, z_{j+1}], which every candidate checks at its hit point. The
+// check allows a slack of eps: a line through a kink of the profile (a
+// plane between sections) meets the two sections' nappes there, and rounding
+// could otherwise put both hit points just outside their ranges. Within eps
+// of the plane the two nappes are within |b_j - b_{j+1}| eps of each other.
+// Nappe roots on the mirror nappe fall outside the ranges (the radii are
+// >= 0 on them). The loops run over the sections, the same for every lane.
+__device__ __forceinline__ bool pcon_contains(const PconRec &P, double x, double y, double z) {
+    const double rsq = x * x + y * y;
+    const int ns = P.nz - 1;
+    bool in = false;
+    for (int j = 0; j < ns; ++j) {
+        const double wo = fma(P.bo[j], z, P.ao[j]);
+        const double wi = fma(P.bi[j], z, P.ai[j]);
+        const bool hole = (P.hole_mask >> j) & 1;
+        in |= z >= P.z[j] && z <= P.z[j + 1] && rsq <= wo * wo && (!hole || rsq >= wi * wi);
+    }
+    return in;
+}
+
+// (u, z) in the profile polygon; u is a signed coordinate in a face's plane.
+__device__ __forceinline__ bool pcon_in_profile(const PconRec &P, double u, double z) {
+    const int ns = P.nz - 1;
+    bool in = false;
+    for (int j = 0; j < ns; ++j) {
+        const double wo = fma(P.bo[j], z, P.ao[j]);
+        const double wi = fma(P.bi[j], z, P.ai[j]);
+        in |= z >= P.z[j] && z <= P.z[j + 1] && u <= wo && u >= wi;
+    }
+    return in;
+}
+
+template <bool SEG>
+__device__ __forceinline__ double pcon_dist_out(const ShapeRec &S, const PconRec &P, double x,
+                                                double y, double z, double ux, double uy,
+                                                double uz, int &sid) {
+    const bool inside = pcon_contains(P, x, y, z) && (!SEG || wedge_in(S, x, y));
+    const int ns = P.nz - 1;
+    double best = kBig;
+    sid = -1;
+    {   // bottom plane, from below moving up, landing on its annulus
+        const double t = fdiv(P.z[0] - z, uz);
+        const double xh = fma(t, ux, x), yh = fma(t, uy, y);
+        const double r2 = xh * xh + yh * yh;
+        const bool ok = z < P.z[0] && uz > 0.0 && r2 >= P.rin2_0 && r2 <= P.rout2_0 &&
+                        (!SEG || wedge_in(S, xh, yh));
+        take(ok, t, 0, best, sid);
+    }
+    {   // top plane, from above moving down
+        const double t = fdiv(P.z[ns] - z, uz);
+        const double xh = fma(t, ux, x), yh = fma(t, uy, y);
+        const double r2 = xh * xh + yh * yh;
+        const bool ok = z > P.z[ns] && uz < 0.0 && r2 >= P.rin2_l && r2 <= P.rout2_l &&
+                        (!SEG || wedge_in(S, xh, yh));
+        take(ok, t, 0, best, sid);
+    }
+    const double rsq = x * x + y * y;
+    const double A0 = ux * ux + uy * uy;
+    const double B0 = x * ux + y * uy;
+    for (int j = 0; j < ns; ++j) {
+        const double zlo = P.z[j] - P.eps, zhi = P.z[j + 1] + P.eps;
+        {   // outer nappe: entered where f goes from + to -
+            const double w = fma(P.bo[j], z, P.ao[j]);
+            const double v = P.bo[j] * uz;
+            const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
+            const double disc = B * B - A * C;
+            const double s = fsqrt(fmax(disc, 0.0));
+            const double t = root_down(A, B, C, s);
+            const double zh = fma(t, uz, z);
+            const bool ok = disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi &&
+                            (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+            take(ok, t, 5 + 2 * j, best, sid);
+        }
+        if ((P.hole_mask >> j) & 1) {  // inner nappe: left from the hole
+            const double w = fma(P.bi[j], z, P.ai[j]);
+            const double v = P.bi[j] * uz;
+            const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
+            const double disc = B * B - A * C;
+            const double s = fsqrt(fmax(disc, 0.0));
+            const double t = root_up(A, B, C, s);
+            const double zh = fma(t, uz, z);
+            const bool ok = disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi &&
+                            (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+            take(ok, t, 6 + 2 * j, best, sid);
+        }
+    }
+    if (SEG) face_entries<kPcon>(S, &P, x, y, z, ux, uy, uz, best, sid);
+    return inside ? 0.0 : best;
+}
+
+template <bool SEG>
+__device__ __forceinline__ double pcon_dist_in(const ShapeRec &S, const PconRec &P, double x,
+                                               double y, double z, double ux, double uy, double uz,
+                                               int &sid) {
+    const bool inside = pcon_contains(P, x, y, z) && (!SEG || wedge_in(S, x, y));
+    const int ns = P.nz - 1;
+    double best = kBig;
+    sid = -1;
+    take(uz < 0.0, fdiv(P.z[0] - z, uz), 0, best, sid);
+    take(uz > 0.0, fdiv(P.z[ns] - z, uz), 0, best, sid);
+    const double rsq = x * x + y * y;
+    const double A0 = ux * ux + uy * uy;
+    const double B0 = x * ux + y * uy;
+    for (int j = 0; j < ns; ++j) {
+        const double zlo = P.z[j] - P.eps, zhi = P.z[j + 1] + P.eps;
+        {   // leave the outer nappe
+            const double w = fma(P.bo[j], z, P.ao[j]);
+            const double v = P.bo[j] * uz;
+            const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
+            const double disc = B * B - A * C;
+            const double s = fsqrt(fmax(disc, 0.0));
+            const double t = root_up(A, B, C, s);
+            const double zh = fma(t, uz, z);
+            take(disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi, t, 5 + 2 * j, best, sid);
+        }
+        if ((P.hole_mask >> j) & 1) {  // enter the hole
+            const double w = fma(P.bi[j], z, P.ai[j]);
+            const double v = P.bi[j] * uz;
+            const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
+            const double disc = B * B - A * C;
+            const double s = fsqrt(fmax(disc, 0.0));
+            const double t = root_down(A, B, C, s);
+            const double zh = fma(t, uz, z);
+            take(disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi, t, 6 + 2 * j, best, sid);
+        }
+    }
+    if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);
+    return inside ? best : 0.0;
+}
+
+// Squared distance from (r, z) to the profile's edges: the two end edges,
+// the outer edges and the inner edges; an inner edge on the axis (both radii
+// 0) bounds no surface and is skipped unless `axis` is set (a face's
+// polygon, whose edge on the axis is real).
+__device__ __forceinline__ double pcon_edges_d2(const PconRec &P, double r, double z, bool axis) {
+    const int ns = P.nz - 1;
+    const double rb = fmin(fmax(r, P.rin[0]), P.rout[0]);
+    const double rt = fmin(fmax(r, P.rin[ns]), P.rout[ns]);
+    double d2 = fmin(sq(r - rb) + sq(z - P.z[0]), sq(r - rt) + sq(z - P.z[ns]));
+    for (int j = 0; j < ns; ++j) {
+        const double h = P.z[j + 1] - P.z[j];
+        d2 = fmin(d2, seg_d2(r, z, P.rout[j], P.z[j], P.rout[j + 1] - P.rout[j], h, P.inv_eo[j]));
+        if (axis || ((P.hole_mask >> j) & 1))
+            d2 = fmin(d2, seg_d2(r, z, P.rin[j], P.z[j], P.rin[j + 1] - P.rin[j], h, P.inv_ei[j]));
+    }
+    return d2;
+}
+
+// A solid of revolution: the planar distance from (r, z) to the profile's
+// edges, inside and outside alike.
+__device__ __forceinline__ double pcon_safety(const PconRec &P, double x, double y, double z) {
+    return sqrt(pcon_edges_d2(P, sqrt(x * x + y * y), z, false));
+}
+
+__device__ __forceinline__ double pcon_face_d2(const PconRec &P, double u, double z) {
+    return pcon_in_profile(P, u, z) ? 0.0 : pcon_edges_d2(P, u, z, true);
 }
 
 // ------------------------------------------------------ segment safety
@@ -565,107 +754,153 @@ __device__ __forceinline__ double cone_face_d2(const double *c, double u, double
 //   least r away, exactly r where the profile reaches the axis, and with a
 //   hole the inner surface is nearer than r.
 template <int BASE>
-__device__ __forceinline__ double seg_safety(const ShapeRec &S, double x, double y, double z) {
+__device__ __forceinline__ double seg_safety(const ShapeRec &S, const PconRec *pc, double x,
+                                             double y, double z) {
     const double *c = S.c;
-    const double base = BASE == kTube ? tube_safety(c, S.hole, x, y, z)
-                                      : cone_safety(c, S.hole, x, y, z);
-    const bool in_base = base_contains<BASE>(S, x, y, z);
+    const double base = BASE == kTube   ? tube_safety(c, S.hole, x, y, z)
+                        : BASE == kCone ? cone_safety(c, S.hole, x, y, z)
+                                        : pcon_safety(*pc, x, y, z);
+    const bool in_base = base_contains<BASE>(S, pc, x, y, z);
     const double a = wedge_a(c, x, y), b = wedge_b(c, x, y);
     const bool in_range = S.convex ? (a >= 0.0 && b >= 0.0) : (a >= 0.0 || b >= 0.0);
     const double u1 = fma(c[18], y, c[17] * x), u2 = fma(c[20], y, c[19] * x);
     const double r = sqrt(x * x + y * y);
     const double f_in = fmin(u1 >= 0.0 ? fabs(a) : r, u2 >= 0.0 ? fabs(b) : r);
-    const double d1 = BASE == kTube ? tube_face_d2(c, u1, z) : cone_face_d2(c, u1, z);
-    const double d2 = BASE == kTube ? tube_face_d2(c, u2, z) : cone_face_d2(c, u2, z);
+    const double d1 = BASE == kTube   ? tube_face_d2(c, u1, z)
+                      : BASE == kCone ? cone_face_d2(c, u1, z)
+                                      : pcon_face_d2(*pc, u1, z);
+    const double d2 = BASE == kTube   ? tube_face_d2(c, u2, z)
+                      : BASE == kCone ? cone_face_d2(c, u2, z)
+                                      : pcon_face_d2(*pc, u2, z);
     const double f_out = sqrt(fmin(fma(a, a, d1), fma(b, b, d2)));
     return (in_base && in_range) ? fmin(base, f_in) : fmin(in_range ? base : kBig, f_out);
 }
 
 // ------------------------------------------------------ dispatch on kind
+// `pc` is the shape's polycone record (read only for the polycone kinds).
 template <int KIND>
-__device__ __forceinline__ bool shape_contains(const ShapeRec &s, double x, double y, double z) {
+__device__ __forceinline__ bool shape_contains(const ShapeRec &s, const PconRec *pc, double x,
+                                               double y, double z) {
     if (KIND == kBox) return box_contains(s.c, x, y, z);
     if (KIND == kTube) return tube_contains(s.c, x, y, z);
     if (KIND == kCone) return cone_contains(s.c, s.hole, x, y, z);
     if (KIND == kTubs) return tube_contains(s.c, x, y, z) && wedge_in(s, x, y);
-    return cone_contains(s.c, s.hole, x, y, z) && wedge_in(s, x, y);
+    if (KIND == kCons) return cone_contains(s.c, s.hole, x, y, z) && wedge_in(s, x, y);
+    if (KIND == kPcon) return pcon_contains(*pc, x, y, z);
+    return pcon_contains(*pc, x, y, z) && wedge_in(s, x, y);
 }
 
 template <int KIND>
-__device__ __forceinline__ double shape_safety(const ShapeRec &s, double x, double y, double z) {
+__device__ __forceinline__ double shape_safety(const ShapeRec &s, const PconRec *pc, double x,
+                                               double y, double z) {
     if (KIND == kBox) return box_safety(s.c, x, y, z);
     if (KIND == kTube) return tube_safety(s.c, s.hole, x, y, z);
     if (KIND == kCone) return cone_safety(s.c, s.hole, x, y, z);
-    if (KIND == kTubs) return seg_safety<kTube>(s, x, y, z);
-    return seg_safety<kCone>(s, x, y, z);
+    if (KIND == kTubs) return seg_safety<kTube>(s, pc, x, y, z);
+    if (KIND == kCons) return seg_safety<kCone>(s, pc, x, y, z);
+    if (KIND == kPcon) return pcon_safety(*pc, x, y, z);
+    return seg_safety<kPcon>(s, pc, x, y, z);
 }
 
 template <int KIND>
-__device__ __forceinline__ double shape_dist_out(const ShapeRec &s, double x, double y, double z,
-                                                 double ux, double uy, double uz, int &sid) {
+__device__ __forceinline__ double shape_dist_out(const ShapeRec &s, const PconRec *pc, double x,
+                                                 double y, double z, double ux, double uy,
+                                                 double uz, int &sid) {
     if (KIND == kBox) return box_dist_out(s.c, x, y, z, ux, uy, uz, sid);
     if (KIND == kTube) return tube_dist_out<false>(s, x, y, z, ux, uy, uz, sid);
     if (KIND == kCone) return cone_dist_out<false>(s, x, y, z, ux, uy, uz, sid);
     if (KIND == kTubs) return tube_dist_out<true>(s, x, y, z, ux, uy, uz, sid);
-    return cone_dist_out<true>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kCons) return cone_dist_out<true>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kPcon) return pcon_dist_out<false>(s, *pc, x, y, z, ux, uy, uz, sid);
+    return pcon_dist_out<true>(s, *pc, x, y, z, ux, uy, uz, sid);
 }
 
 template <int KIND>
-__device__ __forceinline__ double shape_dist_in(const ShapeRec &s, double x, double y, double z,
-                                                double ux, double uy, double uz, int &sid) {
+__device__ __forceinline__ double shape_dist_in(const ShapeRec &s, const PconRec *pc, double x,
+                                                double y, double z, double ux, double uy,
+                                                double uz, int &sid) {
     if (KIND == kBox) return box_dist_in(s.c, x, y, z, ux, uy, uz, sid);
     if (KIND == kTube) return tube_dist_in<false>(s, x, y, z, ux, uy, uz, sid);
     if (KIND == kCone) return cone_dist_in<false>(s, x, y, z, ux, uy, uz, sid);
     if (KIND == kTubs) return tube_dist_in<true>(s, x, y, z, ux, uy, uz, sid);
-    return cone_dist_in<true>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kCons) return cone_dist_in<true>(s, x, y, z, ux, uy, uz, sid);
+    if (KIND == kPcon) return pcon_dist_in<false>(s, *pc, x, y, z, ux, uy, uz, sid);
+    return pcon_dist_in<true>(s, *pc, x, y, z, ux, uy, uz, sid);
 }
 
-// `kind` is uniform across the wavefront wherever these are called.
-__device__ __forceinline__ bool any_contains(const ShapeRec &s, double x, double y, double z) {
-    switch (s.kind) {
-        case kBox: return shape_contains<kBox>(s, x, y, z);
-        case kTube: return shape_contains<kTube>(s, x, y, z);
-        case kCone: return shape_contains<kCone>(s, x, y, z);
-        case kTubs: return shape_contains<kTubs>(s, x, y, z);
-        default: return shape_contains<kCons>(s, x, y, z);
+// `kind` is uniform across the wavefront wherever these are called. KSET
+// bounds the kinds a geometry holds (kSetBasic: box, tube, cone; kSetSeg:
+// and their segments; kSetAll: and polycones), so that kernels for simpler
+// geometries carry no code for the kinds they never meet: the navigator's
+// loop body stays small, which the instruction cache rewards.
+enum : int { kSetBasic = 0, kSetSeg = 1, kSetAll = 2 };
+
+#define GN_KIND_SWITCH(CALL)                \
+    if (KSET == kSetBasic) {                \
+        switch (s.kind) {                   \
+            case kBox: return CALL(kBox);   \
+            case kTube: return CALL(kTube); \
+            default: return CALL(kCone);    \
+        }                                   \
+    }                                       \
+    if (KSET == kSetSeg) {                  \
+        switch (s.kind) {                   \
+            case kBox: return CALL(kBox);   \
+            case kTube: return CALL(kTube); \
+            case kCone: return CALL(kCone); \
+            case kTubs: return CALL(kTubs); \
+            default: return CALL(kCons);    \
+        }                                   \
+    }                                       \
+    switch (s.kind) {                       \
+        case kBox: return CALL(kBox);       \
+        case kTube: return CALL(kTube);     \
+        case kCone: return CALL(kCone);     \
+        case kTubs: return CALL(kTubs);     \
+        case kCons: return CALL(kCons);     \
+        case kPcon: return CALL(kPcon);     \
+        default: return CALL(kPcons);       \
     }
+
+template <int KSET = kSetAll>
+__device__ __forceinline__ bool any_contains(const ShapeRec &s, const PconRec *pc, double x,
+                                             double y, double z) {
+#define GN_CALL(K) shape_contains<K>(s, pc, x, y, z)
+    GN_KIND_SWITCH(GN_CALL)
+#undef GN_CALL
 }
 
-__device__ __forceinline__ double any_safety(const ShapeRec &s, double x, double y, double z) {
-    switch (s.kind) {
-        case kBox: return shape_safety<kBox>(s, x, y, z);
-        case kTube: return shape_safety<kTube>(s, x, y, z);
-        case kCone: return shape_safety<kCone>(s, x, y, z);
-        case kTubs: return shape_safety<kTubs>(s, x, y, z);
-        default: return shape_safety<kCons>(s, x, y, z);
-    }
+template <int KSET = kSetAll>
+__device__ __forceinline__ double any_safety(const ShapeRec &s, const PconRec *pc, double x,
+                                             double y, double z) {
+#define GN_CALL(K) shape_safety<K>(s, pc, x, y, z)
+    GN_KIND_SWITCH(GN_CALL)
+#undef GN_CALL
 }
 
-__device__ __forceinline__ double any_dist_out(const ShapeRec &s, double x, double y, double z,
-                                               double ux, double uy, double uz, int &sid) {
-    switch (s.kind) {
-        case kBox: return shape_dist_out<kBox>(s, x, y, z, ux, uy, uz, sid);
-        case kTube: return shape_dist_out<kTube>(s, x, y, z, ux, uy, uz, sid);
-        case kCone: return shape_dist_out<kCone>(s, x, y, z, ux, uy, uz, sid);
-        case kTubs: return shape_dist_out<kTubs>(s, x, y, z, ux, uy, uz, sid);
-        default: return shape_dist_out<kCons>(s, x, y, z, ux, uy, uz, sid);
-    }
+template <int KSET = kSetAll>
+__device__ __forceinline__ double any_dist_out(const ShapeRec &s, const PconRec *pc, double x,
+                                               double y, double z, double ux, double uy,
+                                               double uz, int &sid) {
+#define GN_CALL(K) shape_dist_out<K>(s, pc, x, y, z, ux, uy, uz, sid)
+    GN_KIND_SWITCH(GN_CALL)
+#undef GN_CALL
 }
 
-__device__ __forceinline__ double any_dist_in(const ShapeRec &s, double x, double y, double z,
-                                              double ux, double uy, double uz, int &sid) {
-    switch (s.kind) {
-        case kBox: return shape_dist_in<kBox>(s, x, y, z, ux, uy, uz, sid);
-        case kTube: return shape_dist_in<kTube>(s, x, y, z, ux, uy, uz, sid);
-        case kCone: return shape_dist_in<kCone>(s, x, y, z, ux, uy, uz, sid);
-        case kTubs: return shape_dist_in<kTubs>(s, x, y, z, ux, uy, uz, sid);
-        default: return shape_dist_in<kCons>(s, x, y, z, ux, uy, uz, sid);
-    }
+template <int KSET = kSetAll>
+__device__ __forceinline__ double any_dist_in(const ShapeRec &s, const PconRec *pc, double x,
+                                              double y, double z, double ux, double uy,
+                                              double uz, int &sid) {
+#define GN_CALL(K) shape_dist_in<K>(s, pc, x, y, z, ux, uy, uz, sid)
+    GN_KIND_SWITCH(GN_CALL)
+#undef GN_CALL
 }
+#undef GN_KIND_SWITCH
 
 // Outward-or-inward normal (any scale/sign) of surface `sid` at local point h.
-__device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, double hx, double hy,
-                                               double hz, double &nx, double &ny, double &nz) {
+__device__ __forceinline__ void surface_normal(const ShapeRec &s, const PconRec *pc, int sid,
+                                               double hx, double hy, double hz, double &nx,
+                                               double &ny, double &nz) {
     nx = ny = nz = 0.0;
     if (s.kind == kBox) {
         nx = sid == 0 ? 1.0 : 0.0;
@@ -687,6 +922,14 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, int sid, doubl
     }
     nx = hx;
     ny = hy;
+    if (s.kind == kPcon || s.kind == kPcons) {  // nappe of section j: r = a + b z
+        const int j = (sid - 5) >> 1;
+        const bool outer = ((sid - 5) & 1) == 0;
+        const double a = outer ? pc->ao[j] : pc->ai[j];
+        const double b = outer ? pc->bo[j] : pc->bi[j];
+        nz = -b * fma(b, hz, a);
+        return;
+    }
     if (s.kind == kCone || s.kind == kCons) {
         const double a = sid == 1 ? s.c[1] : s.c[3];
         const double b = sid == 1 ? s.c[2] : s.c[4];
@@ -721,7 +964,7 @@ __device__ __forceinline__ void census_add(unsigned long long *census, int slot)
         atomicAdd(&census[slot], (unsigned long long)__popcll(act));
 }
 
-template <bool HAS_OFFS, bool TRACK_SURF, bool CULL, bool COUNT = false>
+template <bool HAS_OFFS, bool TRACK_SURF, bool CULL, bool COUNT = false, int KSET = kSetAll>
 __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, double x, double y,
@@ -730,7 +973,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
                                           unsigned long long *census = nullptr) {
     int sid;
     if (COUNT) census_add(census, kCensusTracks);
-    best = any_dist_in(v.mother, x, y, z, ux, uy, uz, sid);
+    best = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
     hit = -1;
     bsid = sid;
     // per-track constants of the culling test: |d|^2, 1 / (2 |d|^2), 2 d
@@ -764,7 +1007,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
         const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
         const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
         const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
-        const double s = any_dist_out(D.shape, lx, ly, lz, lux, luy, luz, sid);
+        const double s = any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
         const bool better = s < best;
         best = better ? s : best;
         hit = better ? k : hit;
@@ -780,12 +1023,12 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // cannot lower the minimum), for localisation when |w| > r (the point is
 // outside the sphere, hence outside the daughter). Results are identical to
 // evaluating every daughter.
-template <bool HAS_OFFS, bool CULL>
+template <bool HAS_OFFS, bool CULL, int KSET = kSetAll>
 __device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                              const CullRec *__restrict__ cul,
                                              const double *__restrict__ offs, double x, double y,
                                              double z) {
-    double best = any_safety(v.mother, x, y, z);
+    double best = any_safety<KSET>(v.mother, v.pcon, x, y, z);
     const int nd = v.nd;
     for (int k = 0; k < nd; ++k) {
         const CullRec &Q = cul[k];
@@ -805,19 +1048,19 @@ __device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterR
         const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
         const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
         const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
-        best = fmin(best, any_safety(D.shape, lx, ly, lz));
+        best = fmin(best, any_safety<KSET>(D.shape, D.pcon, lx, ly, lz));
     }
     return best;
 }
 
 // Daughter holding the point (lowest index), -1 for the mother's own part,
 // -2 outside the mother.
-template <bool HAS_OFFS, bool CULL>
+template <bool HAS_OFFS, bool CULL, int KSET = kSetAll>
 __device__ __forceinline__ int nav_locate(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, double x, double y,
                                           double z) {
-    int where = any_contains(v.mother, x, y, z) ? -1 : -2;
+    int where = any_contains<KSET>(v.mother, v.pcon, x, y, z) ? -1 : -2;
     const int nd = v.nd;
     for (int k = 0; k < nd; ++k) {
         if (__ballot(where == -1) == 0) break;  // every lane placed
@@ -837,7 +1080,7 @@ __device__ __forceinline__ int nav_locate(const VolumeRec &v, const DaughterRec 
         const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
         const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
         const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
-        const bool in = any_contains(D.shape, lx, ly, lz);
+        const bool in = any_contains<KSET>(D.shape, D.pcon, lx, ly, lz);
         where = (where == -1 && in) ? k : where;
     }
     return where;

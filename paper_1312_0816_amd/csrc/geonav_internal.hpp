@@ -11,19 +11,19 @@ namespace gn {
 constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
 constexpr int kBackwardMaxBlocks = 2048;
 
-hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, void *out,
-                              hipStream_t st);
+hipError_t launch_shape_query(const ShapeRec &s, const PconRec &pc, int query, const TracksDev &t,
+                              void *out, hipStream_t st);
 
 hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, double *step, int32_t *hit,
-                             double *hitpt, bool cull, hipStream_t st);
+                             double *hitpt, bool cull, int kset, hipStream_t st);
 
 hipError_t launch_nav_safety(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, double *out, bool cull,
-                             hipStream_t st);
+                             int kset, hipStream_t st);
 hipError_t launch_nav_locate(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, int32_t *out, bool cull,
-                             hipStream_t st);
+                             int kset, hipStream_t st);
 
 // Tile queues of the persistent batched kernel: one per XCD, cursors 256 B
 // apart.
@@ -67,8 +67,9 @@ constexpr int kBuildTilesBlocks = 256;
 
 // Kernel function handles (for graph kernel nodes and hipLaunchKernel).
 // persistent: k_nav_persistent, else k_nav_tiles (one wavefront per tile);
-// count: the variant that fills the work census.
-const void *batched_kernel(int tracks_per_lane, bool cull, bool persistent, bool count);
+// count: the variant that fills the work census; kset: the kinds the
+// geometry holds (kSetBasic, kSetSeg or kSetAll).
+const void *batched_kernel(int tracks_per_lane, bool cull, bool persistent, bool count, int kset);
 const void *build_tiles_kernel();
 // Workgroups of a batched launch: num_cus * waves_per_simd (persistent) or
 // one wavefront per tile (waves_per_simd == 0).
@@ -77,6 +78,6 @@ int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles);
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
-                           double *g_off, bool cull, hipStream_t st);
+                           double *g_off, bool cull, int kset, hipStream_t st);
 
 }  // namespace gn

@@ -17,55 +17,75 @@
 
 namespace gn {
 
+// Runs STMT with the compile-time constant KS set to the runtime kind set.
+#define GN_KSET(kset, STMT)                                 \
+    do {                                                    \
+        if ((kset) == kSetBasic) {                          \
+            constexpr int KS = kSetBasic;                   \
+            STMT;                                           \
+        } else if ((kset) == kSetSeg) {                     \
+            constexpr int KS = kSetSeg;                     \
+            STMT;                                           \
+        } else {                                            \
+            constexpr int KS = kSetAll;                     \
+            STMT;                                           \
+        }                                                   \
+    } while (0)
+
 // ------------------------------------------------------------ shape queries
+// A polycone's sections come by value with the arguments (`pc`, unused for
+// the other kinds).
 template <int KIND, int Q>
-__global__ __launch_bounds__(kBlock) void k_shape_query(ShapeRec s, TracksDev t, void *out) {
+__global__ __launch_bounds__(kBlock) void k_shape_query(ShapeRec s, PconRec pc, TracksDev t,
+                                                        void *out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
     const double x = t.x[i], y = t.y[i], z = t.z[i];
     if (Q == 0) {
-        static_cast<uint8_t *>(out)[i] = shape_contains<KIND>(s, x, y, z) ? 1 : 0;
+        static_cast<uint8_t *>(out)[i] = shape_contains<KIND>(s, &pc, x, y, z) ? 1 : 0;
         return;
     }
     double r;
     if (Q == 1) {
-        r = shape_safety<KIND>(s, x, y, z);
+        r = shape_safety<KIND>(s, &pc, x, y, z);
     } else {
         const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
         int sid;
-        if (Q == 2) r = shape_dist_in<KIND>(s, x, y, z, ux, uy, uz, sid);
-        else r = shape_dist_out<KIND>(s, x, y, z, ux, uy, uz, sid);
+        if (Q == 2) r = shape_dist_in<KIND>(s, &pc, x, y, z, ux, uy, uz, sid);
+        else r = shape_dist_out<KIND>(s, &pc, x, y, z, ux, uy, uz, sid);
     }
     static_cast<double *>(out)[i] = r;
 }
 
 template <int KIND>
-static hipError_t launch_shape_kind(const ShapeRec &s, int query, const TracksDev &t, void *out,
-                                   hipStream_t st) {
+static hipError_t launch_shape_kind(const ShapeRec &s, const PconRec &pc, int query,
+                                    const TracksDev &t, void *out, hipStream_t st) {
     const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
     switch (query) {
-        case 0: hipLaunchKernelGGL((k_shape_query<KIND, 0>), grid, block, 0, st, s, t, out); break;
-        case 1: hipLaunchKernelGGL((k_shape_query<KIND, 1>), grid, block, 0, st, s, t, out); break;
-        case 2: hipLaunchKernelGGL((k_shape_query<KIND, 2>), grid, block, 0, st, s, t, out); break;
-        default: hipLaunchKernelGGL((k_shape_query<KIND, 3>), grid, block, 0, st, s, t, out); break;
+        case 0: hipLaunchKernelGGL((k_shape_query<KIND, 0>), grid, block, 0, st, s, pc, t, out); break;
+        case 1: hipLaunchKernelGGL((k_shape_query<KIND, 1>), grid, block, 0, st, s, pc, t, out); break;
+        case 2: hipLaunchKernelGGL((k_shape_query<KIND, 2>), grid, block, 0, st, s, pc, t, out); break;
+        default: hipLaunchKernelGGL((k_shape_query<KIND, 3>), grid, block, 0, st, s, pc, t, out); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_shape_query(const ShapeRec &s, int query, const TracksDev &t, void *out,
-                              hipStream_t st) {
+hipError_t launch_shape_query(const ShapeRec &s, const PconRec &pc, int query, const TracksDev &t,
+                              void *out, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
     switch (s.kind) {
-        case kBox: return launch_shape_kind<kBox>(s, query, t, out, st);
-        case kTube: return launch_shape_kind<kTube>(s, query, t, out, st);
-        case kCone: return launch_shape_kind<kCone>(s, query, t, out, st);
-        case kTubs: return launch_shape_kind<kTubs>(s, query, t, out, st);
-        default: return launch_shape_kind<kCons>(s, query, t, out, st);
+        case kBox: return launch_shape_kind<kBox>(s, pc, query, t, out, st);
+        case kTube: return launch_shape_kind<kTube>(s, pc, query, t, out, st);
+        case kCone: return launch_shape_kind<kCone>(s, pc, query, t, out, st);
+        case kTubs: return launch_shape_kind<kTubs>(s, pc, query, t, out, st);
+        case kCons: return launch_shape_kind<kCons>(s, pc, query, t, out, st);
+        case kPcon: return launch_shape_kind<kPcon>(s, pc, query, t, out, st);
+        default: return launch_shape_kind<kPcons>(s, pc, query, t, out, st);
     }
 }
 
 // ---------------------------------------------------------- basket navigator
-template <bool HAS_OFFS, bool HITPT, bool CULL>
+template <bool HAS_OFFS, bool HITPT, bool CULL, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
                                                        const CullRec *__restrict__ cul,
@@ -79,7 +99,8 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
     double best;
     int h, sid;
-    nav_track<HAS_OFFS, false, CULL>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h, sid);
+    nav_track<HAS_OFFS, false, CULL, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h,
+                                                  sid);
     step[i] = best;
     hit[i] = h;
     if (HITPT) {
@@ -90,32 +111,32 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     }
 }
 
-template <bool CULL>
+template <bool CULL, int KSET>
 static void launch_basket_variant(dim3 grid, const VolumeRec *vol, const DaughterRec *dau,
                                   const CullRec *cul, const TracksDev &t, const double *offs, double *step, int32_t *hit,
                                   double *hitpt, hipStream_t st) {
     const dim3 block(kBlock);
     if (offs) {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
     } else {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
     }
 }
 
 hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, double *step, int32_t *hit,
-                             double *hitpt, bool cull, hipStream_t st) {
+                             double *hitpt, bool cull, int kset, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
-    if (cull) launch_basket_variant<true>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st);
-    else launch_basket_variant<false>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st);
+    if (cull) GN_KSET(kset, (launch_basket_variant<true, KS>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st)));
+    else GN_KSET(kset, (launch_basket_variant<false, KS>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st)));
     return hipGetLastError();
 }
 
 // -------------------------------------------------- safety and locate
-template <bool HAS_OFFS, bool CULL>
+template <bool HAS_OFFS, bool CULL, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
                                                        const CullRec *__restrict__ cul, TracksDev t,
@@ -123,10 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restri
                                                        double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
-    out[i] = nav_safety<HAS_OFFS, CULL>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+    out[i] = nav_safety<HAS_OFFS, CULL, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
 }
 
-template <bool HAS_OFFS, bool CULL>
+template <bool HAS_OFFS, bool CULL, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
                                                        const CullRec *__restrict__ cul, TracksDev t,
@@ -134,36 +155,42 @@ __global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restri
                                                        int32_t *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
-    out[i] = nav_locate<HAS_OFFS, CULL>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+    out[i] = nav_locate<HAS_OFFS, CULL, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+}
+
+template <bool CULL, int KSET>
+static void launch_safety_variant(dim3 grid, const VolumeRec *vol, const DaughterRec *dau,
+                                  const CullRec *cul, const TracksDev &t, const double *offs,
+                                  double *out, hipStream_t st) {
+    if (offs) hipLaunchKernelGGL((k_nav_safety<true, CULL, KSET>), grid, dim3(kBlock), 0, st, vol, dau, cul, t, offs, out);
+    else hipLaunchKernelGGL((k_nav_safety<false, CULL, KSET>), grid, dim3(kBlock), 0, st, vol, dau, cul, t, offs, out);
+}
+
+template <bool CULL, int KSET>
+static void launch_locate_variant(dim3 grid, const VolumeRec *vol, const DaughterRec *dau,
+                                  const CullRec *cul, const TracksDev &t, const double *offs,
+                                  int32_t *out, hipStream_t st) {
+    if (offs) hipLaunchKernelGGL((k_nav_locate<true, CULL, KSET>), grid, dim3(kBlock), 0, st, vol, dau, cul, t, offs, out);
+    else hipLaunchKernelGGL((k_nav_locate<false, CULL, KSET>), grid, dim3(kBlock), 0, st, vol, dau, cul, t, offs, out);
 }
 
 hipError_t launch_nav_safety(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, double *out, bool cull,
-                             hipStream_t st) {
+                             int kset, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
-    if (offs) {
-        if (cull) hipLaunchKernelGGL((k_nav_safety<true, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-        else hipLaunchKernelGGL((k_nav_safety<true, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-    } else {
-        if (cull) hipLaunchKernelGGL((k_nav_safety<false, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-        else hipLaunchKernelGGL((k_nav_safety<false, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-    }
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
+    if (cull) GN_KSET(kset, (launch_safety_variant<true, KS>(grid, vol, dau, cul, t, offs, out, st)));
+    else GN_KSET(kset, (launch_safety_variant<false, KS>(grid, vol, dau, cul, t, offs, out, st)));
     return hipGetLastError();
 }
 
 hipError_t launch_nav_locate(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, int32_t *out, bool cull,
-                             hipStream_t st) {
+                             int kset, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock)), block(kBlock);
-    if (offs) {
-        if (cull) hipLaunchKernelGGL((k_nav_locate<true, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-        else hipLaunchKernelGGL((k_nav_locate<true, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-    } else {
-        if (cull) hipLaunchKernelGGL((k_nav_locate<false, true>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-        else hipLaunchKernelGGL((k_nav_locate<false, false>), grid, block, 0, st, vol, dau, cul, t, offs, out);
-    }
+    const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
+    if (cull) GN_KSET(kset, (launch_locate_variant<true, KS>(grid, vol, dau, cul, t, offs, out, st)));
+    else GN_KSET(kset, (launch_locate_variant<false, KS>(grid, vol, dau, cul, t, offs, out, st)));
     return hipGetLastError();
 }
 
@@ -172,7 +199,7 @@ hipError_t launch_nav_locate(const VolumeRec *vol, const DaughterRec *dau, const
 // per lane, so the volume and its daughters are uniform over the wavefront.
 // Tiles come in order of decreasing per-track cost (the host sorts the
 // baskets by daughter count; k_build_tiles expands them in that order).
-template <int U, bool CULL, bool COUNT>
+template <int U, bool CULL, bool COUNT, int KSET>
 __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__restrict__ vols,
                                          const DaughterRec *__restrict__ dau_all,
                                          const CullRec *__restrict__ cul_all, const TracksDev &t,
@@ -190,8 +217,8 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__rest
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int h, sid;
-            nav_track<false, false, CULL, COUNT>(v, dau, cul, nullptr, x, y, z, ux, uy, uz, best, h,
-                                                 sid, census);
+            nav_track<false, false, CULL, COUNT, KSET>(v, dau, cul, nullptr, x, y, z, ux, uy, uz,
+                                                       best, h, sid, census);
             step[i] = best;
             hit[i] = h;
         }
@@ -205,7 +232,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__rest
 // drains the queue of its workgroup's XCD slot (blockIdx mod kQueues) first,
 // then the others in turn; it exits once every queue's cursor has passed the
 // queue's length, so every wavefront terminates.
-template <int U, bool CULL, bool COUNT = false>
+template <int U, bool CULL, bool COUNT, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__restrict__ vols,
                                                            const DaughterRec *__restrict__ dau_all,
                                                            const CullRec *__restrict__ cul_all,
@@ -224,15 +251,15 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
             if (lane == 0) id = atomicAdd(&cursors[q * kQueueStride], 1u);
             id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
             if (id >= count) break;
-            run_tile<U, CULL, COUNT>(tiles[q + kQueues * (int64_t)id], vols, dau_all, cul_all, t, step,
-                                     hit, census, lane);
+            run_tile<U, CULL, COUNT, KSET>(tiles[q + kQueues * (int64_t)id], vols, dau_all, cul_all, t,
+                                           step, hit, census, lane);
         }
     }
 }
 
 // Hardware-scheduled form: one wavefront per tile, workgroups dispatched in
 // tile order (same parameters as the persistent form; `cursors` unused).
-template <int U, bool CULL, bool COUNT = false>
+template <int U, bool CULL, bool COUNT, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restrict__ vols,
                                                       const DaughterRec *__restrict__ dau_all,
                                                       const CullRec *__restrict__ cul_all,
@@ -244,8 +271,8 @@ __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restric
     (void)cursors;
     const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
     if (w >= ntiles) return;
-    run_tile<U, CULL, COUNT>(tiles[w], vols, dau_all, cul_all, t, step, hit, census,
-                             (int)(threadIdx.x & 63));
+    run_tile<U, CULL, COUNT, KSET>(tiles[w], vols, dau_all, cul_all, t, step, hit, census,
+                                   (int)(threadIdx.x & 63));
 }
 
 // Expands the (cost-sorted) basket list into tiles of at most tile_n tracks:
@@ -293,27 +320,35 @@ __global__ __launch_bounds__(kBlock) void k_build_tiles(BuildTilesArgs a) {
     }
 }
 
-template <int U, bool CULL, bool COUNT>
+template <int U, bool CULL, bool COUNT, int KSET>
 static const void *pick_mode(bool persistent) {
-    return persistent ? reinterpret_cast<const void *>(&k_nav_persistent<U, CULL, COUNT>)
-                      : reinterpret_cast<const void *>(&k_nav_tiles<U, CULL, COUNT>);
+    return persistent ? reinterpret_cast<const void *>(&k_nav_persistent<U, CULL, COUNT, KSET>)
+                      : reinterpret_cast<const void *>(&k_nav_tiles<U, CULL, COUNT, KSET>);
 }
 
-template <bool CULL, bool COUNT>
+template <bool CULL, bool COUNT, int KSET>
 static const void *pick_u(int U, bool persistent) {
     switch (U) {
-        case 1: return pick_mode<1, CULL, COUNT>(persistent);
-        case 2: return pick_mode<2, CULL, COUNT>(persistent);
-        case 4: return pick_mode<4, CULL, COUNT>(persistent);
-        default: return pick_mode<8, CULL, COUNT>(persistent);
+        case 1: return pick_mode<1, CULL, COUNT, KSET>(persistent);
+        case 2: return pick_mode<2, CULL, COUNT, KSET>(persistent);
+        case 4: return pick_mode<4, CULL, COUNT, KSET>(persistent);
+        default: return pick_mode<8, CULL, COUNT, KSET>(persistent);
     }
 }
 
-const void *batched_kernel(int tracks_per_lane, bool cull, bool persistent, bool count) {
-    if (cull) return count ? pick_u<true, true>(tracks_per_lane, persistent)
-                           : pick_u<true, false>(tracks_per_lane, persistent);
-    return count ? pick_u<false, true>(tracks_per_lane, persistent)
-                 : pick_u<false, false>(tracks_per_lane, persistent);
+// The census variants (instrumentation, not timed) exist for the full kind
+// set only.
+const void *batched_kernel(int tracks_per_lane, bool cull, bool persistent, bool count, int kset) {
+    const void *k = nullptr;
+    if (count) {
+        k = cull ? pick_u<true, true, kSetAll>(tracks_per_lane, persistent)
+                 : pick_u<false, true, kSetAll>(tracks_per_lane, persistent);
+    } else if (cull) {
+        GN_KSET(kset, (k = pick_u<true, false, KS>(tracks_per_lane, persistent)));
+    } else {
+        GN_KSET(kset, (k = pick_u<false, false, KS>(tracks_per_lane, persistent)));
+    }
+    return k;
 }
 
 const void *build_tiles_kernel() { return reinterpret_cast<const void *>(&k_build_tiles); }
@@ -335,7 +370,7 @@ int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles) {
 //   g_p = ghit + c ds/dp,  g_d = s ghit + c ds/dd,  g_delta_hit += c ds/d delta.
 // The offset gradient of the workgroup's tracks is summed per daughter in a
 // fixed lane order into the workgroup's row of `partial`.
-template <bool HAS_OFFS, bool CULL>
+template <bool HAS_OFFS, bool CULL, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_backward(
     const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau,
     const CullRec *__restrict__ cul, TracksDev t, const double *__restrict__ offs,
@@ -360,13 +395,14 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int sid;
-            nav_track<HAS_OFFS, true, CULL>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h, sid);
+            nav_track<HAS_OFFS, true, CULL, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best,
+                                                         h, sid);
             const bool finite = best < kBig;
             const double s = finite ? best : 0.0;
             const double hx = fma(s, ux, x), hy = fma(s, uy, y), hz = fma(s, uz, z);
             double nx, ny, nz;
             if (h < 0) {
-                surface_normal(vol->mother, sid, hx, hy, hz, nx, ny, nz);
+                surface_normal(vol->mother, vol->pcon, sid, hx, hy, hz, nx, ny, nz);
             } else {
                 const DaughterRec &D = dau[h];
                 double wx = hx - D.tr[0], wy = hy - D.tr[1], wz = hz - D.tr[2];
@@ -380,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
                 const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
                 const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
                 double mx, my, mz;
-                surface_normal(D.shape, sid, lx, ly, lz, mx, my, mz);
+                surface_normal(D.shape, D.pcon, sid, lx, ly, lz, mx, my, mz);
                 // back to the mother frame: n = R m
                 nx = fma(R[2], mz, fma(R[1], my, R[0] * mx));
                 ny = fma(R[5], mz, fma(R[4], my, R[3] * mx));
@@ -447,29 +483,33 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__rest
     if (threadIdx.x == 0) out[j] = s[0];
 }
 
-template <bool CULL>
+template <bool CULL, int KSET>
 static void launch_backward_variant(int nblocks, const VolumeRec *vol, const DaughterRec *dau,
                                     const CullRec *cul, const TracksDev &t, const double *offs, const double *gstep,
                                     const double *ghit, double *g_o, double *g_d, double *part,
                                     hipStream_t st) {
     if (offs)
-        hipLaunchKernelGGL((k_nav_backward<true, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
+        hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
                            offs, gstep, ghit, g_o, g_d, part);
     else
-        hipLaunchKernelGGL((k_nav_backward<false, CULL>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
+        hipLaunchKernelGGL((k_nav_backward<false, CULL, KSET>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
                            offs, gstep, ghit, g_o, g_d, part);
 }
 
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
-                           double *g_off, bool cull, hipStream_t st) {
+                           double *g_off, bool cull, int kset, hipStream_t st) {
     const int64_t need = (t.n + kBlock - 1) / kBlock;
     const int nblocks = (int)(need < kBackwardMaxBlocks ? (need > 0 ? need : 1) : kBackwardMaxBlocks);
     double *part = (g_off && nd > 0) ? partial : nullptr;
     if (t.n > 0 || part) {
-        if (cull) launch_backward_variant<true>(nblocks, vol, dau, cul, t, offs, gstep, ghit, g_o, g_d, part, st);
-        else launch_backward_variant<false>(nblocks, vol, dau, cul, t, offs, gstep, ghit, g_o, g_d, part, st);
+        if (cull)
+            GN_KSET(kset, (launch_backward_variant<true, KS>(nblocks, vol, dau, cul, t, offs, gstep, ghit,
+                                                             g_o, g_d, part, st)));
+        else
+            GN_KSET(kset, (launch_backward_variant<false, KS>(nblocks, vol, dau, cul, t, offs, gstep, ghit,
+                                                              g_o, g_d, part, st)));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -21,12 +21,13 @@ from . import build as _build
 
 LIB_PATH = _build.LIB
 
-GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS, GEO_CONS = 0, 1, 2, 3, 4
-CENSUS_SLOTS, CENSUS_CULL, CENSUS_TRACKS = 12, 10, 11
+GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS, GEO_CONS, GEO_PCON = 0, 1, 2, 3, 4, 5
+CENSUS_SLOTS, CENSUS_CULL, CENSUS_TRACKS = 16, 14, 15
 GEO_CONTAINS, GEO_SAFETY, GEO_DIST_IN, GEO_DIST_OUT = 0, 1, 2, 3
 GEO_BIG = 1e30
 GEO_MAX_DAUGHTERS = 1024
-NPAR = 7
+GEO_PCON_MAX_PLANES = 8
+NPAR = 3 + 3 * GEO_PCON_MAX_PLANES   # parameters per shape (GEO_NPAR)
 
 
 class GeoTracks(C.Structure):

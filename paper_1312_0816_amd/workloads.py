@@ -27,10 +27,28 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BOX, TUBE, CONE, TUBS, CONS = 0, 1, 2, 3, 4
+BOX, TUBE, CONE, TUBS, CONS, PCON = 0, 1, 2, 3, 4, 5
 KIND_NAMES = {BOX: "box", TUBE: "tube", CONE: "cone", TUBS: "tube segment",
-              CONS: "cone segment"}
-NPAR = 7   # parameters per shape (zero-padded)
+              CONS: "cone segment", PCON: "polycone"}
+PCON_MAX = 8   # z planes of a polycone
+NPAR = 3 + 3 * PCON_MAX   # parameters per shape (zero-padded)
+
+
+def pcon_par(phi1, dphi, planes):
+    """Polycone parameters {phi1, dphi, nz, z_0, rmin_0, rmax_0, ...} from a
+    list of (z, rmin, rmax) planes (z strictly increasing)."""
+    out = [float(phi1), float(dphi), float(len(planes))]
+    for z, a, b in planes:
+        out += [float(z), float(a), float(b)]
+    return np.array(out)
+
+
+def pcon_planes(par):
+    """(z, rmin, rmax) arrays of a polycone's parameters."""
+    par = np.asarray(par, np.float64).reshape(-1)
+    n = int(par[2])
+    q = par[3:3 + 3 * n].reshape(n, 3)
+    return q[:, 0], q[:, 1], q[:, 2]
 
 # Shape-suite shapes (parameter order as above).
 SUITE_SHAPES = {
@@ -41,7 +59,26 @@ SUITE_SHAPES = {
     # cone segment with a hole that closes to 2 at the narrow end
     TUBS: np.array([5.0, 15.0, 20.0, np.pi / 6, 4 * np.pi / 3]),
     CONS: np.array([20.0, 2.0, 10.0, 5.0, 20.0, -np.pi / 4, 5 * np.pi / 6]),
+    # polycone of four sections: the hole opens from an apex at z = -20,
+    # the outer radius rises to a plateau and falls again
+    PCON: pcon_par(0.0, 2 * np.pi, [(-20.0, 0.0, 6.0), (-8.0, 3.0, 12.0), (0.0, 3.0, 15.0),
+                                    (12.0, 5.0, 15.0), (20.0, 2.0, 8.0)]),
 }
+
+# Polycones for the parity tests: two planes (the cone of the suite), a
+# pipe with a flared end, eight planes with a zig-zag outer profile, the
+# same cut to a non-convex range, a spindle (apexes at both ends) cut to a
+# convex range, and three collinear planes (the suite cone again).
+_ZIGZAG = [(-30.0, 2.0, 8.0), (-22.0, 3.0, 12.0), (-15.0, 3.0, 6.0), (-5.0, 1.0, 14.0),
+           (0.0, 1.0, 14.0), (6.0, 4.0, 9.0), (18.0, 2.0, 16.0), (30.0, 2.0, 5.0)]
+PCON_VARIANTS = [
+    pcon_par(0.0, 2 * np.pi, [(-20.0, 0.0, 10.0), (20.0, 5.0, 20.0)]),
+    pcon_par(0.0, 2 * np.pi, [(-10.0, 0.0, 5.0), (0.0, 0.0, 5.0), (10.0, 0.0, 10.0)]),
+    pcon_par(0.0, 2 * np.pi, _ZIGZAG),
+    pcon_par(0.4, 4.0, _ZIGZAG),
+    pcon_par(-1.0, 1.5, [(-12.0, 0.0, 0.0), (0.0, 0.0, 10.0), (12.0, 0.0, 0.0)]),
+    pcon_par(0.0, 2 * np.pi, [(-20.0, 0.0, 10.0), (0.0, 2.5, 15.0), (20.0, 5.0, 20.0)]),
+]
 
 # Further segments for the parity tests: narrow, right-angle, half and wide
 # ranges, ranges that wrap through phi = pi, solid (no hole) profiles whose
@@ -119,9 +156,31 @@ def box_c0(seed: int = 1000, n: int = 1024):
 
 
 def segment_range(kind, par):
-    """(phi1, dphi) of a tube or cone segment's parameters (padded or not)."""
+    """(phi1, dphi) of a tube or cone segment's or polycone's parameters
+    (padded or not)."""
     par = np.asarray(par, np.float64).reshape(-1)
+    if kind == PCON:
+        return float(par[0]), float(par[1])
     return (float(par[3]), float(par[4])) if kind == TUBS else (float(par[5]), float(par[6]))
+
+
+def _sample_profile(rng, z, rin, rout, n):
+    """(r, z) uniform in the volume of revolution of a piecewise-linear
+    profile: z by acceptance on the cross-section pi (ro^2 - ri^2) against
+    the bound max(rout)^2, then r^2 uniform in the annulus."""
+    zs = [np.zeros(0)]
+    need = n
+    bound = float(np.max(rout)) ** 2
+    while need > 0:
+        m = 2 * need + 64
+        zz = rng.uniform(z[0], z[-1], m)
+        ri, ro = np.interp(zz, z, rin), np.interp(zz, z, rout)
+        acc = rng.uniform(0.0, bound, m) < (ro * ro - ri * ri)
+        zs.append(zz[acc][:need])
+        need -= zs[-1].size
+    zz = np.concatenate(zs)
+    ri, ro = np.interp(zz, z, rin), np.interp(zz, z, rout)
+    return np.sqrt(rng.uniform(ri * ri, ro * ro)), zz
 
 
 def _sample_in_shape(rng, kind, par, n):
@@ -159,6 +218,10 @@ def _sample_in_shape(rng, kind, par, n):
         ri = rmin1 + (rmin2 - rmin1) * f
         r = np.sqrt(rng.uniform(ri * ri, ro * ro))
         ph = rng.uniform(0.0, 2.0 * np.pi, n) if kind == CONE else par[5] + rng.uniform(0.0, par[6], n)
+        return [r * np.cos(ph), r * np.sin(ph), z]
+    if kind == PCON:
+        r, z = _sample_profile(rng, *pcon_planes(par), n)
+        ph = par[0] + rng.uniform(0.0, min(par[1], 2.0 * np.pi), n)
         return [r * np.cos(ph), r * np.sin(ph), z]
     raise ValueError(kind)
 
@@ -230,6 +293,22 @@ def _draw_daughter(rng, kind):
         par, rb = _draw_daughter(rng, TUBE if kind == TUBS else CONE)
         ang = [rng.uniform(0.0, 2 * np.pi), rng.uniform(0.3, 2 * np.pi - 0.3)]
         return np.concatenate([par[:3] if kind == TUBS else par[:5], ang]), rb
+    if kind == PCON:
+        # 3..6 planes over [-dz, dz] at least 0.5 apart; radii per plane as
+        # above; cut to a random range with probability 1/2
+        nz = int(rng.integers(3, 7))
+        dz = rng.uniform(5.0, 20.0)
+        while True:
+            z = np.concatenate([[-dz], np.sort(rng.uniform(-dz, dz, nz - 2)), [dz]])
+            if np.all(np.diff(z) >= 0.5):
+                break
+        rout = rng.uniform(5.0, 20.0, nz)
+        rin = np.array([inner(r) for r in rout])
+        if rng.uniform() < 0.5:
+            phi1, dphi = rng.uniform(0.0, 2 * np.pi), rng.uniform(0.3, 2 * np.pi - 0.3)
+        else:
+            phi1, dphi = 0.0, 2 * np.pi
+        return pcon_par(phi1, dphi, list(zip(z, rin, rout))), float(np.hypot(rout.max(), dz))
     raise ValueError(kind)
 
 
@@ -265,16 +344,17 @@ def toy_detector_volume(seed: int = 1200) -> Volume:
     return Volume(BOX, np.array([MOTHER_HALF] * 3 + [0.0, 0.0]), kinds, pars, rots, trs, bound)
 
 
-def segmented_detector_volume(seed: int = 1250) -> Volume:
+def mixed_detector_volume(seed: int = 1250) -> Volume:
     """The toy detector's layout (mother box (200)^3, 32 daughters on the
-    4 x 4 x 2 grid of cells) with daughter i of kind i mod 5: box, tube,
-    cone, tube segment, cone segment; segments cut to phi1 ~ U[0, 2 pi),
-    dphi ~ U[0.3, 2 pi - 0.3] (convex and non-convex ranges)."""
+    4 x 4 x 2 grid of cells) with daughter i of kind i mod 6: box, tube,
+    cone, tube segment, cone segment, polycone; segments cut to
+    phi1 ~ U[0, 2 pi), dphi ~ U[0.3, 2 pi - 0.3] (convex and non-convex
+    ranges); polycones of 3..6 planes, half of them cut likewise."""
     rng = np.random.default_rng(seed)
     cs = [-150.0, -50.0, 50.0, 150.0]
     centres = [(x, y, z) for z in (-100.0, 100.0) for y in cs for x in cs]
     kinds, pars, rots, trs, bound = _place_daughters(rng, centres, 50.0,
-                                                     (BOX, TUBE, CONE, TUBS, CONS))
+                                                     (BOX, TUBE, CONE, TUBS, CONS, PCON))
     return Volume(BOX, np.array([MOTHER_HALF] * 3 + [0.0, 0.0]), kinds, pars, rots, trs, bound)
 
 

@@ -75,6 +75,17 @@ def test_shape_validation_without_device(gv):
     assert b"dphi" in lib.geo_strerror(_bad_shape_call(gv, 3, [1, 2, 3, 0.5, 0.0]))
     assert _bad_shape_call(gv, 3, [1, 2, 3, 0.5, 2 * np.pi]) == 0   # full turn is valid
     assert _bad_shape_call(gv, 0, [1, 2, 3, np.nan, np.nan]) == 0   # unread parameters ignored
+    from paper_1312_0816_amd import workloads as W
+    P = W.pcon_par
+    assert _bad_shape_call(gv, 5, P(0, 2 * np.pi, [(0, 0, 5), (1, 1, 6), (3, 0, 2)])) == 0
+    assert _bad_shape_call(gv, 5, P(0, 2 * np.pi, [(0, 0, 5)])) == -1              # nz = 1
+    assert _bad_shape_call(gv, 5, np.r_[0, 2 * np.pi, 2.5, 0, 0, 5, 1, 0, 5, 2, 0, 5]) == -1  # nz not integral
+    assert _bad_shape_call(gv, 5, P(0, 2 * np.pi, [(0, 0, 5), (0, 0, 6)])) == -1   # z not increasing
+    assert _bad_shape_call(gv, 5, P(0, 2 * np.pi, [(0, 3, 2), (1, 0, 6)])) == -1   # rmin > rmax
+    assert _bad_shape_call(gv, 5, P(0, 2 * np.pi, [(0, 0, 0), (1, 0, 0)])) == -1   # empty section
+    assert _bad_shape_call(gv, 5, P(0, 7.0, [(0, 0, 5), (1, 0, 6)])) == -1         # dphi > 2 pi
+    assert _bad_shape_call(gv, 5, P(0, 1.0, [(0, 0, 5), (1, np.nan, 6)])) == -1
+    assert b"strictly" in lib.geo_strerror(_bad_shape_call(gv, 5, P(0, 1, [(0, 0, 5), (0, 0, 6)])))
     s = gv.make_shape(0, [10, 20, 30])
     t = gv.GeoTracks(None, None, None, None, None, None, 5)          # NULL arrays with n > 0
     assert lib.geo_shape_query(C.byref(s), 0, t, None, None) == -1

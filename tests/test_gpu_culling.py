@@ -93,6 +93,6 @@ def test_census_counts(gv):
     T, Q = gv.CENSUS_TRACKS, gv.CENSUS_CULL
     assert len(c_on) == gv.CENSUS_SLOTS
     assert c_on[T] == n and c_off[T] == n
-    assert sum(c_off[:10]) == pairs and c_off[Q] == 0
-    assert c_on[Q] == pairs and 0 < sum(c_on[:10]) < pairs
+    assert sum(c_off[:14]) == pairs and c_off[Q] == 0
+    assert c_on[Q] == pairs and 0 < sum(c_on[:14]) < pairs
     g.close()

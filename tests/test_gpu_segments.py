@@ -2,7 +2,7 @@
 shape queries on nine segment variants and on tracks lying in the face
 planes or crossing the axis, and every navigator entry point (basket,
 safety, locate, batched, adjoint) on a detector whose daughters include
-segments."""
+segments and polycones."""
 import numpy as np
 import pytest
 
@@ -98,30 +98,30 @@ def test_segment_errors(gv):
 
 # ----------------------------------------------------------- navigator
 @pytest.mark.parametrize("n", [1, 65, 4099])
-def test_segmented_detector_ragged(gv, orc, n):
-    vol = W.segmented_detector_volume()
+def test_mixed_detector_ragged(gv, orc, n):
+    vol = W.mixed_detector_volume()
     t = W.tracks_in_mother(np.random.default_rng(1260 + n), vol, n)
     step, hit = run_nav(gv, vol, t)
-    check_nav(orc, vol, t, step, hit, what=f"segmented n={n}")
+    check_nav(orc, vol, t, step, hit, what=f"mixed n={n}")
 
 
-def test_segmented_detector_sampled(gv, orc):
+def test_mixed_detector_sampled(gv, orc):
     """2^20 tracks in one launch; 12000 sampled tracks compared with the
-    oracle; every daughter, segments included, is hit."""
-    vol = W.segmented_detector_volume()
+    oracle; every daughter, segments and polycones included, is hit."""
+    vol = W.mixed_detector_volume()
     t = W.tracks_in_mother(np.random.default_rng(1261), vol, 1 << 20)
     step, hit = run_nav(gv, vol, t)
     assert not np.isnan(step).any() and np.all(step > 0)
     assert len(np.unique(hit)) == vol.nd + 1
     idx = np.sort(np.random.default_rng(5).choice(t.shape[1], size=12000, replace=False))
     print(check_nav(orc, vol, np.ascontiguousarray(t[:, idx]), step[idx], hit[idx],
-                    what="segmented sampled"))
+                    what="mixed sampled"))
 
 
-def test_segmented_detector_aimed_at_faces(gv, orc):
+def test_mixed_detector_aimed_at_faces(gv, orc):
     """Tracks aimed at points of the segments' flat faces and cut edges, so
     that face entries decide many steps."""
-    vol = W.segmented_detector_volume()
+    vol = W.mixed_detector_volume()
     rng = np.random.default_rng(1262)
     segs = [k for k in range(vol.nd) if vol.kinds[k] in (W.TUBS, W.CONS)]
     origins, dirs = [], []
@@ -145,10 +145,10 @@ def test_segmented_detector_aimed_at_faces(gv, orc):
     print(check_nav(orc, vol, t, step, hit, offsets=offs, what="aimed at faces"))
 
 
-def test_segmented_safety_and_locate(gv, orc):
+def test_mixed_safety_and_locate(gv, orc):
     import torch
     from tests.test_gpu_safety_locate import _points
-    vol = W.segmented_detector_volume()
+    vol = W.mixed_detector_volume()
     p = _points(vol, 20000, 1263)
     g = gv.Geometry([vol])
     tp = torch.from_numpy(p).cuda()
@@ -156,18 +156,18 @@ def test_segmented_safety_and_locate(gv, orc):
     w = gv.geo_locate(g, 0, tp).cpu().numpy()
     ref = orc.navigate_safety(vol, p, None, "ld")
     ill = rel_diff(orc.navigate_safety(vol, p, None, "d"), ref) > 1e-13
-    print(check_values(s, ref, ill, "segmented safety"))
+    print(check_values(s, ref, ill, "mixed safety"))
     near = ref < 1e-9
     assert np.array_equal(w[~near], orc.locate(vol, p, None, "ld")[~near])
     assert len(np.unique(w)) == vol.nd + 2
     g.close()
 
 
-def test_segmented_batched_bit_identical(gv, orc):
-    """Batched navigation over segmented and plain volumes equals the
+def test_mixed_batched_bit_identical(gv, orc):
+    """Batched navigation over mixed and plain volumes equals the
     per-basket navigator bit for bit, and the oracle."""
     import torch
-    vols = [W.segmented_detector_volume(1250 + i) for i in range(4)] + [W.toy_detector_volume()]
+    vols = [W.mixed_detector_volume(1250 + i) for i in range(4)] + [W.toy_detector_volume()]
     rng = np.random.default_rng(1264)
     sizes = [37, 4099, 64, 1000, 2500, 1, 777]
     parts, bv, bo, bn, off = [], [], [], [], 0
@@ -192,13 +192,13 @@ def test_segmented_batched_bit_identical(gv, orc):
     g.close()
 
 
-def test_segmented_adjoint_matches_fd(gv, orc):
-    """Gradients of L = sum |hit point - target|^2 through the segmented
+def test_mixed_adjoint_matches_fd(gv, orc):
+    """Gradients of L = sum |hit point - target|^2 through the mixed
     detector (face planes among the surfaces that set steps) against the
     oracle's central differences on smooth tracks."""
     import torch
     from tests.test_gpu_adjoint import _close, _oracle_upstream
-    vol = W.segmented_detector_volume()
+    vol = W.mixed_detector_volume()
     rng = np.random.default_rng(1265)
     tr = W.tracks_in_mother(rng, vol, 6000)
     targets = rng.uniform(-200, 200, (3, tr.shape[1]))

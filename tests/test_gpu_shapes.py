@@ -67,7 +67,7 @@ def test_closed_forms_on_gpu(gv):
             assert abs(got - val) <= 1e-13 * max(1.0, abs(val)), (text, got, val)
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS])
+@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON])
 @pytest.mark.parametrize("n", [1, 257, 3001])
 def test_suite_ragged_sizes(gv, orc, kind, n):
     """Several workgroups plus a ragged tail, every track compared."""
@@ -75,7 +75,7 @@ def test_suite_ragged_sizes(gv, orc, kind, n):
     compare(gv, orc, kind, par, t, f"{W.KIND_NAMES[kind]} n={n}")
 
 
-@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS])
+@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON])
 def test_suite_full_size_sampled(gv, orc, kind):
     """The 2^20-track shape-suite workload in one launch per query; a random
     sample of 60000 outputs is compared track by track with the oracle, and
@@ -133,7 +133,7 @@ def test_hole_free_and_pointed_shapes(gv, orc):
 def test_axis_aligned_and_unnormalised_directions(gv, orc):
     """Directions with exact zero components and non-unit lengths (C6, C7)."""
     rng = np.random.default_rng(3)
-    for kind in (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS):
+    for kind in (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON):
         par = W.SUITE_SHAPES[kind]
         p = rng.uniform(-40, 40, (3, 3000))
         axis = rng.integers(0, 3, 3000)

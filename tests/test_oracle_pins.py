@@ -15,7 +15,7 @@ from paper_1312_0816_amd import workloads as W
 from tests.util import BIG, fib_dirs, first_transition, load_closed_forms, rel_err, to_local
 
 CASES = load_closed_forms()
-ALL_KINDS = [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS]
+ALL_KINDS = [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON]
 
 
 def _one(p, d):
@@ -315,6 +315,95 @@ def test_segment_variants_safety_and_ray_marching(orc, v):
     _check_safety_variational(orc, kind, par, t)
     _, _, t = _suite(kind, 60, 950 + v, par=par)
     _check_ray_marching(orc, kind, par, t)
+
+
+# -------------------------------------------------------------- polycone
+
+def _pcon_sections(par):
+    """The polycone's sections as cones, each with the shift of its centre:
+    [(cone par, z_mid)]."""
+    z, rin, rout = W.pcon_planes(par)
+    return [(np.array([(z[j + 1] - z[j]) / 2, rin[j], rout[j], rin[j + 1], rout[j + 1]]),
+             (z[j] + z[j + 1]) / 2) for j in range(len(z) - 1)]
+
+
+@pytest.mark.parametrize("prec", ["d", "ld"])
+def test_two_plane_polycone_is_the_cone(orc, prec):
+    """A polycone with planes at -dz and +dz is the cone (dz; radii at the
+    two planes), and so is one whose middle plane lies on the cone (the
+    plane is then no boundary)."""
+    cone = W.SUITE_SHAPES[W.CONE]
+    _, _, t = _suite(W.CONE, 20000, 61)
+    for par in (W.PCON_VARIANTS[0], W.PCON_VARIANTS[5]):
+        for q in (orc.CONTAINS, orc.SAFETY, orc.DIST_IN, orc.DIST_OUT):
+            a = orc.shape_query(W.PCON, par, q, t, prec)
+            b = orc.shape_query(W.CONE, cone, q, t, prec)
+            if q == orc.CONTAINS:
+                near = orc.safety(W.CONE, cone, t, prec) < 1e-9
+                assert np.array_equal(a[~near], b[~near])
+            else:
+                both_big = (a >= BIG) & (b >= BIG)
+                assert np.all(both_big | (rel_err(a, b) <= 1e-12))
+
+
+@pytest.mark.parametrize("v", range(len(W.PCON_VARIANTS)))
+def test_polycone_is_the_union_of_its_sections(orc, v):
+    """Each section of an uncut polycone is a cone between two planes, so
+    on every track: Contains = OR over the sections, DistFromOutside = the
+    smallest over the sections (entering a union is entering its first
+    part), and for points outside, Safety = the smallest over the sections.
+    Ties the polycone to the cone, which the closed forms pin. For a cut
+    polycone the same holds of the cut sections (cone segments)."""
+    par = W.PCON_VARIANTS[v]
+    _, _, t = _suite(W.PCON, 6000, 700 + v, par=par)
+    phi1, dphi = W.segment_range(W.PCON, par)
+    cut = dphi < 2 * np.pi
+    c = orc.contains(W.PCON, par, t)
+    d = orc.dist_out(W.PCON, par, t)
+    s = orc.safety(W.PCON, par, t)
+    cs, ds, ss, near = [], [], [], np.zeros(t.shape[1], bool)
+    for cpar, zm in _pcon_sections(par):
+        tt = t.copy()
+        tt[2] -= zm
+        kind, sp = (W.CONS, np.concatenate([cpar, [phi1, dphi]])) if cut else (W.CONE, cpar)
+        cs.append(orc.contains(kind, sp, tt))
+        ds.append(orc.dist_out(kind, sp, tt))
+        sk = orc.safety(kind, sp, tt)
+        ss.append(sk)
+        near |= sk < 1e-9
+    c_or = np.bitwise_or.reduce(np.stack(cs), axis=0)
+    assert np.array_equal(c[~near], c_or[~near])
+    dmin = np.min(np.stack(ds), axis=0)
+    both_big = (d >= BIG) & (dmin >= BIG)
+    # shifting z by the section centre rounds: agree to 1e-11
+    assert np.all(both_big | (np.abs(d - dmin) <= 1e-11 * np.maximum(1, d)))
+    out = (c == 0) & ~near
+    assert np.all(np.abs(s[out] - np.min(np.stack(ss), axis=0)[out]) <= 1e-11 * np.maximum(1, s[out]))
+
+
+@pytest.mark.parametrize("v", range(len(W.PCON_VARIANTS)))
+def test_polycone_variants_safety_and_ray_marching(orc, v):
+    par = W.PCON_VARIANTS[v]
+    _, _, t = _suite(W.PCON, 60, 800 + v, par=par)
+    _check_safety_variational(orc, W.PCON, par, t)
+    _, _, t = _suite(W.PCON, 60, 850 + v, par=par)
+    _check_ray_marching(orc, W.PCON, par, t)
+
+
+def test_cut_polycone_glues_into_the_uncut(orc):
+    """Two cut polycones [phi1, phi1 + a] and [phi1 + a, phi1 + 2 pi] make up
+    the uncut one (as for the segments)."""
+    par = W.PCON_VARIANTS[2]
+    _, _, t = _suite(W.PCON, 6000, 901, par=par)
+    s1 = par.copy(); s1[0], s1[1] = 0.3, 2.2
+    s2 = par.copy(); s2[0], s2[1] = 2.5, 2 * np.pi - 2.2
+    c = orc.contains(W.PCON, par, t)
+    c12 = orc.contains(W.PCON, s1, t) | orc.contains(W.PCON, s2, t)
+    near = (orc.safety(W.PCON, s1, t) < 1e-9) | (orc.safety(W.PCON, s2, t) < 1e-9)
+    assert np.array_equal(c[~near], c12[~near])
+    d = orc.dist_out(W.PCON, par, t)
+    d12 = np.minimum(orc.dist_out(W.PCON, s1, t), orc.dist_out(W.PCON, s2, t))
+    assert np.all(((d >= BIG) & (d12 >= BIG)) | (np.abs(d - d12) <= 1e-9 * np.maximum(1, d)))
 
 
 # ------------------------------------------------------------- navigator

@@ -12,8 +12,9 @@ BIG = 1e30
 
 def load_closed_forms():
     """Rows of tests/golden/closed_forms.txt as
-    (kind, par[5 or 7], query, p[3], d[3], expected, text). The cone segment
-    (kind 4) has 7 parameters, every other kind 5."""
+    (kind, par, query, p[3], d[3], expected, text). The cone segment (kind 4)
+    has 7 parameters, the polycone (kind 5) 3 + 3 nz (phi1, dphi, nz, then
+    z, rmin, rmax per plane), every other kind 5."""
     env = {"sqrt": math.sqrt, "min": min, "pi": math.pi}
 
     def num(tok):
@@ -27,7 +28,7 @@ def load_closed_forms():
                 continue
             tok = line.split()
             kind = int(tok[0])
-            npar = 7 if kind == 4 else 5
+            npar = 7 if kind == 4 else (3 + 3 * int(tok[3]) if kind == 5 else 5)
             par = [num(v) for v in tok[1:1 + npar]]
             tok = tok[1 + npar:]
             q = int(tok[0])
