@@ -7,11 +7,12 @@ grid (about 4.26M tracks, FP64). The step runs the whole navigator path:
 basket load, geometry access, master-to-local transforms, every daughter's
 DistFromOutside, the mother's DistFromInside, min/argmin and the outputs,
 scheduled as one launch from a cached HIP graph (the persistent kernel, or
-one wavefront per tile, whichever the autotuner finds faster).
+one wavefront per tile, whichever the autotuner finds faster). The timed
+steps follow enough warmup steps for the GPU to reach its full clock.
 
 Printed: one JSON line with tracks/s, the plain per-basket comparison (512
 separate geo_navigate_basket launches doing the same work), the roofline of
-the dominant kernel (the persistent navigator, FP64-ALU-bound), the HBM
+the dominant kernel (the batched navigator, FP64-ALU-bound), the HBM
 fraction, and the CPU oracle timed on this host on the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
@@ -317,8 +318,10 @@ def cpu_baseline(wl, gpu_step, gpu_hit, threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    # the GPU needs some 50 ms of sustained load to reach its full clock:
+    # 300 warmup steps (about 60 ms) precede the 200 timed ones (about 40 ms)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-rows", action="store_true", help="skip the per-row measurements")
     ap.add_argument("--no-autotune", action="store_true")

@@ -913,10 +913,21 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
     for (auto &row : tbest)
         for (float &v : row) v = 1e30f;
     rc = GEO_OK;
-    // bring the clocks up first (an idle GPU starts slow, which would favour
-    // the shapes timed last), then time every shape in two passes and keep
-    // each shape's best
-    for (int k = 0; k < 16 && rc == GEO_OK; ++k) rc = launch_batched(g, b, nb, all, step, hit, stream);
+    // bring the clocks up first (the GPU needs tens of milliseconds of load
+    // to reach its full clock; timing from idle would favour the shapes timed
+    // last), then time every shape in two passes and keep each shape's best
+    {
+        (void)hipEventRecord(e0, stream);
+        float warm = 0;
+        for (int k = 0; k < 1024 && rc == GEO_OK && warm < 50.0f; ++k) {
+            rc = launch_batched(g, b, nb, all, step, hit, stream);
+            if (k % 16 == 15 && rc == GEO_OK) {
+                (void)hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess) rc = fail(GEO_ERR_HIP, "autotune warm-up failed");
+                (void)hipEventElapsedTime(&warm, e0, e1);
+            }
+        }
+    }
     for (int pass = 0; pass < 2 && rc == GEO_OK; ++pass) {
         for (int iu = 0; iu < kNU && rc == GEO_OK; ++iu) {
             for (int iw = 0; iw < kNW && rc == GEO_OK; ++iw) {
