@@ -16,7 +16,7 @@ the dominant kernel (the batched navigator, FP64-ALU-bound), the HBM
 fraction, and the CPU oracle timed on this host on the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
-                       [--launch U,W | --no-autotune]
+                       [--launch U,W | --no-autotune] [--no-rows] [--no-plain]
 """
 from __future__ import annotations
 
@@ -324,6 +324,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-rows", action="store_true", help="skip the per-row measurements")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip timing the plain per-basket form (for profiling the batched kernel)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="force the batched launch shape 'tracks_per_lane,waves_per_simd' (no autotune)")
@@ -442,14 +444,16 @@ def main():
     batched_step()
 
     # timed: plain per-basket launches (after W warmup steps of their own)
-    for _ in range(args.warmup):
-        plain_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step()
-    torch.cuda.synchronize()
-    plain_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    plain_ms = None
+    if not args.no_plain:
+        for _ in range(args.warmup):
+            plain_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
     value = n / (ms_per_step * 1e-3)
     kernel_ms = float(ev_ms)
@@ -494,9 +498,10 @@ def main():
         },
         "hbm": {"achieved_GBps": hbm_gbs, "peak_GBps": HBM_PEAK_GBS, "frac": hbm_gbs / HBM_PEAK_GBS,
                 "bytes_per_track": BYTES_PER_TRACK},
-        "plain_per_basket": {"value": n / (plain_ms * 1e-3), "unit": "tracks/s", "ms_per_step": plain_ms,
-                             "launches": len(plain)},
-        "batched_over_plain": plain_ms / ms_per_step,
+        "plain_per_basket": None if plain_ms is None else {
+            "value": n / (plain_ms * 1e-3), "unit": "tracks/s", "ms_per_step": plain_ms,
+            "launches": len(plain)},
+        "batched_over_plain": None if plain_ms is None else plain_ms / ms_per_step,
         "batched_without_culling": {"value": n / (nocull_ms * 1e-3), "unit": "tracks/s",
                                     "ms_per_step": nocull_ms, "flops_per_launch": flops_nocull,
                                     "achieved_TFLOPs": flops_nocull / (nocull_ms * 1e-3) / 1e12,
