@@ -213,8 +213,10 @@ def basket_scan(gv, W, dev):
         offs = start + N * np.arange(P)
         barr, nb = gv._baskets(np.zeros(P, np.int32), offs, np.full(P, N))
         sp, hp = gv._ptr(step), gv._ptr(hit)
+        # 20 warmup calls: the first call of each of the library's 16 staging
+        # buffers grows it to this basket count
         ms_b = _time_ms(lambda: gv._check(lib.geo_navigate_batched(g.handle, barr, nb, tr, sp, hp, hs)),
-                        reps=5, warm=2)
+                        reps=10, warm=20)
         plain = [(gv.GeoTracks(tr.x + 8 * o, tr.y + 8 * o, tr.z + 8 * o, tr.ux + 8 * o, tr.uy + 8 * o,
                                tr.uz + 8 * o, N),
                   gv.C.c_void_p(step.data_ptr() + 8 * o), gv.C.c_void_p(hit.data_ptr() + 4 * o))

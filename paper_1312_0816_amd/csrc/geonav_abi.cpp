@@ -307,6 +307,7 @@ struct geo_geometry {
     hipGraphNode_t node_build = nullptr, node_nav = nullptr;
     int graph_U = 0, graph_grid = 0, graph_cull = -1, graph_mode = -1;
     std::vector<BasketRec> sorted;   // reused host scratch
+    std::vector<int> sort_count;
 };
 
 namespace {
@@ -644,15 +645,22 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
                    int32_t *hit, hipStream_t stream, unsigned long long *census = nullptr) {
     const int U = g->tracks_per_lane;
     const int tile_n = 64 * U;
-    // cost-sorted basket list (per-track cost ~ daughters + mother), stable
+    // cost-sorted basket list (per-track cost ~ daughters + mother): a
+    // stable counting sort on the daughter count, descending (O(nb), which
+    // matters for tens of thousands of small baskets)
     std::vector<BasketRec> &s = g->sorted;
-    s.clear();
+    std::vector<int> &cnt = g->sort_count;
+    cnt.assign((size_t)g->max_nd + 2, 0);
+    int ns = 0;
     for (int i = 0; i < nb; ++i)
-        if (b[i].n > 0) s.push_back(BasketRec{b[i].volume, 0, b[i].offset, b[i].n});
-    std::stable_sort(s.begin(), s.end(), [&](const BasketRec &a, const BasketRec &c) {
-        return g->h_vols[a.volume].nd > g->h_vols[c.volume].nd;
-    });
-    const int ns = (int)s.size();
+        if (b[i].n > 0) {
+            ++cnt[g->max_nd - g->h_vols[b[i].volume].nd + 1];
+            ++ns;
+        }
+    for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
+    s.resize((size_t)ns);
+    for (int i = 0; i < nb; ++i)
+        if (b[i].n > 0) s[cnt[g->max_nd - g->h_vols[b[i].volume].nd]++] = BasketRec{b[i].volume, 0, b[i].offset, b[i].n};
     if (ns == 0) return GEO_OK;
     int64_t ntiles = 0;
     for (const BasketRec &r : s) ntiles += (r.n + tile_n - 1) / tile_n;
