@@ -99,16 +99,24 @@ def test_tracks_inside_daughters_and_outside_mother(gv, orc):
 
 
 def test_other_mothers_and_no_daughters(gv, orc):
-    """Tube and cone mothers, and a volume with no daughters."""
+    """Tube, cone, segment and polycone mothers (cut and uncut), with and
+    without daughters."""
     rng = np.random.default_rng(8)
+    planes = [(-250.0, 0.0, 200.0), (-50.0, 30.0, 330.0), (100.0, 30.0, 300.0), (250.0, 0.0, 150.0)]
     cases = [
         W.Volume(W.TUBE, np.array([20.0, 300.0, 250.0, 0, 0])),
         W.Volume(W.CONE, np.array([250.0, 10.0, 200.0, 30.0, 350.0])),
         W.Volume(W.BOX, np.array([100.0, 50.0, 70.0, 0, 0])),
+        W.Volume(W.TUBS, np.array([20.0, 300.0, 250.0, 0.5, 4.0])),
+        W.Volume(W.CONS, np.array([250.0, 10.0, 200.0, 30.0, 350.0, -1.0, 2.5])),
+        W.Volume(W.PCON, W.pcon_par(0.0, 2 * np.pi, planes)),
     ]
     det = W.toy_detector_volume()
     cases.append(W.Volume(W.TUBE, np.array([0.0, 330.0, 210.0, 0, 0]), det.kinds, det.pars, det.rots,
                           det.trs, det.bound_r))
+    mix = W.mixed_detector_volume()
+    cases.append(W.Volume(W.PCON, W.pcon_par(0.3, 5.0, planes), mix.kinds, mix.pars, mix.rots, mix.trs,
+                          mix.bound_r))
     for vol in cases:
         n = 3000
         p = rng.uniform(-150, 150, (3, n))
