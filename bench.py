@@ -235,10 +235,16 @@ def basket_scan(gv, W, dev):
 
 
 def kernel_source_digest() -> str:
+    """Digest of the device code (comments and layout stripped), naming the
+    kernel source a committed counter summary was taken on."""
+    import re
     h = hashlib.sha256()
     for f in ("geonav_device.hpp", "geonav_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_1312_0816_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1312_0816_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,14 +1,18 @@
 // Kernels of libgeonav for gfx950 and their launchers.
 //
 //  k_shape_query     one query of one shape over a basket (section 3.1);
-//                    streaming, one lane per track, HBM-bound.
+//                    streaming, one lane per track, HBM-bound (the polycone
+//                    and the cone segment's Safety are ALU-bound).
 //  k_nav_basket      the simple navigator (section 3, Fig. 1b) over one
 //                    basket; FP64-ALU-bound (every lane walks every daughter).
 //  k_nav_safety      the navigator's isotropic safety (section 3) per point;
 //  k_nav_locate      the daughter holding each point (localization);
-//  k_nav_persistent  the same per-track navigator over many baskets of many
-//                    volumes in one launch: wavefronts pull tiles of one
-//                    volume from a global cursor (largest cost first).
+//  k_build_tiles     expands a host-sorted basket list into tiles of at most
+//                    64 x U tracks of one volume (largest cost first);
+//  k_nav_tiles       the per-track navigator over all tiles of many baskets
+//                    of many volumes in one launch, one wavefront per tile;
+//  k_nav_persistent  the same with a machine-sized grid whose wavefronts
+//                    pull tiles from per-XCD queues;
 //  k_nav_backward    adjoint of the navigator (recompute + implicit-function
 //                    gradient of the surface that set the step) with
 //                    per-workgroup partial sums of the offset gradient;
