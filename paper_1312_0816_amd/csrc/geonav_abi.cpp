@@ -46,6 +46,10 @@ int hip_fail(hipError_t e, const char *where) {
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
+// Relative slack of the range tests at candidate hit points (see "Edges" in
+// geonav_device.hpp).
+constexpr double kEdgeSlack = 1e-12;
+
 // Parameters each kind reads (the rest of par[] is ignored).
 static_assert(GEO_CENSUS_SLOTS == kCensusSlots, "census layout");
 
@@ -97,12 +101,14 @@ int make_pcon(const double *p, PconRec &pc, double *bound_r, const char *what) {
         pc.inv_eo[j] = 1.0 / ((pc.rout[j + 1] - pc.rout[j]) * (pc.rout[j + 1] - pc.rout[j]) + h * h);
         pc.inv_ei[j] = 1.0 / ((pc.rin[j + 1] - pc.rin[j]) * (pc.rin[j + 1] - pc.rin[j]) + h * h);
     }
-    pc.rin2_0 = pc.rin[0] * pc.rin[0];
-    pc.rout2_0 = pc.rout[0] * pc.rout[0];
-    pc.rin2_l = pc.rin[nz - 1] * pc.rin[nz - 1];
-    pc.rout2_l = pc.rout[nz - 1] * pc.rout[nz - 1];
     const double zm = std::max(std::fabs(pc.z[0]), std::fabs(pc.z[nz - 1]));
-    pc.eps = 1e-12 * (zm + rm);
+    pc.eps = kEdgeSlack * (zm + rm);
+    auto lo2 = [&](double r) { return r > pc.eps ? (r - pc.eps) * (r - pc.eps) : 0.0; };
+    auto hi2 = [&](double r) { return (r + pc.eps) * (r + pc.eps); };
+    pc.rin2_0 = lo2(pc.rin[0]);
+    pc.rout2_0 = hi2(pc.rout[0]);
+    pc.rin2_l = lo2(pc.rin[nz - 1]);
+    pc.rout2_l = hi2(pc.rout[nz - 1]);
     if (bound_r) *bound_r = std::sqrt(rm * rm + zm * zm);
     return GEO_OK;
 }
@@ -116,7 +122,13 @@ int make_base(int kind, const double *p, ShapeRec &out, double *bound_r, const c
             out.c[0] = p[0];
             out.c[1] = p[1];
             out.c[2] = p[2];
-            if (bound_r) *bound_r = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+            {
+                const double br = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+                const double eps = kEdgeSlack * br;
+                out.c[21] = eps;
+                for (int i = 0; i < 3; ++i) out.c[3 + i] = p[i] + eps;
+                if (bound_r) *bound_r = br;
+            }
             return GEO_OK;
         case GEO_TUBE:
             if (!(p[0] >= 0 && p[1] > 0 && p[0] <= p[1] && p[2] > 0))
@@ -128,7 +140,15 @@ int make_base(int kind, const double *p, ShapeRec &out, double *bound_r, const c
             out.c[2] = p[2];
             out.c[3] = p[0] * p[0];
             out.c[4] = p[1] * p[1];
-            if (bound_r) *bound_r = std::sqrt(p[1] * p[1] + p[2] * p[2]);
+            {
+                const double br = std::sqrt(p[1] * p[1] + p[2] * p[2]);
+                const double eps = kEdgeSlack * br;
+                out.c[21] = eps;
+                out.c[5] = p[2] + eps;
+                out.c[6] = p[0] > eps ? (p[0] - eps) * (p[0] - eps) : 0.0;
+                out.c[7] = (p[1] + eps) * (p[1] + eps);
+                if (bound_r) *bound_r = br;
+            }
             return GEO_OK;
         default: {  // GEO_CONE
             const double dz = p[0], rmin1 = p[1], rmax1 = p[2], rmin2 = p[3], rmax2 = p[4];
@@ -156,9 +176,19 @@ int make_base(int kind, const double *p, ShapeRec &out, double *bound_r, const c
             out.c[14] = 1.0 / std::sqrt(1.0 + bi * bi);
             out.c[15] = 1.0 / ((rmax2 - rmax1) * (rmax2 - rmax1) + 4 * dz * dz);
             out.c[16] = 1.0 / ((rmin2 - rmin1) * (rmin2 - rmin1) + 4 * dz * dz);
-            if (bound_r) {
+            {
                 const double rm = std::max(rmax1, rmax2);
-                *bound_r = std::sqrt(rm * rm + dz * dz);
+                const double br = std::sqrt(rm * rm + dz * dz);
+                const double eps = kEdgeSlack * br;
+                auto lo2 = [&](double r) { return r > eps ? (r - eps) * (r - eps) : 0.0; };
+                auto hi2 = [&](double r) { return (r + eps) * (r + eps); };
+                out.c[21] = eps;
+                out.c[22] = dz + eps;
+                out.c[23] = lo2(rmin1);
+                out.c[24] = hi2(rmax1);
+                out.c[25] = lo2(rmin2);
+                out.c[26] = hi2(rmax2);
+                if (bound_r) *bound_r = br;
             }
             return GEO_OK;
         }

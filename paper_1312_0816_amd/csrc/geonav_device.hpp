@@ -37,14 +37,19 @@ enum : int32_t { kBox = 0, kTube = 1, kCone = 2, kTubs = 3, kCons = 4, kPcon = 5
 //        constants, and c17, c18 = cos phi1, sin phi1; c19, c20 = cos phi2, sin phi2.
 //   PCON, PCONS (polycone, uncut or cut): its sections live in a PconRec
 //        (see below); PCONS keeps the azimuth range in c17..c20.
+// Slack of the range tests at candidate hit points (see "Edges" below):
+//   c21 = eps = 1e-12 x the shape's bounding radius, and the limits widened
+//   by it: BOX c3..5 = dx, dy, dz + eps; TUBE/TUBS c5 = dz + eps,
+//   c6, c7 = (rmin - eps)^2 (0 if rmin <= eps), (rmax + eps)^2; CONE/CONS
+//   c22 = dz + eps, c23..26 = the same two squares at -dz and at +dz.
 struct alignas(16) ShapeRec {
     int32_t kind;
     int32_t hole;    // tube/cone: an inner surface exists (not both inner radii 0)
     int32_t convex;  // segment: dphi <= pi (the azimuth range is convex)
     int32_t pad;
-    double c[22];
+    double c[28];
 };
-static_assert(sizeof(ShapeRec) == 192, "ShapeRec layout");
+static_assert(sizeof(ShapeRec) == 240, "ShapeRec layout");
 
 // Polycone: nz planes z_0 < ... < z_{nz-1} (nz <= kPconMax) with radii
 // rin/rout at each; between two planes the radii are linear in z, section
@@ -56,10 +61,10 @@ struct alignas(16) PconRec {
     int32_t hole_mask;
     int32_t pad[2];
     double z[kPconMax], rin[kPconMax], rout[kPconMax];
-    double rin2_0, rout2_0, rin2_l, rout2_l;             // squared radii at the end planes
+    double rin2_0, rout2_0, rin2_l, rout2_l;  // squared end radii, widened by eps (hit tests)
     double ao[kPconMax - 1], bo[kPconMax - 1], ai[kPconMax - 1], bi[kPconMax - 1];
     double inv_eo[kPconMax - 1], inv_ei[kPconMax - 1];   // 1 / |profile edge|^2, outer and inner
-    double eps;  // slack of the section z-range tests: 1e-12 x (max |z| + max rmax)
+    double eps;  // slack of the range tests at hit points: 1e-12 x (max |z| + max rmax)
     double pad2;
 };
 static_assert(sizeof(PconRec) == 592, "PconRec layout");
@@ -74,7 +79,7 @@ struct alignas(16) DaughterRec {
     double pad;
     ShapeRec shape;
 };
-static_assert(sizeof(DaughterRec) == 320, "DaughterRec layout");
+static_assert(sizeof(DaughterRec) == 368, "DaughterRec layout");
 
 // Culling record of a daughter, in its own compact array (32 B, so the
 // records of a whole volume stay in the scalar cache during the daughter
@@ -95,7 +100,7 @@ struct alignas(16) VolumeRec {
     const PconRec *pcon;  // the mother's polycone sections (device), or NULL
     int32_t pad[2];
 };
-static_assert(sizeof(VolumeRec) == 224, "VolumeRec layout");
+static_assert(sizeof(VolumeRec) == 272, "VolumeRec layout");
 
 struct TracksDev {
     const double *x, *y, *z, *ux, *uy, *uz;
@@ -168,6 +173,26 @@ __device__ __forceinline__ double root_up(double A, double B, double C, double s
     return fdiv(num, den);
 }
 
+// Near-double roots. A line through a nappe's apex (or tangent to it) has a
+// double root t0: B^2 - A C vanishes in exact arithmetic but comes out as
+// +-(a few ulps of B^2), whose square root would move both roots by about
+// sqrt(eps) t0. Within kSnap B^2 of zero the discriminant is taken as 0, and
+// the formulas above then give t0 = C / (-B) = -B / A to rounding.
+constexpr double kSnap = 64.0 * 2.220446049250313e-16;
+__device__ __forceinline__ double disc_sqrt(double disc, double B) {
+    return disc > kSnap * (B * B) ? fsqrt(disc) : 0.0;
+}
+__device__ __forceinline__ bool disc_ok(double disc, double B) { return disc >= -kSnap * (B * B); }
+
+// Edges. A candidate counts only if its hit point lies on the surface's part
+// that bounds the solid (a face's rectangle or annulus, a nappe's z range, a
+// segment's azimuth range). At an edge two such tests meet, and a line
+// through the edge could fail both by rounding. The tests at hit points
+// therefore allow a slack eps of 1e-12 x the shape's size; a hit that far
+// outside a face is within a comparable distance of the neighbouring
+// surface's own hit. The membership tests themselves (Contains, and "the
+// point is inside" in the distance queries) stay exact.
+
 // ---------------------------------------------------------------------- box
 __device__ __forceinline__ bool box_contains(const double *c, double x, double y, double z) {
     return fabs(x) <= c[0] && fabs(y) <= c[1] && fabs(z) <= c[2];
@@ -191,20 +216,20 @@ __device__ __forceinline__ double box_dist_out(const double *c, double x, double
     sid = -1;
     {
         const double t = fdiv(ax, fabs(ux));
-        const bool ok = ax > 0.0 && x * ux < 0.0 && fabs(fma(t, uy, y)) <= c[1] &&
-                        fabs(fma(t, uz, z)) <= c[2];
+        const bool ok = ax > 0.0 && x * ux < 0.0 && fabs(fma(t, uy, y)) <= c[4] &&
+                        fabs(fma(t, uz, z)) <= c[5];
         take(ok, t, 0, best, sid);
     }
     {
         const double t = fdiv(ay, fabs(uy));
-        const bool ok = ay > 0.0 && y * uy < 0.0 && fabs(fma(t, ux, x)) <= c[0] &&
-                        fabs(fma(t, uz, z)) <= c[2];
+        const bool ok = ay > 0.0 && y * uy < 0.0 && fabs(fma(t, ux, x)) <= c[3] &&
+                        fabs(fma(t, uz, z)) <= c[5];
         take(ok, t, 1, best, sid);
     }
     {
         const double t = fdiv(az, fabs(uz));
-        const bool ok = az > 0.0 && z * uz < 0.0 && fabs(fma(t, ux, x)) <= c[0] &&
-                        fabs(fma(t, uy, y)) <= c[1];
+        const bool ok = az > 0.0 && z * uz < 0.0 && fabs(fma(t, ux, x)) <= c[3] &&
+                        fabs(fma(t, uy, y)) <= c[4];
         take(ok, t, 2, best, sid);
     }
     return inside ? 0.0 : best;
@@ -261,6 +286,12 @@ __device__ __forceinline__ bool wedge_in(const ShapeRec &s, double x, double y) 
     const double a = wedge_a(s.c, x, y), b = wedge_b(s.c, x, y);
     return s.convex ? (a >= 0.0 && b >= 0.0) : (a >= 0.0 || b >= 0.0);
 }
+// The same for a candidate's hit point, with the slack eps (c21).
+__device__ __forceinline__ bool wedge_in_hit(const ShapeRec &s, double x, double y) {
+    const double a = wedge_a(s.c, x, y), b = wedge_b(s.c, x, y);
+    const double e = -s.c[21];
+    return s.convex ? (a >= e && b >= e) : (a >= e || b >= e);
+}
 
 // Leaving the range along the line (the point is in it). Convex range: the
 // first plane crossed outwards. Wider range: entering the open complement
@@ -290,6 +321,7 @@ __device__ __forceinline__ void wedge_exit(const ShapeRec &s, double x, double y
 __device__ __forceinline__ bool cone_contains(const double *c, int hole, double x, double y,
                                               double z);
 __device__ __forceinline__ bool pcon_contains(const PconRec &P, double x, double y, double z);
+__device__ __forceinline__ bool pcon_contains_hit(const PconRec &P, double x, double y, double z);
 
 template <int BASE>
 __device__ __forceinline__ bool base_contains(const ShapeRec &s, const PconRec *pc, double x,
@@ -297,6 +329,22 @@ __device__ __forceinline__ bool base_contains(const ShapeRec &s, const PconRec *
     if (BASE == kTube) return tube_contains(s.c, x, y, z);
     if (BASE == kCone) return cone_contains(s.c, s.hole, x, y, z);
     return pcon_contains(*pc, x, y, z);
+}
+
+// Membership of a face entry's hit point in the base solid, with the slack
+// eps on every bound.
+template <int BASE>
+__device__ __forceinline__ bool base_contains_hit(const ShapeRec &s, const PconRec *pc, double x,
+                                                  double y, double z) {
+    const double *c = s.c;
+    const double rsq = x * x + y * y;
+    if (BASE == kTube) return fabs(z) <= c[5] && rsq <= c[7] && rsq >= c[6];
+    if (BASE == kCone) {
+        const double wo = fma(c[2], z, c[1]) + c[21];
+        const double wi = fmax(fma(c[4], z, c[3]) - c[21], 0.0);
+        return fabs(z) <= c[22] && rsq <= wo * wo && rsq >= wi * wi;
+    }
+    return pcon_contains_hit(*pc, x, y, z);
 }
 
 // Entering the range through a flat face, at a point inside the base solid
@@ -338,7 +386,7 @@ __device__ __forceinline__ void face_entries(const ShapeRec &s, const PconRec *p
         id = hi_a <= hi_b ? 3 : 4;
     }
     const double xh = fma(t, ux, x), yh = fma(t, uy, y), zh = fma(t, uz, z);
-    take(ok && base_contains<BASE>(s, pc, xh, yh, zh), t, id, best, sid);
+    take(ok && base_contains_hit<BASE>(s, pc, xh, yh, zh), t, id, best, sid);
 }
 
 // With SEG (a segment) an entry through a base surface counts only at a hit
@@ -358,8 +406,8 @@ __device__ __forceinline__ double tube_dist_out(const ShapeRec &S, double x, dou
         const double t = fdiv(az, fabs(uz));
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
-        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= c[3] && r2 <= c[4] &&
-                        (!SEG || wedge_in(S, xh, yh));
+        const bool ok = az > 0.0 && z * uz < 0.0 && r2 >= c[6] && r2 <= c[7] &&
+                        (!SEG || wedge_in_hit(S, xh, yh));
         take(ok, t, 0, best, sid);
     }
     const double A = ux * ux + uy * uy;
@@ -367,19 +415,19 @@ __device__ __forceinline__ double tube_dist_out(const ShapeRec &S, double x, dou
     {   // outer cylinder, entered from r > rmax
         const double C = rsq - c[4];
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = fdiv(C, s - B);
-        const bool ok = C > 0.0 && B < 0.0 && disc >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
-                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+        const bool ok = C > 0.0 && B < 0.0 && disc_ok(disc, B) && fabs(fma(t, uz, z)) <= c[5] &&
+                        (!SEG || wedge_in_hit(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 1, best, sid);
     }
     if (hole) {  // inner cylinder, left from inside the hole into the material
         const double C = rsq - c[3];
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_up(A, B, C, s);
-        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
-                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+        const bool ok = disc_ok(disc, B) && t >= 0.0 && fabs(fma(t, uz, z)) <= c[5] &&
+                        (!SEG || wedge_in_hit(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 2, best, sid);
     }
     if (SEG) face_entries<kTube>(S, nullptr, x, y, z, ux, uy, uz, best, sid);
@@ -403,16 +451,16 @@ __device__ __forceinline__ double tube_dist_in(const ShapeRec &S, double x, doub
     {   // leave the outer cylinder
         const double C = rsq - c[4];
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_up(A, B, C, s);
-        take(disc >= 0.0 && t >= 0.0, t, 1, best, sid);
+        take(disc_ok(disc, B) && t >= 0.0, t, 1, best, sid);
     }
     if (hole) {  // enter the hole's cylinder
         const double C = rsq - c[3];
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_down(A, B, C, s);
-        take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
+        take(disc_ok(disc, B) && t >= 0.0, t, 2, best, sid);
     }
     if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);
     return inside ? best : 0.0;
@@ -484,10 +532,10 @@ __device__ __forceinline__ double cone_dist_out(const ShapeRec &S, double x, dou
         const double r2 = xh * xh + yh * yh;
         // select between the two faces' verdicts (not their constants, which
         // stay uniform scalars)
-        const bool on_bot = r2 >= c[9] && r2 <= c[10];
-        const bool on_top = r2 >= c[11] && r2 <= c[12];
+        const bool on_bot = r2 >= c[23] && r2 <= c[24];
+        const bool on_top = r2 >= c[25] && r2 <= c[26];
         const bool ok = az > 0.0 && z * uz < 0.0 && (z > 0.0 ? on_top : on_bot) &&
-                        (!SEG || wedge_in(S, xh, yh));
+                        (!SEG || wedge_in_hit(S, xh, yh));
         take(ok, t, 0, best, sid);
     }
     const double A0 = ux * ux + uy * uy;
@@ -496,20 +544,20 @@ __device__ __forceinline__ double cone_dist_out(const ShapeRec &S, double x, dou
         const double v = c[2] * uz;
         const double A = A0 - v * v, B = B0 - v * wo, C = rsq - wo * wo;
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_down(A, B, C, s);
-        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
-                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+        const bool ok = disc_ok(disc, B) && t >= 0.0 && fabs(fma(t, uz, z)) <= c[22] &&
+                        (!SEG || wedge_in_hit(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 1, best, sid);
     }
     if (hole) {  // inner nappe: left from the hole where f goes from - to +
         const double v = c[4] * uz;
         const double A = A0 - v * v, B = B0 - v * wi, C = rsq - wi * wi;
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_up(A, B, C, s);
-        const bool ok = disc >= 0.0 && t >= 0.0 && fabs(fma(t, uz, z)) <= dz &&
-                        (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+        const bool ok = disc_ok(disc, B) && t >= 0.0 && fabs(fma(t, uz, z)) <= c[22] &&
+                        (!SEG || wedge_in_hit(S, fma(t, ux, x), fma(t, uy, y)));
         take(ok, t, 2, best, sid);
     }
     if (SEG) face_entries<kCone>(S, nullptr, x, y, z, ux, uy, uz, best, sid);
@@ -536,17 +584,17 @@ __device__ __forceinline__ double cone_dist_in(const ShapeRec &S, double x, doub
         const double v = c[2] * uz;
         const double A = A0 - v * v, B = B0 - v * wo, C = rsq - wo * wo;
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_up(A, B, C, s);
-        take(disc >= 0.0 && t >= 0.0, t, 1, best, sid);
+        take(disc_ok(disc, B) && t >= 0.0, t, 1, best, sid);
     }
     if (hole) {  // enter the inner nappe (the hole)
         const double v = c[4] * uz;
         const double A = A0 - v * v, B = B0 - v * wi, C = rsq - wi * wi;
         const double disc = B * B - A * C;
-        const double s = fsqrt(fmax(disc, 0.0));
+        const double s = disc_sqrt(disc, B);
         const double t = root_down(A, B, C, s);
-        take(disc >= 0.0 && t >= 0.0, t, 2, best, sid);
+        take(disc_ok(disc, B) && t >= 0.0, t, 2, best, sid);
     }
     if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);
     return inside ? best : 0.0;
@@ -577,6 +625,19 @@ __device__ __forceinline__ bool pcon_contains(const PconRec &P, double x, double
     return in;
 }
 
+// Membership of a candidate's hit point, with the slack eps on every bound.
+__device__ __forceinline__ bool pcon_contains_hit(const PconRec &P, double x, double y, double z) {
+    const double rsq = x * x + y * y;
+    const int ns = P.nz - 1;
+    bool in = false;
+    for (int j = 0; j < ns; ++j) {
+        const double wo = fma(P.bo[j], z, P.ao[j]) + P.eps;
+        const double wi = fmax(fma(P.bi[j], z, P.ai[j]) - P.eps, 0.0);
+        in |= z >= P.z[j] - P.eps && z <= P.z[j + 1] + P.eps && rsq <= wo * wo && rsq >= wi * wi;
+    }
+    return in;
+}
+
 // (u, z) in the profile polygon; u is a signed coordinate in a face's plane.
 __device__ __forceinline__ bool pcon_in_profile(const PconRec &P, double u, double z) {
     const int ns = P.nz - 1;
@@ -602,7 +663,7 @@ __device__ __forceinline__ double pcon_dist_out(const ShapeRec &S, const PconRec
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
         const bool ok = z < P.z[0] && uz > 0.0 && r2 >= P.rin2_0 && r2 <= P.rout2_0 &&
-                        (!SEG || wedge_in(S, xh, yh));
+                        (!SEG || wedge_in_hit(S, xh, yh));
         take(ok, t, 0, best, sid);
     }
     {   // top plane, from above moving down
@@ -610,7 +671,7 @@ __device__ __forceinline__ double pcon_dist_out(const ShapeRec &S, const PconRec
         const double xh = fma(t, ux, x), yh = fma(t, uy, y);
         const double r2 = xh * xh + yh * yh;
         const bool ok = z > P.z[ns] && uz < 0.0 && r2 >= P.rin2_l && r2 <= P.rout2_l &&
-                        (!SEG || wedge_in(S, xh, yh));
+                        (!SEG || wedge_in_hit(S, xh, yh));
         take(ok, t, 0, best, sid);
     }
     const double rsq = x * x + y * y;
@@ -623,11 +684,11 @@ __device__ __forceinline__ double pcon_dist_out(const ShapeRec &S, const PconRec
             const double v = P.bo[j] * uz;
             const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
             const double disc = B * B - A * C;
-            const double s = fsqrt(fmax(disc, 0.0));
+            const double s = disc_sqrt(disc, B);
             const double t = root_down(A, B, C, s);
             const double zh = fma(t, uz, z);
-            const bool ok = disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi &&
-                            (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+            const bool ok = disc_ok(disc, B) && t >= 0.0 && zh >= zlo && zh <= zhi &&
+                            (!SEG || wedge_in_hit(S, fma(t, ux, x), fma(t, uy, y)));
             take(ok, t, 5 + 2 * j, best, sid);
         }
         if ((P.hole_mask >> j) & 1) {  // inner nappe: left from the hole
@@ -635,11 +696,11 @@ __device__ __forceinline__ double pcon_dist_out(const ShapeRec &S, const PconRec
             const double v = P.bi[j] * uz;
             const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
             const double disc = B * B - A * C;
-            const double s = fsqrt(fmax(disc, 0.0));
+            const double s = disc_sqrt(disc, B);
             const double t = root_up(A, B, C, s);
             const double zh = fma(t, uz, z);
-            const bool ok = disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi &&
-                            (!SEG || wedge_in(S, fma(t, ux, x), fma(t, uy, y)));
+            const bool ok = disc_ok(disc, B) && t >= 0.0 && zh >= zlo && zh <= zhi &&
+                            (!SEG || wedge_in_hit(S, fma(t, ux, x), fma(t, uy, y)));
             take(ok, t, 6 + 2 * j, best, sid);
         }
     }
@@ -667,20 +728,20 @@ __device__ __forceinline__ double pcon_dist_in(const ShapeRec &S, const PconRec 
             const double v = P.bo[j] * uz;
             const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
             const double disc = B * B - A * C;
-            const double s = fsqrt(fmax(disc, 0.0));
+            const double s = disc_sqrt(disc, B);
             const double t = root_up(A, B, C, s);
             const double zh = fma(t, uz, z);
-            take(disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi, t, 5 + 2 * j, best, sid);
+            take(disc_ok(disc, B) && t >= 0.0 && zh >= zlo && zh <= zhi, t, 5 + 2 * j, best, sid);
         }
         if ((P.hole_mask >> j) & 1) {  // enter the hole
             const double w = fma(P.bi[j], z, P.ai[j]);
             const double v = P.bi[j] * uz;
             const double A = A0 - v * v, B = B0 - v * w, C = rsq - w * w;
             const double disc = B * B - A * C;
-            const double s = fsqrt(fmax(disc, 0.0));
+            const double s = disc_sqrt(disc, B);
             const double t = root_down(A, B, C, s);
             const double zh = fma(t, uz, z);
-            take(disc >= 0.0 && t >= 0.0 && zh >= zlo && zh <= zhi, t, 6 + 2 * j, best, sid);
+            take(disc_ok(disc, B) && t >= 0.0 && zh >= zlo && zh <= zhi, t, 6 + 2 * j, best, sid);
         }
     }
     if (SEG) wedge_exit(S, x, y, ux, uy, best, sid);

@@ -8,7 +8,9 @@ exactly) unless the track is ill-conditioned, i.e. one of:
   * moving the origin by 1e-9 along any axis (both signs) changes the result
     by more than an FP64 evaluation can resolve at 1e-12: the difference
     quotient kappa satisfies kappa * (|p| + |ref| + 1) * 8 eps > 1e-12 * max(|ref|, 1),
-    or flips hit/miss;
+    or flips hit/miss, in either the double or the long-double build (a line
+    that only touches the closed solid at one point is a hit or a miss by
+    rounding, and one build may see the flip where the other does not);
   * for Contains: the point lies within 1e-9 of the surface;
   * for the navigator's hit index: the two smallest candidate distances are
     within 1e-9 of each other.
@@ -54,7 +56,7 @@ def ill_conditioned(f_d, f_ld, tracks):
     ref = f_ld(tracks)
     rd = f_d(tracks)
     flag = rel_diff(rd, ref) > 1e-13
-    kap = _kappa(f_d, tracks, rd)
+    kap = np.maximum(_kappa(f_d, tracks, rd), _kappa(f_ld, tracks, ref))
     scale = np.linalg.norm(tracks[:3], axis=0) + np.where(ref < BIG, np.abs(ref), 0.0) + 1.0
     flag |= kap * scale * 8 * EPS > TOL * np.maximum(np.where(ref < BIG, np.abs(ref), 1.0), 1.0)
     return ref, flag

@@ -158,3 +158,61 @@ def test_errors_raise(gv):
         gv.geo_shape_query(W.TUBE, [5, 1, 1], 0, t)
     with pytest.raises(ValueError):
         gv.geo_shape_query(W.BOX, [1, 1, 1], 3, t[:3].contiguous())
+
+
+def _edge_points(rng, kind, par, m):
+    """Points on the edges of a shape, where two of its surfaces meet: box
+    edges, the rims of tubes and cones (outer and inner), and for segments
+    the lines where a flat face meets the curved surfaces and the end
+    planes."""
+    par = np.asarray(par, float)
+    if kind == W.BOX:
+        d = par[:3]
+        p = rng.uniform(-1, 1, (3, m)) * d[:, None]
+        a = rng.integers(0, 3, m)                     # the free axis
+        for i in range(3):
+            fix = a != i
+            p[i, fix] = np.where(rng.uniform(size=fix.sum()) < 0.5, -d[i], d[i])
+        return p
+    if kind in (W.TUBE, W.TUBS):
+        rin1 = rin2 = par[0]
+        rout1 = rout2 = par[1]
+        dz = par[2]
+    else:
+        dz, rin1, rout1, rin2, rout2 = par[:5]
+    top = rng.uniform(size=m) < 0.5
+    outer = rng.uniform(size=m) < 0.5
+    r = np.where(top, np.where(outer, rout2, rin2), np.where(outer, rout1, rin1))
+    z = np.where(top, dz, -dz)
+    if kind in (W.TUBE, W.CONE):
+        ph = rng.uniform(0, 2 * np.pi, m)
+    else:
+        phi1, dphi = W.segment_range(kind, par)
+        ph = phi1 + dphi * rng.integers(0, 2, m)
+        # half of them on the face's edge with the curved surfaces instead
+        side = rng.uniform(size=m) < 0.5
+        f = rng.uniform(size=m)
+        z = np.where(side, -dz + 2 * dz * f, z)
+        r = np.where(side, np.where(outer, rout1 + (rout2 - rout1) * f, rin1 + (rin2 - rin1) * f), r)
+    return np.stack([r * np.cos(ph), r * np.sin(ph), z])
+
+
+@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS])
+def test_tracks_aimed_at_edges(gv, orc, kind):
+    """Lines from random origins through points of the shape's edges (rims,
+    box edges, a cone's apex, the edges of a segment's faces). At an edge
+    two surfaces' range tests meet, and through an apex the nappe's
+    quadratic has a double root; yet a small move of such a line changes
+    the distance only slightly, so these tracks are not exempt as
+    ill-conditioned unless they merely touch the solid (a line through an
+    edge of a convex solid from outside does so about half the time, and
+    more often at a segment's face edges)."""
+    rng = np.random.default_rng(61 + kind)
+    par = W.SUITE_SHAPES[kind]
+    m = 6000
+    q = _edge_points(rng, kind, par, m)
+    o = rng.uniform(-45, 45, (3, m))
+    d = q - o
+    d /= np.linalg.norm(d, axis=0)
+    t = np.ascontiguousarray(np.concatenate([o, d]))
+    print(compare(gv, orc, kind, par, t, f"{W.KIND_NAMES[kind]} edges", max_exempt_frac=0.6))
