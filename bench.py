@@ -255,19 +255,17 @@ def read_traffic(digest: str, launch: str):
     path = os.path.join(ROOT, "profiles", "k_nav_tiles_batched512.md")
     if not os.path.exists(path):
         return None
-    vals = {}
     with open(path) as f:
         for line in f:
-            if line.startswith("traffic:"):
-                for kv in line.split()[1:]:
-                    k, v = kv.split("=")
-                    vals[k] = v
-    if vals.get("kernel_source") != digest or vals.get("launch") != launch:
-        return None
-    try:
-        return float(vals["bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+            if not line.startswith("traffic:"):
+                continue
+            vals = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if vals.get("kernel_source") == digest and vals.get("launch") == launch:
+                try:
+                    return float(vals["bytes_per_launch"])
+                except (KeyError, ValueError):
+                    return None
+    return None
 
 
 def cpu_baseline(wl, gpu_step, gpu_hit, threads):
