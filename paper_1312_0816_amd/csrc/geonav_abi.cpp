@@ -4,6 +4,7 @@
 // launch-shape autotuner and error reporting.
 #include <algorithm>
 #include <chrono>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -399,7 +400,8 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         char what[64];
         snprintf(what, sizeof what, "volume %d mother", iv);
         PconRec pc;
-        int rc = make_shape(d.mother, r.mother, &pc, nullptr, what);
+        double mother_r = 0.0;
+        int rc = make_shape(d.mother, r.mother, &pc, &mother_r, what);
         if (rc) return rc;
         if (r.mother.kind == kPcon || r.mother.kind == kPcons) {
             pcons.push_back(pc);
@@ -437,7 +439,13 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             std::memcpy(dr.rot, d.placements[k].rot, sizeof dr.rot);
             std::memcpy(dr.tr, d.placements[k].tr, sizeof dr.tr);
             dau.push_back(dr);
-            cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2, std::sqrt(dr.cull_r2), 0.0});
+            {
+                // threshold of the expanded culling test, widened by its rounding bound
+                const double tt = dr.tr[0] * dr.tr[0] + dr.tr[1] * dr.tr[1] + dr.tr[2] * dr.tr[2];
+                const double span = 3.0 * mother_r + std::sqrt(tt);
+                const double q = dr.cull_r2 - tt + 64.0 * DBL_EPSILON * span * span;
+                cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2, std::sqrt(dr.cull_r2), q});
+            }
         }
     }
     geo_geometry *g = new (std::nothrow) geo_geometry();

@@ -81,15 +81,19 @@ struct alignas(16) DaughterRec {
 };
 static_assert(sizeof(DaughterRec) == 368, "DaughterRec layout");
 
-// Culling record of a daughter, in its own compact array (32 B, so the
+// Culling record of a daughter, in its own compact array (48 B, so the
 // records of a whole volume stay in the scalar cache during the daughter
 // loop): the centre of the bounding sphere in the mother frame (T), the
 // culling radius (bounding radius enlarged by 1e-6 relative + 1e-6) and its
-// square.
+// square, and the threshold q of the expanded test of the compacted
+// navigator: that test evaluates |p - T + tau d|^2 - |T|^2 as
+// |p|^2 - 2 p.T + tau (2 (p - T).d + tau |d|^2), whose rounding error is
+// below 16 eps (3 R + |T|)^2 for a segment inside the mother (R the
+// mother's bounding radius); q = r2 - |T|^2 + 64 eps (3 R + |T|)^2.
 struct alignas(16) CullRec {
     double tx, ty, tz, r2;
     double r;    // the enlarged radius itself
-    double pad;
+    double q;
 };
 static_assert(sizeof(CullRec) == 48, "CullRec layout");
 
@@ -1073,6 +1077,212 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
         best = better ? s : best;
         hit = better ? k : hit;
         if (TRACK_SURF) bsid = better ? sid : bsid;
+    }
+    best = best == 0.0 ? 0.0 : best;  // a step of -0 is reported as +0
+}
+
+// ------------------------------------------------ compacted navigator
+// The culling test above leaves a wavefront evaluating a daughter for all 64
+// lanes when any one lane needs it; with random tracks about one lane in 64
+// does. The compacted form separates the two: the wavefront first runs the
+// culling tests of its tracks against every daughter (lockstep, as above)
+// and appends each (track, daughter) pair that passes to a queue in LDS;
+// then each lane takes one queued pair and evaluates that daughter's
+// DistFromOutside for that track, so a batch of 64 pairs costs one pass
+// (the lanes of different kinds take their kinds' code in turn).
+//
+// The step of a track is the minimum over its candidates of (s, index),
+// compared lexicographically with the mother as index -1: the result of
+// the sequential loop, whose strict < keeps the earlier of equal steps.
+// Each track's running minimum sits in LDS as a 64-bit key (an
+// order-preserving map of the double, -0 taken as +0, so that a step of -0
+// is reported as +0 as in the sequential loop) and an index; a
+// batch merges into it with a 64-bit LDS min on the key, then, for the
+// pairs whose key equals the new minimum, an integer min on the index
+// (reset first when the batch lowered the key). Pairs of one track enter
+// the queue in increasing daughter order, so an earlier batch never holds
+// a larger index of an equal step.
+//
+// The culling tests use the mother's step as the track's reach (the sphere
+// must meet the segment from p to p + s_mother d); that is at least the
+// final step, so a culled daughter could not have lowered the step or won
+// a tie: the results equal those of evaluating every daughter.
+//
+// Queue entries pack the daughter index (bits 10..31), the track's round
+// within the tile (bits 6..9) and its lane (bits 0..5). All LDS traffic of
+// a queue is the wavefront's own, whose LDS instructions execute in program
+// order, so no barrier is needed.
+constexpr int kQueueCap = 256;
+template <int U>
+struct NavScratch {
+    unsigned long long key[U * 64];
+    int hit[U * 64];
+    unsigned int queue[kQueueCap];
+};
+
+// A NaN daughter step never wins and a NaN mother step is never beaten, as
+// in the sequential loop.
+__device__ __forceinline__ unsigned long long step_key(double s, bool mother = false) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(s == 0.0 ? 0.0 : s);
+    const unsigned long long k = (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+    return s == s ? k : (mother ? 0ull : ~0ull);
+}
+__device__ __forceinline__ double key_step(unsigned long long k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+
+// Accesses to the running minima, which other lanes of the wavefront update
+// atomically.
+template <typename T>
+__device__ __forceinline__ T lds_load(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+template <typename T>
+__device__ __forceinline__ void lds_store(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+template <int U, bool HAS_OFFS, bool COUNT, int KSET>
+__device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
+                                          const CullRec *__restrict__ cul,
+                                          const double *__restrict__ offs, const TracksDev &t,
+                                          int64_t base, NavScratch<U> &S, int qn, int lane,
+                                          unsigned long long *census) {
+    for (int e0 = 0; e0 < qn; e0 += 64) {
+        const int e = e0 + lane;
+        const bool on = e < qn;
+        const unsigned int q = on ? S.queue[e] : 0u;
+        const int j = (int)(q & 1023u);  // round * 64 + lane of the track
+        const int k = (int)(q >> 10);
+        if (COUNT) {
+            const int slot = 2 * dau[k].shape.kind + dau[k].shape.hole;
+            for (int sl = 0; sl < 2 * (kPcons + 1); ++sl) {
+                const unsigned long long m = __ballot(on && slot == sl);
+                if (m != 0ull && lane == __ffsll(m) - 1) atomicAdd(&census[sl], (unsigned long long)__popcll(m));
+            }
+        }
+        if (on) {
+            const int64_t i = base + j;
+            const double x = t.x[i], y = t.y[i], z = t.z[i];
+            const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+            const CullRec &Q = cul[k];
+            double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
+            if (HAS_OFFS) {
+                wx -= offs[3 * k + 0];
+                wy -= offs[3 * k + 1];
+                wz -= offs[3 * k + 2];
+            }
+            const DaughterRec &D = dau[k];
+            const double *R = D.rot;
+            const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+            const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+            const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+            const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
+            const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
+            const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
+            int sid;
+            const double s = any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
+            const unsigned long long key = step_key(s);
+            const unsigned long long before = lds_load(&S.key[j]);
+            __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const unsigned long long now = lds_load(&S.key[j]);
+            if (now < before) lds_store(&S.hit[j], 0x7fffffff);
+            if (key == now) __hip_atomic_fetch_min(&S.hit[j], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+    }
+}
+
+// Navigates the tracks base + u * 64 + lane (u < U, index below `count`
+// past base) of one volume, writing step, hit and (when HITPT) the hit
+// point.
+template <int U, bool HAS_OFFS, bool HITPT, bool COUNT, int KSET>
+__device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                            const CullRec *__restrict__ cul,
+                                            const double *__restrict__ offs, const TracksDev &t,
+                                            int64_t base, int count, NavScratch<U> &S, int lane,
+                                            double *__restrict__ step, int32_t *__restrict__ hit,
+                                            double *__restrict__ hitpt,
+                                            unsigned long long *census = nullptr) {
+    int qn = 0;  // queue length (uniform)
+    const int nd = v.nd;
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+        if (u * 64 >= count) break;
+        const int j = u * 64 + lane;
+        const bool act = j < count;
+        const unsigned long long amask = __builtin_amdgcn_ballot_w64(act);
+        const int64_t i = base + (act ? j : 0);
+        const double x = t.x[i], y = t.y[i], z = t.z[i];
+        const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+        if (COUNT && lane == 0) atomicAdd(&census[kCensusTracks], (unsigned long long)__popcll(amask));
+        int sid;
+        // (canonicalized once here rather than by every fmin below)
+        const double reach =
+            __builtin_canonicalize(any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid));
+        lds_store(&S.key[j], step_key(reach, true));
+        lds_store(&S.hit[j], -1);
+        // per-track constants of the culling test: |d|^2, 1 / (2 |d|^2), and
+        // for the expanded form (no offsets) |p|^2, 2 p.d, -2 p, -2 d
+        const double dd = fma(uz, uz, fma(uy, uy, ux * ux));
+        const double hdd = dd > 0.0 ? fdiv(0.5, dd) : 0.0;
+        const double pp = fma(z, z, fma(y, y, x * x));
+        const double pd2 = 2.0 * fma(z, uz, fma(y, uy, x * ux));
+        const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
+        const double mux = -2.0 * ux, muy = -2.0 * uy, muz = -2.0 * uz;
+        for (int k = 0; k < nd; ++k) {
+            const CullRec &Q = cul[k];
+            double b2, g, lim;  // 2 w.d and |w|^2 - shift, with w = p - centre; lim = r2 - shift
+            if (HAS_OFFS) {
+                // the centre moves with the offset: w formed explicitly, shift 0
+                const double wx = x - Q.tx - offs[3 * k + 0];
+                const double wy = y - Q.ty - offs[3 * k + 1];
+                const double wz = z - Q.tz - offs[3 * k + 2];
+                b2 = fma(wz, -muz, fma(wy, -muy, wx * -mux));
+                g = fma(wz, wz, fma(wy, wy, wx * wx));
+                lim = Q.r2;
+            } else {
+                // shift |T|^2, rounding covered by q
+                b2 = fma(Q.tz, muz, fma(Q.ty, muy, fma(Q.tx, mux, pd2)));
+                g = fma(Q.tz, mpz, fma(Q.ty, mpy, fma(Q.tx, mpx, pp)));
+                lim = Q.q;
+            }
+            const double tau = fmax(fmin(-b2 * hdd, reach), 0.0);
+            const double f = fma(tau, fma(tau, dd, b2), g);             // |w + tau d|^2 - shift
+            // every lane's f is defined; lanes past the tile's end are masked out
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
+            if (COUNT && lane == 0) atomicAdd(&census[kCensusCull], (unsigned long long)__popcll(amask));
+            if (m == 0ull) continue;
+            const int c = __popcll(m);
+            if (qn + c > kQueueCap) {
+                nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
+                qn = 0;
+            }
+            if ((m >> lane) & 1ull) S.queue[qn + lanes_below(m)] = ((unsigned int)k << 10) | (unsigned int)j;
+            qn += c;
+        }
+    }
+    nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+        const int j = u * 64 + lane;
+        if (j < count) {
+            const int64_t i = base + j;
+            const double s = key_step(lds_load(&S.key[j]));
+            step[i] = s;
+            hit[i] = lds_load(&S.hit[j]);
+            if (HITPT) {
+                const int64_t n = t.n;
+                hitpt[i] = fma(s, t.ux[i], t.x[i]);
+                hitpt[n + i] = fma(s, t.uy[i], t.y[i]);
+                hitpt[2 * n + i] = fma(s, t.uz[i], t.z[i]);
+            }
+        }
     }
 }
 

@@ -97,6 +97,17 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
                                                        double *__restrict__ step,
                                                        int32_t *__restrict__ hit,
                                                        double *__restrict__ hitpt) {
+    if constexpr (CULL) {
+        // one wavefront per 64 tracks, compacted evaluation
+        __shared__ NavScratch<1> scr[kBlock / 64];
+        const int wave = threadIdx.x >> 6;
+        const int64_t base = (int64_t)blockIdx.x * kBlock + wave * 64;
+        if (base >= t.n) return;
+        const int count = t.n - base < 64 ? (int)(t.n - base) : 64;
+        nav_compact<1, HAS_OFFS, HITPT, false, KSET>(*vol, dau, cul, offs, t, base, count, scr[wave],
+                                                     (int)(threadIdx.x & 63), step, hit, hitpt);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
     const double x = t.x[i], y = t.y[i], z = t.z[i];
@@ -208,10 +219,16 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__rest
                                          const DaughterRec *__restrict__ dau_all,
                                          const CullRec *__restrict__ cul_all, const TracksDev &t,
                                          double *__restrict__ step, int32_t *__restrict__ hit,
-                                         unsigned long long *census, int lane) {
+                                         unsigned long long *census, int lane,
+                                         NavScratch<U> *scr) {
     const VolumeRec &v = vols[tl.volume];
     const DaughterRec *dau = dau_all + v.first;
     const CullRec *cul = cul_all + v.first;
+    if constexpr (CULL) {
+        nav_compact<U, false, false, COUNT, KSET>(v, dau, cul, nullptr, t, tl.offset, tl.count, *scr,
+                                                  lane, step, hit, nullptr, census);
+        return;
+    }
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;
@@ -246,6 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
                                                            int32_t *__restrict__ hit,
                                                            unsigned long long *census) {
     const int lane = threadIdx.x & 63;
+    __shared__ NavScratch<U> scr[CULL ? kBlock / 64 : 1];
+    NavScratch<U> *my = &scr[CULL ? (threadIdx.x >> 6) : 0];
     const int home = (int)(blockIdx.x % kQueues);
     for (int qq = 0; qq < kQueues; ++qq) {
         const int q = (home + qq) % kQueues;
@@ -256,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
             id = (unsigned int)__builtin_amdgcn_readfirstlane((int)id);
             if (id >= count) break;
             run_tile<U, CULL, COUNT, KSET>(tiles[q + kQueues * (int64_t)id], vols, dau_all, cul_all, t,
-                                           step, hit, census, lane);
+                                           step, hit, census, lane, my);
         }
     }
 }
@@ -273,10 +292,11 @@ __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restric
                                                       int32_t *__restrict__ hit,
                                                       unsigned long long *census) {
     (void)cursors;
+    __shared__ NavScratch<U> scr[CULL ? kBlock / 64 : 1];
     const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
     if (w >= ntiles) return;
     run_tile<U, CULL, COUNT, KSET>(tiles[w], vols, dau_all, cul_all, t, step, hit, census,
-                                   (int)(threadIdx.x & 63));
+                                   (int)(threadIdx.x & 63), &scr[CULL ? (threadIdx.x >> 6) : 0]);
 }
 
 // Expands the (cost-sorted) basket list into tiles of at most tile_n tracks:
