@@ -447,6 +447,13 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
                 cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2, std::sqrt(dr.cull_r2), q});
             }
         }
+        // pad to whole culling chunks with records that never pass a test
+        while ((dau.size() - (size_t)r.first) % kCullChunk != 0) {
+            DaughterRec pad;
+            std::memset(&pad, 0, sizeof pad);
+            dau.push_back(pad);
+            cul.push_back(CullRec{0.0, 0.0, 0.0, -HUGE_VAL, 0.0, -HUGE_VAL});
+        }
     }
     geo_geometry *g = new (std::nothrow) geo_geometry();
     if (!g) return fail(GEO_ERR_NOMEM, "host allocation failed");

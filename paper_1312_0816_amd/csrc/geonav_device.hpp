@@ -56,6 +56,10 @@ static_assert(sizeof(ShapeRec) == 240, "ShapeRec layout");
 // j's nappes being r = ao[j] + bo[j] z (outer) and ai[j] + bi[j] z (inner,
 // present when bit j of hole_mask is set: not both inner radii 0).
 constexpr int kPconMax = 8;
+// The daughter and culling tables hold each volume's records padded to a
+// multiple of kCullChunk; padding records have r2 = q = -infinity, so that
+// no culling test passes them.
+constexpr int kCullChunk = 4;
 struct alignas(16) PconRec {
     int32_t nz;
     int32_t hole_mask;
@@ -1112,7 +1116,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // within the tile (bits 6..9) and its lane (bits 0..5). All LDS traffic of
 // a queue is the wavefront's own, whose LDS instructions execute in program
 // order, so no barrier is needed.
-constexpr int kQueueCap = 256;
+constexpr int kQueueCap = 512;
 template <int U>
 struct NavScratch {
     unsigned long long key[U * 64];
@@ -1211,6 +1215,7 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
                                             unsigned long long *census = nullptr) {
     int qn = 0;  // queue length (uniform)
     const int nd = v.nd;
+    const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         if (u * 64 >= count) break;
@@ -1235,36 +1240,55 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
         const double pd2 = 2.0 * fma(z, uz, fma(y, uy, x * ux));
         const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
         const double mux = -2.0 * ux, muy = -2.0 * uy, muz = -2.0 * uz;
-        for (int k = 0; k < nd; ++k) {
-            const CullRec &Q = cul[k];
-            double b2, g, lim;  // 2 w.d and |w|^2 - shift, with w = p - centre; lim = r2 - shift
-            if (HAS_OFFS) {
-                // the centre moves with the offset: w formed explicitly, shift 0
-                const double wx = x - Q.tx - offs[3 * k + 0];
-                const double wy = y - Q.ty - offs[3 * k + 1];
-                const double wz = z - Q.tz - offs[3 * k + 2];
-                b2 = fma(wz, -muz, fma(wy, -muy, wx * -mux));
-                g = fma(wz, wz, fma(wy, wy, wx * wx));
-                lim = Q.r2;
-            } else {
-                // shift |T|^2, rounding covered by q
-                b2 = fma(Q.tz, muz, fma(Q.ty, muy, fma(Q.tx, mux, pd2)));
-                g = fma(Q.tz, mpz, fma(Q.ty, mpy, fma(Q.tx, mpx, pp)));
-                lim = Q.q;
-            }
-            const double tau = fmax(fmin(-b2 * hdd, reach), 0.0);
-            const double f = fma(tau, fma(tau, dd, b2), g);             // |w + tau d|^2 - shift
-            // every lane's f is defined; lanes past the tile's end are masked out
-            const unsigned long long m = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
-            if (COUNT && lane == 0) atomicAdd(&census[kCensusCull], (unsigned long long)__popcll(amask));
-            if (m == 0ull) continue;
-            const int c = __popcll(m);
-            if (qn + c > kQueueCap) {
+        // Daughters in chunks of kCullChunk (the tables are padded to whole
+        // chunks with records that never pass): the queue is flushed between
+        // chunks when a chunk could overflow it, so the tests of a chunk run
+        // back to back.
+        for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
+            if (qn > kQueueCap - 64 * kCullChunk) {
                 nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
                 qn = 0;
             }
-            if ((m >> lane) & 1ull) S.queue[qn + lanes_below(m)] = ((unsigned int)k << 10) | (unsigned int)j;
-            qn += c;
+            // the chunk's records, loaded together (scalar loads)
+            double ctx[kCullChunk], cty[kCullChunk], ctz[kCullChunk], clim[kCullChunk];
+#pragma unroll
+            for (int kk = 0; kk < kCullChunk; ++kk) {
+                const CullRec &Q = cul[k0 + kk];
+                ctx[kk] = Q.tx;
+                cty[kk] = Q.ty;
+                ctz[kk] = Q.tz;
+                clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
+            }
+#pragma unroll
+            for (int kk = 0; kk < kCullChunk; ++kk) {
+                const int k = k0 + kk;
+                double b2, g;  // 2 w.d and |w|^2 - shift, with w = p - centre
+                if (HAS_OFFS) {
+                    // the centre moves with the offset: w formed explicitly, shift 0,
+                    // limit r2
+                    const int ko = k < nd ? k : 0;  // (padding records never pass)
+                    const double wx = x - ctx[kk] - offs[3 * ko + 0];
+                    const double wy = y - cty[kk] - offs[3 * ko + 1];
+                    const double wz = z - ctz[kk] - offs[3 * ko + 2];
+                    b2 = fma(wz, -muz, fma(wy, -muy, wx * -mux));
+                    g = fma(wz, wz, fma(wy, wy, wx * wx));
+                } else {
+                    // shift |T|^2, limit q (its rounding bound included)
+                    b2 = fma(ctz[kk], muz, fma(cty[kk], muy, fma(ctx[kk], mux, pd2)));
+                    g = fma(ctz[kk], mpz, fma(cty[kk], mpy, fma(ctx[kk], mpx, pp)));
+                }
+                const double lim = clim[kk];
+                const double tau = fmax(fmin(-b2 * hdd, reach), 0.0);
+                const double f = fma(tau, fma(tau, dd, b2), g);             // |w + tau d|^2 - shift
+                // every lane's f is defined; lanes past the tile's end are masked out
+                const unsigned long long m = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
+                if (COUNT && lane == 0 && k < nd)
+                    atomicAdd(&census[kCensusCull], (unsigned long long)__popcll(amask));
+                if (m == 0ull) continue;
+                if (__builtin_amdgcn_inverse_ballot_w64(m))
+                    S.queue[qn + lanes_below(m)] = ((unsigned int)k << 10) | (unsigned int)j;
+                qn += __popcll(m);
+            }
         }
     }
     nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
