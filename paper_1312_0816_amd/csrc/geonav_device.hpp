@@ -1259,6 +1259,9 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
                 ctz[kk] = Q.tz;
                 clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
             }
+            // the chunk's tests (independent, so they interleave), then its
+            // queue appends
+            unsigned long long cm[kCullChunk];
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 const int k = k0 + kk;
@@ -1281,7 +1284,12 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
                 const double tau = fmax(fmin(-b2 * hdd, reach), 0.0);
                 const double f = fma(tau, fma(tau, dd, b2), g);             // |w + tau d|^2 - shift
                 // every lane's f is defined; lanes past the tile's end are masked out
-                const unsigned long long m = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
+                cm[kk] = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
+            }
+#pragma unroll
+            for (int kk = 0; kk < kCullChunk; ++kk) {
+                const int k = k0 + kk;
+                const unsigned long long m = cm[kk];
                 if (COUNT && lane == 0 && k < nd)
                     atomicAdd(&census[kCensusCull], (unsigned long long)__popcll(amask));
                 if (m == 0ull) continue;
