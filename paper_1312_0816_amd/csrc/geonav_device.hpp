@@ -1318,6 +1318,131 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
     }
 }
 
+// ---------------------------- compacted navigator safety and localization
+// The same queue for the navigator's other two tasks. Safety: a daughter is
+// queued for a point when |w| < s_mother + r (its Safety is at least
+// |w| - r, so otherwise it cannot go below the mother's, hence not below the
+// minimum); the minimum is merged as a 64-bit key like the step (-0 as +0).
+// Localization: a daughter is queued for a point inside the mother when
+// |w| <= r; the lowest index of a queued daughter that contains the point
+// wins (an integer LDS min). The culling tests form w = p - T explicitly, as
+// points may lie outside the mother. The sequential loops report -0 as +0
+// too, so both forms give the same bits.
+__device__ __forceinline__ unsigned long long safety_key(double s) {
+    return s == s ? step_key(s) : ~0ull;
+}
+
+template <int MODE, bool HAS_OFFS, int KSET>  // MODE 0: safety, 1: locate
+__device__ __forceinline__ void point_flush(const DaughterRec *__restrict__ dau,
+                                            const CullRec *__restrict__ cul,
+                                            const double *__restrict__ offs, const TracksDev &t,
+                                            int64_t base, NavScratch<1> &S, int qn, int lane) {
+    for (int e0 = 0; e0 < qn; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < qn) {
+            const unsigned int q = S.queue[e];
+            const int j = (int)(q & 63u);
+            const int k = (int)(q >> 10);
+            const int64_t i = base + j;
+            const CullRec &Q = cul[k];
+            double wx = t.x[i] - Q.tx, wy = t.y[i] - Q.ty, wz = t.z[i] - Q.tz;
+            if (HAS_OFFS) {
+                wx -= offs[3 * k + 0];
+                wy -= offs[3 * k + 1];
+                wz -= offs[3 * k + 2];
+            }
+            const DaughterRec &D = dau[k];
+            const double *R = D.rot;
+            const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+            const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+            const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+            if (MODE == 0) {
+                const unsigned long long key = safety_key(any_safety<KSET>(D.shape, D.pcon, lx, ly, lz));
+                __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            } else if (any_contains<KSET>(D.shape, D.pcon, lx, ly, lz)) {
+                __hip_atomic_fetch_min(&S.hit[j], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+        }
+    }
+}
+
+// Safety (MODE 0, out_s) or localization (MODE 1, out_w) of the points
+// base + lane, lane < count.
+template <int MODE, bool HAS_OFFS, int KSET>
+__device__ __forceinline__ void point_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                              const CullRec *__restrict__ cul,
+                                              const double *__restrict__ offs, const TracksDev &t,
+                                              int64_t base, int count, NavScratch<1> &S, int lane,
+                                              double *__restrict__ out_s,
+                                              int32_t *__restrict__ out_w) {
+    const bool act = lane < count;
+    const int64_t i = base + (act ? lane : 0);
+    const double x = t.x[i], y = t.y[i], z = t.z[i];
+    double reach = 0.0;
+    bool in_m = false;
+    if (MODE == 0) {
+        const double ms = any_safety<KSET>(v.mother, v.pcon, x, y, z);
+        lds_store(&S.key[lane], safety_key(ms));
+        reach = ms;
+    } else {
+        in_m = any_contains<KSET>(v.mother, v.pcon, x, y, z);
+        lds_store(&S.hit[lane], 0x7fffffff);
+    }
+    const unsigned long long amask = __builtin_amdgcn_ballot_w64(MODE == 0 ? act : (act && in_m));
+    int qn = 0;
+    const int nd = v.nd;
+    if (amask != 0ull) {
+        const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
+        for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
+            if (qn > kQueueCap - 64 * kCullChunk) {
+                point_flush<MODE, HAS_OFFS, KSET>(dau, cul, offs, t, base, S, qn, lane);
+                qn = 0;
+            }
+            unsigned long long cm[kCullChunk];
+#pragma unroll
+            for (int kk = 0; kk < kCullChunk; ++kk) {
+                const int k = k0 + kk;
+                const CullRec &Q = cul[k];
+                double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
+                if (HAS_OFFS) {
+                    const int ko = k < nd ? k : 0;
+                    wx -= offs[3 * ko + 0];
+                    wy -= offs[3 * ko + 1];
+                    wz -= offs[3 * ko + 2];
+                }
+                const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
+                bool pass;
+                if (MODE == 0) {
+                    const double lim = reach + Q.r;
+                    pass = ww < lim * lim;
+                } else {
+                    pass = ww <= Q.r2;
+                }
+                // padding records (k >= nd) are excluded here: their radius is 0
+                cm[kk] = __builtin_amdgcn_ballot_w64(pass) & (k < nd ? amask : 0ull);
+            }
+#pragma unroll
+            for (int kk = 0; kk < kCullChunk; ++kk) {
+                const unsigned long long m = cm[kk];
+                if (m == 0ull) continue;
+                if (__builtin_amdgcn_inverse_ballot_w64(m))
+                    S.queue[qn + lanes_below(m)] = ((unsigned int)(k0 + kk) << 10) | (unsigned int)lane;
+                qn += __popcll(m);
+            }
+        }
+    }
+    point_flush<MODE, HAS_OFFS, KSET>(dau, cul, offs, t, base, S, qn, lane);
+    if (act) {
+        const int64_t o = base + lane;
+        if (MODE == 0) {
+            out_s[o] = key_step(lds_load(&S.key[lane]));
+        } else {
+            const int w = lds_load(&S.hit[lane]);
+            out_w[o] = !in_m ? -2 : (w != 0x7fffffff ? w : -1);
+        }
+    }
+}
+
 // ------------------------------------------ navigator safety and locate
 // The navigator's other two per-track tasks (section 3). With CULL, a
 // daughter is skipped by the whole wavefront when its bounding sphere (the
@@ -1353,7 +1478,7 @@ __device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterR
         const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
         best = fmin(best, any_safety<KSET>(D.shape, D.pcon, lx, ly, lz));
     }
-    return best;
+    return best == 0.0 ? 0.0 : best;  // -0 reported as +0
 }
 
 // Daughter holding the point (lowest index), -1 for the mother's own part,

@@ -157,6 +157,16 @@ __global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restri
                                                        const CullRec *__restrict__ cul, TracksDev t,
                                                        const double *__restrict__ offs,
                                                        double *__restrict__ out) {
+    if constexpr (CULL) {
+        __shared__ NavScratch<1> scr[kBlock / 64];
+        const int wave = threadIdx.x >> 6;
+        const int64_t base = (int64_t)blockIdx.x * kBlock + wave * 64;
+        if (base >= t.n) return;
+        const int count = t.n - base < 64 ? (int)(t.n - base) : 64;
+        point_compact<0, HAS_OFFS, KSET>(*vol, dau, cul, offs, t, base, count, scr[wave],
+                                         (int)(threadIdx.x & 63), out, nullptr);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
     out[i] = nav_safety<HAS_OFFS, CULL, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
@@ -168,6 +178,16 @@ __global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restri
                                                        const CullRec *__restrict__ cul, TracksDev t,
                                                        const double *__restrict__ offs,
                                                        int32_t *__restrict__ out) {
+    if constexpr (CULL) {
+        __shared__ NavScratch<1> scr[kBlock / 64];
+        const int wave = threadIdx.x >> 6;
+        const int64_t base = (int64_t)blockIdx.x * kBlock + wave * 64;
+        if (base >= t.n) return;
+        const int count = t.n - base < 64 ? (int)(t.n - base) : 64;
+        point_compact<1, HAS_OFFS, KSET>(*vol, dau, cul, offs, t, base, count, scr[wave],
+                                         (int)(threadIdx.x & 63), nullptr, out);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
     out[i] = nav_locate<HAS_OFFS, CULL, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
