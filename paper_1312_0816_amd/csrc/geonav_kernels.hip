@@ -89,7 +89,10 @@ hipError_t launch_shape_query(const ShapeRec &s, const PconRec &pc, int query, c
 }
 
 // ---------------------------------------------------------- basket navigator
-template <bool HAS_OFFS, bool HITPT, bool CULL, int KSET>
+// With culling, one wavefront takes U rounds of 64 tracks (compacted
+// evaluation; more tracks per wavefront fill more lanes of each batch of
+// queued pairs).
+template <bool HAS_OFFS, bool HITPT, bool CULL, int KSET, int U = 1>
 __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
                                                        const CullRec *__restrict__ cul,
@@ -98,13 +101,12 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
                                                        int32_t *__restrict__ hit,
                                                        double *__restrict__ hitpt) {
     if constexpr (CULL) {
-        // one wavefront per 64 tracks, compacted evaluation
-        __shared__ NavScratch<1> scr[kBlock / 64];
+        __shared__ NavScratch<U> scr[kBlock / 64];
         const int wave = threadIdx.x >> 6;
-        const int64_t base = (int64_t)blockIdx.x * kBlock + wave * 64;
+        const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         if (base >= t.n) return;
-        const int count = t.n - base < 64 ? (int)(t.n - base) : 64;
-        nav_compact<1, HAS_OFFS, HITPT, false, KSET>(*vol, dau, cul, offs, t, base, count, scr[wave],
+        const int count = t.n - base < 64 * U ? (int)(t.n - base) : 64 * U;
+        nav_compact<U, HAS_OFFS, HITPT, false, KSET>(*vol, dau, cul, offs, t, base, count, scr[wave],
                                                      (int)(threadIdx.x & 63), step, hit, hitpt);
         return;
     }
@@ -126,27 +128,37 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     }
 }
 
-template <bool CULL, int KSET>
+template <bool CULL, int KSET, int U = 1>
 static void launch_basket_variant(dim3 grid, const VolumeRec *vol, const DaughterRec *dau,
                                   const CullRec *cul, const TracksDev &t, const double *offs, double *step, int32_t *hit,
                                   double *hitpt, hipStream_t st) {
     const dim3 block(kBlock);
     if (offs) {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<true, true, CULL, KSET, U>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<true, false, CULL, KSET, U>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
     } else {
-        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
-        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL, KSET>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        if (hitpt) hipLaunchKernelGGL((k_nav_basket<false, true, CULL, KSET, U>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
+        else hipLaunchKernelGGL((k_nav_basket<false, false, CULL, KSET, U>), grid, block, 0, st, vol, dau, cul, t, offs, step, hit, hitpt);
     }
 }
+
+// Baskets of at least kBasketWide tracks run 4 rounds per wavefront (still
+// about 4096 wavefronts, several per SIMD); smaller ones one round.
+constexpr int64_t kBasketWide = (int64_t)1 << 20;
 
 hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
                              const TracksDev &t, const double *offs, double *step, int32_t *hit,
                              double *hitpt, bool cull, int kset, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
-    if (cull) GN_KSET(kset, (launch_basket_variant<true, KS>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st)));
-    else GN_KSET(kset, (launch_basket_variant<false, KS>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st)));
+    if (cull && t.n >= kBasketWide) {
+        const dim3 grid4((unsigned)((t.n + 4 * kBlock - 1) / (4 * kBlock)));
+        GN_KSET(kset, (launch_basket_variant<true, KS, 4>(grid4, vol, dau, cul, t, offs, step, hit, hitpt, st)));
+    } else if (cull) {
+        GN_KSET(kset, (launch_basket_variant<true, KS>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st)));
+    } else {
+        GN_KSET(kset, (launch_basket_variant<false, KS>(grid, vol, dau, cul, t, offs, step, hit, hitpt, st)));
+    }
     return hipGetLastError();
 }
 
