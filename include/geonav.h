@@ -223,18 +223,21 @@ int geo_autotune(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tra
  * tile size (64 * tracks_per_lane tracks of one volume per wavefront task);
  * waves_per_simd 1..8 selects the persistent kernel with that many
  * wavefronts per SIMD pulling tiles from per-XCD queues, 0 selects one
- * wavefront per tile scheduled by the hardware. Default 4 and 4; the
+ * wavefront per tile scheduled by the hardware. Default 4 and 0; the
  * autotuner may change them. Results do not depend on the launch shape. */
 int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd);
 int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd);
 
-/* Wavefront culling in the navigators (basket, batched, backward): a
- * daughter is skipped by a whole wavefront when no lane's line can enter the
- * daughter's bounding sphere (radius enlarged by 1e-6 relative + 1e-6) before
- * that lane's current best step. The daughter could neither lower a step nor
+/* Culling in the navigators (basket, batched, backward): a daughter is not
+ * evaluated for a track whose line cannot enter the daughter's bounding
+ * sphere (radius enlarged by 1e-6 relative + 1e-6) before the mother's exit
+ * (the backward kernel: before the track's current best step, skipping the
+ * daughter for the whole wavefront when no lane needs it). The forward
+ * navigators queue the (track, daughter) pairs that pass in LDS and evaluate
+ * them one pair per lane. A culled daughter could neither lower a step nor
  * win a tie, so results are bit-identical with culling on or off; only the
  * work done changes. Applies likewise to geo_navigate_safety (a daughter
- * whose sphere is farther than the current safety) and geo_locate (a point
+ * whose sphere is farther than the mother's safety) and geo_locate (a point
  * outside the sphere). On by default. */
 int geo_set_culling(geo_geometry *g, int32_t enable);
 int geo_get_culling(const geo_geometry *g, int32_t *enabled);

@@ -308,7 +308,7 @@ struct geo_geometry {
     double *d_partial = nullptr;
     // batched state
     int tracks_per_lane = 4;
-    int waves_per_simd = 4;
+    int waves_per_simd = 0;  // hardware-scheduled until geo_autotune picks
     bool cull = true;               // wavefront bounding-sphere culling in the navigators
     // Basket lists are staged in a ring of mapped pinned host buffers that the
     // tile-expansion kernel reads directly (no copy node). The ring holds

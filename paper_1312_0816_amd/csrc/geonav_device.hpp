@@ -1103,9 +1103,9 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // is reported as +0 as in the sequential loop) and an index; a
 // batch merges into it with a 64-bit LDS min on the key, then, for the
 // pairs whose key equals the new minimum, an integer min on the index
-// (reset first when the batch lowered the key). Pairs of one track enter
-// the queue in increasing daughter order, so an earlier batch never holds
-// a larger index of an equal step.
+// (reset first when the batch lowered the key). After every batch the slot
+// holds the lexicographic minimum of all candidates merged so far, whatever
+// the order of the batches.
 //
 // The culling tests use the mother's step as the track's reach (the sphere
 // must meet the segment from p to p + s_mother d); that is at least the
@@ -1152,6 +1152,42 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// DistFromOutside of daughter k (records D, Q) for a mother-frame track.
+template <bool HAS_OFFS, int KSET>
+__device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const CullRec &Q,
+                                                    const double *__restrict__ offs, int k, double x,
+                                                    double y, double z, double ux, double uy,
+                                                    double uz) {
+    double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
+    if (HAS_OFFS) {
+        wx -= offs[3 * k + 0];
+        wy -= offs[3 * k + 1];
+        wz -= offs[3 * k + 2];
+    }
+    const double *R = D.rot;
+    const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
+    const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
+    const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
+    const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
+    const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
+    const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
+    int sid;
+    return any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
+}
+
+// Merges candidate (s, k) into track slot j's running minimum. Lanes of one
+// call may share a slot; whatever the order of calls, the slot ends at the
+// lexicographic minimum of all candidates merged.
+template <int U>
+__device__ __forceinline__ void merge_step(NavScratch<U> &S, int j, double s, int k) {
+    const unsigned long long key = step_key(s);
+    const unsigned long long before = lds_load(&S.key[j]);
+    __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const unsigned long long now = lds_load(&S.key[j]);
+    if (now < before) lds_store(&S.hit[j], 0x7fffffff);
+    if (key == now) __hip_atomic_fetch_min(&S.hit[j], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 template <int U, bool HAS_OFFS, bool COUNT, int KSET>
 __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
@@ -1173,31 +1209,9 @@ __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
         }
         if (on) {
             const int64_t i = base + j;
-            const double x = t.x[i], y = t.y[i], z = t.z[i];
-            const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
-            const CullRec &Q = cul[k];
-            double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
-            if (HAS_OFFS) {
-                wx -= offs[3 * k + 0];
-                wy -= offs[3 * k + 1];
-                wz -= offs[3 * k + 2];
-            }
-            const DaughterRec &D = dau[k];
-            const double *R = D.rot;
-            const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
-            const double ly = fma(R[7], wz, fma(R[4], wy, R[1] * wx));
-            const double lz = fma(R[8], wz, fma(R[5], wy, R[2] * wx));
-            const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
-            const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
-            const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
-            int sid;
-            const double s = any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
-            const unsigned long long key = step_key(s);
-            const unsigned long long before = lds_load(&S.key[j]);
-            __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            const unsigned long long now = lds_load(&S.key[j]);
-            if (now < before) lds_store(&S.hit[j], 0x7fffffff);
-            if (key == now) __hip_atomic_fetch_min(&S.hit[j], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, t.x[i], t.y[i],
+                                                               t.z[i], t.ux[i], t.uy[i], t.uz[i]);
+            merge_step(S, j, s, k);
         }
     }
 }
@@ -1332,16 +1346,16 @@ __device__ __forceinline__ unsigned long long safety_key(double s) {
     return s == s ? step_key(s) : ~0ull;
 }
 
-template <int MODE, bool HAS_OFFS, int KSET>  // MODE 0: safety, 1: locate
+template <int MODE, bool HAS_OFFS, int KSET, int U>  // MODE 0: safety, 1: locate
 __device__ __forceinline__ void point_flush(const DaughterRec *__restrict__ dau,
                                             const CullRec *__restrict__ cul,
                                             const double *__restrict__ offs, const TracksDev &t,
-                                            int64_t base, NavScratch<1> &S, int qn, int lane) {
+                                            int64_t base, NavScratch<U> &S, int qn, int lane) {
     for (int e0 = 0; e0 < qn; e0 += 64) {
         const int e = e0 + lane;
         if (e < qn) {
             const unsigned int q = S.queue[e];
-            const int j = (int)(q & 63u);
+            const int j = (int)(q & 1023u);
             const int k = (int)(q >> 10);
             const int64_t i = base + j;
             const CullRec &Q = cul[k];
@@ -1367,35 +1381,41 @@ __device__ __forceinline__ void point_flush(const DaughterRec *__restrict__ dau,
 }
 
 // Safety (MODE 0, out_s) or localization (MODE 1, out_w) of the points
-// base + lane, lane < count.
-template <int MODE, bool HAS_OFFS, int KSET>
+// base + u * 64 + lane (u < U, index below `count` past base). In
+// localization mode the key slots hold whether the point is in the mother.
+template <int MODE, bool HAS_OFFS, int KSET, int U>
 __device__ __forceinline__ void point_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                               const CullRec *__restrict__ cul,
                                               const double *__restrict__ offs, const TracksDev &t,
-                                              int64_t base, int count, NavScratch<1> &S, int lane,
+                                              int64_t base, int count, NavScratch<U> &S, int lane,
                                               double *__restrict__ out_s,
                                               int32_t *__restrict__ out_w) {
-    const bool act = lane < count;
-    const int64_t i = base + (act ? lane : 0);
-    const double x = t.x[i], y = t.y[i], z = t.z[i];
-    double reach = 0.0;
-    bool in_m = false;
-    if (MODE == 0) {
-        const double ms = any_safety<KSET>(v.mother, v.pcon, x, y, z);
-        lds_store(&S.key[lane], safety_key(ms));
-        reach = ms;
-    } else {
-        in_m = any_contains<KSET>(v.mother, v.pcon, x, y, z);
-        lds_store(&S.hit[lane], 0x7fffffff);
-    }
-    const unsigned long long amask = __builtin_amdgcn_ballot_w64(MODE == 0 ? act : (act && in_m));
     int qn = 0;
     const int nd = v.nd;
-    if (amask != 0ull) {
-        const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
+    const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+        if (u * 64 >= count) break;
+        const int j = u * 64 + lane;
+        const bool act = j < count;
+        const int64_t i = base + (act ? j : 0);
+        const double x = t.x[i], y = t.y[i], z = t.z[i];
+        double reach = 0.0;
+        bool in_m = false;
+        if (MODE == 0) {
+            const double ms = any_safety<KSET>(v.mother, v.pcon, x, y, z);
+            lds_store(&S.key[j], safety_key(ms));
+            reach = ms;
+        } else {
+            in_m = any_contains<KSET>(v.mother, v.pcon, x, y, z);
+            lds_store(&S.key[j], (unsigned long long)in_m);
+            lds_store(&S.hit[j], 0x7fffffff);
+        }
+        const unsigned long long amask = __builtin_amdgcn_ballot_w64(MODE == 0 ? act : (act && in_m));
+        if (amask == 0ull) continue;
         for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
             if (qn > kQueueCap - 64 * kCullChunk) {
-                point_flush<MODE, HAS_OFFS, KSET>(dau, cul, offs, t, base, S, qn, lane);
+                point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, t, base, S, qn, lane);
                 qn = 0;
             }
             unsigned long long cm[kCullChunk];
@@ -1426,19 +1446,23 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
                 const unsigned long long m = cm[kk];
                 if (m == 0ull) continue;
                 if (__builtin_amdgcn_inverse_ballot_w64(m))
-                    S.queue[qn + lanes_below(m)] = ((unsigned int)(k0 + kk) << 10) | (unsigned int)lane;
+                    S.queue[qn + lanes_below(m)] = ((unsigned int)(k0 + kk) << 10) | (unsigned int)j;
                 qn += __popcll(m);
             }
         }
     }
-    point_flush<MODE, HAS_OFFS, KSET>(dau, cul, offs, t, base, S, qn, lane);
-    if (act) {
-        const int64_t o = base + lane;
-        if (MODE == 0) {
-            out_s[o] = key_step(lds_load(&S.key[lane]));
-        } else {
-            const int w = lds_load(&S.hit[lane]);
-            out_w[o] = !in_m ? -2 : (w != 0x7fffffff ? w : -1);
+    point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, t, base, S, qn, lane);
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+        const int j = u * 64 + lane;
+        if (j < count) {
+            const int64_t o = base + j;
+            if (MODE == 0) {
+                out_s[o] = key_step(lds_load(&S.key[j]));
+            } else {
+                const int w = lds_load(&S.hit[j]);
+                out_w[o] = lds_load(&S.key[j]) == 0ull ? -2 : (w != 0x7fffffff ? w : -1);
+            }
         }
     }
 }

@@ -82,3 +82,35 @@ def test_empty_and_errors(gv):
     with pytest.raises(gv.GeoError):
         gv.geo_locate(g, 5, torch.zeros((3, 4), dtype=torch.float64, device="cuda"))
     g.close()
+
+
+@pytest.mark.parametrize("offsets", [False, True])
+def test_large_point_sets(gv, orc, offsets):
+    """2^20 + 37 points: culling on and off give identical bits, and 6000
+    sampled points match the oracle."""
+    import torch
+    vol = W.toy_detector_volume()
+    rng = np.random.default_rng(33)
+    n = (1 << 20) + 37
+    extra = _points(vol, 12000, 34)  # inside daughters and outside the mother too
+    p = np.ascontiguousarray(np.concatenate([W.tracks_in_mother(rng, vol, n - extra.shape[1])[:3],
+                                             extra], axis=1))
+    p = np.ascontiguousarray(p[:, rng.permutation(p.shape[1])])
+    offs = rng.uniform(-2, 2, (vol.nd, 3)) if offsets else None
+    g = gv.Geometry([vol])
+    tp = torch.from_numpy(p).cuda()
+    to = None if offs is None else torch.from_numpy(offs).cuda()
+    s = gv.geo_navigate_safety(g, 0, tp, to).cpu().numpy()
+    w = gv.geo_locate(g, 0, tp, to).cpu().numpy()
+    g.culling = False
+    s2 = gv.geo_navigate_safety(g, 0, tp, to).cpu().numpy()
+    w2 = gv.geo_locate(g, 0, tp, to).cpu().numpy()
+    g.close()
+    assert np.array_equal(s.view(np.int64), s2.view(np.int64)) and np.array_equal(w, w2)
+    idx = np.sort(rng.choice(p.shape[1], 6000, replace=False))
+    ps = np.ascontiguousarray(p[:, idx])
+    ref = orc.navigate_safety(vol, ps, offs, "ld")
+    ill = rel_diff(orc.navigate_safety(vol, ps, offs, "d"), ref) > 1e-13
+    print(check_values(s[idx], ref, ill, "large safety"))
+    near = ref < 1e-9
+    assert np.array_equal(w[idx][~near], orc.locate(vol, ps, offs, "ld")[~near])
