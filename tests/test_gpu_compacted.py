@@ -153,3 +153,37 @@ def test_tracks_starting_on_a_daughter_surface(gv, orc):
     assert np.array_equal(hit, k.astype(np.int32))
     ref, rhit, _ = orc.navigate(vol, tr)
     assert np.all(ref == 0) and np.array_equal(rhit, k)
+
+
+def test_tangent_to_culling_spheres_in_a_large_mother(gv, orc):
+    """A mother of half size 10^4 with 40 small, rotated daughters near its
+    corners (|T| up to 1.6e4, bounding radii 1-4): tracks from random origins
+    along lines tangent to a daughter's bounding sphere, or passing just
+    inside or outside it, where the expanded culling test's rounding
+    matters most. Culling on (compacted) and off (sequential) must agree bit
+    for bit, and with the oracle."""
+    rng = np.random.default_rng(1704)
+    nd = 40
+    sign = rng.choice([-1.0, 1.0], (nd, 3))
+    centres = sign * rng.uniform(7000, 9500, (nd, 3))
+    halves = rng.uniform(0.5, 2.0, (nd, 3))
+    vol = _volume((1.0e4, 1.0e4, 1.0e4), centres, halves)
+    ang = rng.uniform(0, 2 * np.pi, (nd, 3))
+    vol.rots = np.stack([W.euler_zxz(*a).reshape(9) for a in ang])
+    n = 4000
+    k = rng.integers(0, nd, n)
+    o = rng.uniform(-9000, 9000, (3, n))
+    T = centres[k].T
+    r = np.linalg.norm(halves[k], axis=1)
+    a = T - o
+    a /= np.linalg.norm(a, axis=0)
+    perp = np.cross(a.T, rng.normal(size=(n, 3))).T
+    perp /= np.linalg.norm(perp, axis=0)
+    scale = rng.choice([1.0, 1.0 - 1e-7, 1.0 + 1e-7, 0.5], n)
+    target = T + perp * (r * scale)
+    d = target - o
+    d /= np.linalg.norm(d, axis=0)
+    tr = np.ascontiguousarray(np.concatenate([o, d]))
+    step, hit = _all_paths(gv, [vol], tr)
+    print(check_nav(orc, vol, tr, step, hit, what="tangent lines, large mother"))
+    assert (hit >= 0).any()
