@@ -434,7 +434,7 @@ def main():
     ev_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = 1e3 * wall / args.steps
 
-    # the same batched launch without wavefront culling (every daughter of
+    # the same batched launch without culling (every daughter of
     # every track evaluated), for the record
     g.culling = False
     _, _, counts_nocull = gv.geo_navigate_batched_census(g, bv, bo, bn, t)

@@ -201,7 +201,9 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
  *   counts[2 * kind + hole]  lane-evaluations of DistFromOutside for daughters
  *                            of that kind (kind 0..4 as above, 5 an uncut
  *                            polycone, 6 a cut one; hole = 1 for a shape with
- *                            an inner surface): every active lane of a
+ *                            an inner surface): with culling, one per
+ *                            (track, daughter) pair that passed the culling
+ *                            test; without, every active lane of a
  *                            wavefront that evaluates the daughter,
  *   counts[14]               lane culling tests (0 with culling off),
  *   counts[15]               tracks navigated (mother DistFromInside).

@@ -4,8 +4,10 @@
 // all candidate surfaces of a shape are evaluated and the valid smallest one
 // is kept with selects, so a wavefront never diverges inside a shape. The
 // only branches are on the shape kind and the hole and convexity flags,
-// which are uniform across a wavefront (the navigator walks the daughters in
-// lockstep).
+// which are uniform across a wavefront where the daughters are walked in
+// lockstep (shape queries, sequential navigator loops); in a batch of the
+// compacted navigators the lanes hold different daughters, and lanes of
+// each kind take that kind's code in turn.
 //
 // Each distance query is a minimum over per-surface candidates (faces,
 // z-planes, the outer and inner cylinder/cone nappes): for DistFromOutside
@@ -1007,11 +1009,12 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, const PconRec 
 }
 
 // ----------------------------------------------------------- navigator
-// Per-track navigator of Fig. 1b: the mother's DistFromInside, then each
-// daughter's DistFromOutside in its own frame, keeping the smallest (ties to
-// the mother, then the lowest index). Daughters are walked in lockstep by
-// the whole wavefront, so the daughter record and its kind are uniform
-// (scalar loads, scalar branch).
+// Per-track navigator of Fig. 1b, sequential form (the adjoint's forward
+// recomputation, and the forward navigators with culling off): the mother's
+// DistFromInside, then each daughter's DistFromOutside in its own frame,
+// keeping the smallest (ties to the mother, then the lowest index).
+// Daughters are walked in lockstep by the whole wavefront, so the daughter
+// record and its kind are uniform (scalar loads, scalar branch).
 //
 // With CULL, a daughter is skipped for the whole wavefront when no lane's
 // segment from p to p + best d (best = that lane's current step) comes within
@@ -1468,7 +1471,8 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
 }
 
 // ------------------------------------------ navigator safety and locate
-// The navigator's other two per-track tasks (section 3). With CULL, a
+// The navigator's other two per-track tasks (section 3), sequential form
+// (culling off; the culled kernels take the compacted form above). With CULL, a
 // daughter is skipped by the whole wavefront when its bounding sphere (the
 // culling radius r, enlarged as above) is too far to matter for every lane:
 // for the safety when |w| >= best + r (its Safety is at least |w| - r, so it

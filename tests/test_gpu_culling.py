@@ -1,5 +1,6 @@
-"""Wavefront culling changes the work done, never the results: the
-navigators give bit-identical outputs with culling on and off."""
+"""Culling changes the work done, never the results: the navigators give
+bit-identical outputs with culling on (compacted evaluation of the pairs
+that pass) and off (every daughter evaluated in lockstep)."""
 import numpy as np
 import pytest
 
