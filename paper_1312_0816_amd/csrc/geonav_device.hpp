@@ -1016,16 +1016,6 @@ __device__ __forceinline__ void surface_normal(const ShapeRec &s, const PconRec 
 // Daughters are walked in lockstep by the whole wavefront, so the daughter
 // record and its kind are uniform (scalar loads, scalar branch).
 //
-// With CULL, a daughter is skipped for the whole wavefront when no lane's
-// segment from p to p + best d (best = that lane's current step) comes within
-// the daughter's bounding-sphere radius of the sphere's centre c (radius
-// enlarged by 1e-6 relative + 1e-6, which covers the rounding of this test).
-// Such a daughter cannot be entered before `best`, so it could neither lower
-// the step nor win a tie (ties keep the earlier candidate): the results are
-// bit-identical to evaluating it. With w = p - c the squared distance from c
-// to the point at parameter tau is |w|^2 + tau (2 w.d + tau |d|^2), smallest
-// over [0, best] at tau = clamp(-w.d / |d|^2, 0, best).
-//
 // With COUNT, the work done is tallied into census[kCensusSlots] (one atomic
 // per wavefront and event, adding the number of active lanes): slots
 // 2 * kind + hole count daughter evaluations, slot kCensusCull culling
@@ -1036,7 +1026,7 @@ __device__ __forceinline__ void census_add(unsigned long long *census, int slot)
         atomicAdd(&census[slot], (unsigned long long)__popcll(act));
 }
 
-template <bool HAS_OFFS, bool TRACK_SURF, bool CULL, bool COUNT = false, int KSET = kSetAll>
+template <bool HAS_OFFS, bool TRACK_SURF, bool COUNT = false, int KSET = kSetAll>
 __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, double x, double y,
@@ -1048,10 +1038,6 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
     best = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
     hit = -1;
     bsid = sid;
-    // per-track constants of the culling test: |d|^2, 1 / (2 |d|^2), 2 d
-    const double dd = CULL ? fma(uz, uz, fma(uy, uy, ux * ux)) : 0.0;
-    const double hdd = (CULL && dd > 0.0) ? fdiv(0.5, dd) : 0.0;
-    const double ux2 = 2.0 * ux, uy2 = 2.0 * uy, uz2 = 2.0 * uz;
     const int nd = v.nd;
     for (int k = 0; k < nd; ++k) {
         const CullRec &Q = cul[k];
@@ -1060,14 +1046,6 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
             wx -= offs[3 * k + 0];
             wy -= offs[3 * k + 1];
             wz -= offs[3 * k + 2];
-        }
-        if (CULL) {
-            if (COUNT) census_add(census, kCensusCull);
-            const double b2 = fma(wz, uz2, fma(wy, uy2, wx * ux2));    // 2 w.d
-            const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
-            const double tau = fmax(fmin(-b2 * hdd, best), 0.0);
-            const double f = fma(tau, fma(tau, dd, b2), ww);            // |w + tau d|^2
-            if (__ballot(f <= Q.r2) == 0) continue;
         }
         const DaughterRec &D = dau[k];
         if (COUNT) census_add(census, 2 * D.shape.kind + D.shape.hole);
@@ -1089,14 +1067,18 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 }
 
 // ------------------------------------------------ compacted navigator
-// The culling test above leaves a wavefront evaluating a daughter for all 64
-// lanes when any one lane needs it; with random tracks about one lane in 64
-// does. The compacted form separates the two: the wavefront first runs the
-// culling tests of its tracks against every daughter (lockstep, as above)
-// and appends each (track, daughter) pair that passes to a queue in LDS;
-// then each lane takes one queued pair and evaluates that daughter's
-// DistFromOutside for that track, so a batch of 64 pairs costs one pass
-// (the lanes of different kinds take their kinds' code in turn).
+// Culling: a (track, daughter) pair needs evaluating only when the track's
+// segment from p to p + reach d passes within the daughter's culling radius
+// (its bounding radius enlarged by 1e-6 relative + 1e-6) of the sphere's
+// centre T. Skipping a daughter for a whole wavefront unless some lane needs
+// it would leave all 64 lanes evaluating it for the one lane or two that do
+// (with random tracks about one lane in 64). The compacted form separates the
+// two: the wavefront first runs the culling tests of its tracks against
+// every daughter (lockstep: the culling record is uniform) and appends each
+// (track, daughter) pair that passes to a queue in LDS; then each lane takes
+// one queued pair and evaluates that daughter's DistFromOutside for that
+// track, so a batch of 64 pairs costs one pass (the lanes of different kinds
+// take their kinds' code in turn).
 //
 // The step of a track is the minimum over its candidates of (s, index),
 // compared lexicographically with the mother as index -1: the result of
@@ -1155,12 +1137,13 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// DistFromOutside of daughter k (records D, Q) for a mother-frame track.
+// DistFromOutside of daughter k (records D, Q) for a mother-frame track;
+// sid receives the surface that set it.
 template <bool HAS_OFFS, int KSET>
 __device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const CullRec &Q,
                                                     const double *__restrict__ offs, int k, double x,
                                                     double y, double z, double ux, double uy,
-                                                    double uz) {
+                                                    double uz, int &sid) {
     double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
     if (HAS_OFFS) {
         wx -= offs[3 * k + 0];
@@ -1174,7 +1157,6 @@ __device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const 
     const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
     const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
     const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
-    int sid;
     return any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
 }
 
@@ -1212,24 +1194,23 @@ __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
         }
         if (on) {
             const int64_t i = base + j;
+            int sid;
             const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, t.x[i], t.y[i],
-                                                               t.z[i], t.ux[i], t.uy[i], t.uz[i]);
+                                                               t.z[i], t.ux[i], t.uy[i], t.uz[i], sid);
             merge_step(S, j, s, k);
         }
     }
 }
 
 // Navigates the tracks base + u * 64 + lane (u < U, index below `count`
-// past base) of one volume, writing step, hit and (when HITPT) the hit
-// point.
-template <int U, bool HAS_OFFS, bool HITPT, bool COUNT, int KSET>
-__device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
-                                            const CullRec *__restrict__ cul,
-                                            const double *__restrict__ offs, const TracksDev &t,
-                                            int64_t base, int count, NavScratch<U> &S, int lane,
-                                            double *__restrict__ step, int32_t *__restrict__ hit,
-                                            double *__restrict__ hitpt,
-                                            unsigned long long *census = nullptr) {
+// past base) of one volume, leaving each track's step (as a key) and hit
+// index in S.
+template <int U, bool HAS_OFFS, bool COUNT, int KSET>
+__device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                                 const CullRec *__restrict__ cul,
+                                                 const double *__restrict__ offs, const TracksDev &t,
+                                                 int64_t base, int count, NavScratch<U> &S, int lane,
+                                                 unsigned long long *census = nullptr) {
     int qn = 0;  // queue length (uniform)
     const int nd = v.nd;
     const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
@@ -1317,6 +1298,18 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
         }
     }
     nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
+}
+
+// The same, writing step, hit and (when HITPT) the hit point.
+template <int U, bool HAS_OFFS, bool HITPT, bool COUNT, int KSET>
+__device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                            const CullRec *__restrict__ cul,
+                                            const double *__restrict__ offs, const TracksDev &t,
+                                            int64_t base, int count, NavScratch<U> &S, int lane,
+                                            double *__restrict__ step, int32_t *__restrict__ hit,
+                                            double *__restrict__ hitpt,
+                                            unsigned long long *census = nullptr) {
+    nav_compact_core<U, HAS_OFFS, COUNT, KSET>(v, dau, cul, offs, t, base, count, S, lane, census);
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;
@@ -1472,14 +1465,9 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
 
 // ------------------------------------------ navigator safety and locate
 // The navigator's other two per-track tasks (section 3), sequential form
-// (culling off; the culled kernels take the compacted form above). With CULL, a
-// daughter is skipped by the whole wavefront when its bounding sphere (the
-// culling radius r, enlarged as above) is too far to matter for every lane:
-// for the safety when |w| >= best + r (its Safety is at least |w| - r, so it
-// cannot lower the minimum), for localisation when |w| > r (the point is
-// outside the sphere, hence outside the daughter). Results are identical to
-// evaluating every daughter.
-template <bool HAS_OFFS, bool CULL, int KSET = kSetAll>
+// with every daughter evaluated (culling off; the culled kernels take the
+// compacted form above).
+template <bool HAS_OFFS, int KSET = kSetAll>
 __device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                              const CullRec *__restrict__ cul,
                                              const double *__restrict__ offs, double x, double y,
@@ -1494,11 +1482,6 @@ __device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterR
             wy -= offs[3 * k + 1];
             wz -= offs[3 * k + 2];
         }
-        if (CULL) {
-            const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
-            const double reach = best + Q.r;
-            if (__ballot(ww < reach * reach) == 0) continue;
-        }
         const DaughterRec &D = dau[k];
         const double *R = D.rot;
         const double lx = fma(R[6], wz, fma(R[3], wy, R[0] * wx));
@@ -1511,7 +1494,7 @@ __device__ __forceinline__ double nav_safety(const VolumeRec &v, const DaughterR
 
 // Daughter holding the point (lowest index), -1 for the mother's own part,
 // -2 outside the mother.
-template <bool HAS_OFFS, bool CULL, int KSET = kSetAll>
+template <bool HAS_OFFS, int KSET = kSetAll>
 __device__ __forceinline__ int nav_locate(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, double x, double y,
@@ -1526,10 +1509,6 @@ __device__ __forceinline__ int nav_locate(const VolumeRec &v, const DaughterRec 
             wx -= offs[3 * k + 0];
             wy -= offs[3 * k + 1];
             wz -= offs[3 * k + 2];
-        }
-        if (CULL) {
-            const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
-            if (__ballot(where == -1 && ww <= Q.r2) == 0) continue;
         }
         const DaughterRec &D = dau[k];
         const double *R = D.rot;

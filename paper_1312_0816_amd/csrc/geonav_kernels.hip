@@ -116,8 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
     const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
     double best;
     int h, sid;
-    nav_track<HAS_OFFS, false, CULL, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h,
-                                                  sid);
+    nav_track<HAS_OFFS, false, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best, h, sid);
     step[i] = best;
     hit[i] = h;
     if (HITPT) {
@@ -181,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restri
     }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
-    out[i] = nav_safety<HAS_OFFS, CULL, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+    out[i] = nav_safety<HAS_OFFS, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
 }
 
 template <bool HAS_OFFS, bool CULL, int KSET, int U = 1>
@@ -202,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restri
     }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= t.n) return;
-    out[i] = nav_locate<HAS_OFFS, CULL, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
+    out[i] = nav_locate<HAS_OFFS, KSET>(*vol, dau, cul, offs, t.x[i], t.y[i], t.z[i]);
 }
 
 template <bool CULL, int KSET, int U = 1>
@@ -272,7 +271,7 @@ __device__ __forceinline__ void run_tile(const Tile &tl, const VolumeRec *__rest
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int h, sid;
-            nav_track<false, false, CULL, COUNT, KSET>(v, dau, cul, nullptr, x, y, z, ux, uy, uz,
+            nav_track<false, false, COUNT, KSET>(v, dau, cul, nullptr, x, y, z, ux, uy, uz,
                                                        best, h, sid, census);
             step[i] = best;
             hit[i] = h;
@@ -435,9 +434,11 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
     const double *__restrict__ gstep,
     const double *__restrict__ ghit, double *__restrict__ g_o, double *__restrict__ g_d,
     double *__restrict__ partial) {
-    __shared__ int s_hit[kBlock];
     __shared__ double s_g[3][kBlock];
+    __shared__ NavScratch<1> scr[CULL ? kBlock / 64 : 1];
+    extern __shared__ int s_bins[];  // 4 * nd + nd + 1 ints (see below)
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int nd = vol->nd;
     const int nj = 3 * nd;
     double *prow = partial ? partial + (size_t)blockIdx.x * nj : nullptr;
@@ -448,13 +449,32 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
         const int64_t i = base + tid;
         int h = -2;
         double gdx = 0.0, gdy = 0.0, gdz = 0.0;
+        if constexpr (CULL) {
+            // the forward step and hit by the compacted navigator (per
+            // wavefront of 64 tracks)
+            const int64_t wbase = base + wave * 64;
+            if (wbase < n)
+                nav_compact_core<1, HAS_OFFS, false, KSET>(*vol, dau, cul, offs, t, wbase,
+                                                           n - wbase < 64 ? (int)(n - wbase) : 64,
+                                                           scr[wave], lane);
+        }
         if (i < n) {
             const double x = t.x[i], y = t.y[i], z = t.z[i];
             const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
             double best;
             int sid;
-            nav_track<HAS_OFFS, true, CULL, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best,
-                                                         h, sid);
+            if constexpr (CULL) {
+                // the surface that set the step: the winner evaluated again
+                // (the same function on the same inputs, hence the same
+                // candidate)
+                best = key_step(lds_load(&scr[wave].key[lane]));
+                h = lds_load(&scr[wave].hit[lane]);
+                if (h < 0) (void)any_dist_in<KSET>(vol->mother, vol->pcon, x, y, z, ux, uy, uz, sid);
+                else (void)daughter_dist_out<HAS_OFFS, KSET>(dau[h], cul[h], offs, h, x, y, z, ux, uy, uz, sid);
+            } else {
+                nav_track<HAS_OFFS, true, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best,
+                                                       h, sid);
+            }
             const bool finite = best < kBig;
             const double s = finite ? best : 0.0;
             const double hx = fma(s, ux, x), hy = fma(s, uy, y), hz = fma(s, uz, z);
@@ -508,15 +528,62 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             gdz = -c * dsz;
         }
         if (prow) {
-            s_hit[tid] = h;
-            s_g[0][tid] = gdx;
-            s_g[1][tid] = gdy;
-            s_g[2][tid] = gdz;
+            // Offset gradient of the workgroup's tracks per daughter: a
+            // stable counting sort of the contributions by hit daughter,
+            // then each (daughter, component) sums its run in track order,
+            // the order of a plain scan over the workgroup's tracks.
+            int *cnt = s_bins;           // [4][nd]: per-wavefront counts, then offsets
+            int *run = s_bins + 4 * nd;  // [nd + 1]: start of each daughter's run
+            for (int j = tid; j < 4 * nd; j += kBlock) cnt[j] = 0;
+            __syncthreads();
+            // rank among the earlier lanes of the wavefront with the same daughter
+            int rank = 0;
+            unsigned long long rem = __builtin_amdgcn_ballot_w64(h >= 0);
+            while (rem != 0ull) {
+                const int k = __builtin_amdgcn_readlane(h, __ffsll((long long)rem) - 1);
+                const unsigned long long m = __builtin_amdgcn_ballot_w64(h == k);
+                if (h == k) rank = lanes_below(m);
+                if (lane == 0) cnt[wave * nd + k] = __popcll(m);
+                rem &= ~m;
+            }
+            __syncthreads();
+            // runs: exclusive scan of the daughters' totals (wavefront 0, 64
+            // daughters a pass), then each wavefront's offset within a run
+            if (wave == 0) {
+                int carry = 0;
+                for (int k0 = 0; k0 < nd; k0 += 64) {
+                    const int k = k0 + lane;
+                    const int tot = k < nd ? cnt[k] + cnt[nd + k] + cnt[2 * nd + k] + cnt[3 * nd + k] : 0;
+                    int incl = tot;
+                    for (int dlt = 1; dlt < 64; dlt <<= 1) {
+                        const int v = __shfl_up(incl, dlt);
+                        if (lane >= dlt) incl += v;
+                    }
+                    if (k < nd) {
+                        int off = carry + incl - tot;
+                        run[k] = off;
+                        for (int w = 0; w < kBlock / 64; ++w) {
+                            const int c = cnt[w * nd + k];
+                            cnt[w * nd + k] = off;
+                            off += c;
+                        }
+                    }
+                    carry += __shfl(incl, 63);
+                }
+                if (lane == 0) run[nd] = carry;
+            }
+            __syncthreads();
+            if (h >= 0) {
+                const int p = cnt[wave * nd + h] + rank;
+                s_g[0][p] = gdx;
+                s_g[1][p] = gdy;
+                s_g[2][p] = gdz;
+            }
             __syncthreads();
             for (int j = tid; j < nj; j += kBlock) {
                 const int k = j / 3, comp = j - 3 * k;
                 double acc = 0.0;
-                for (int l = 0; l < kBlock; ++l) acc += (s_hit[l] == k) ? s_g[comp][l] : 0.0;
+                for (int q = run[k]; q < run[k + 1]; ++q) acc += s_g[comp][q];
                 prow[j] += acc;
             }
             __syncthreads();
@@ -542,15 +609,16 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__rest
 }
 
 template <bool CULL, int KSET>
-static void launch_backward_variant(int nblocks, const VolumeRec *vol, const DaughterRec *dau,
+static void launch_backward_variant(int nblocks, int nd, const VolumeRec *vol, const DaughterRec *dau,
                                     const CullRec *cul, const TracksDev &t, const double *offs, const double *gstep,
                                     const double *ghit, double *g_o, double *g_d, double *part,
                                     hipStream_t st) {
+    const size_t bins = sizeof(int) * (size_t)(5 * nd + 1);  // the offset-gradient sort
     if (offs)
-        hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
+        hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET>), dim3(nblocks), dim3(kBlock), bins, st, vol, dau, cul, t,
                            offs, gstep, ghit, g_o, g_d, part);
     else
-        hipLaunchKernelGGL((k_nav_backward<false, CULL, KSET>), dim3(nblocks), dim3(kBlock), 0, st, vol, dau, cul, t,
+        hipLaunchKernelGGL((k_nav_backward<false, CULL, KSET>), dim3(nblocks), dim3(kBlock), bins, st, vol, dau, cul, t,
                            offs, gstep, ghit, g_o, g_d, part);
 }
 
@@ -563,10 +631,10 @@ hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const C
     double *part = (g_off && nd > 0) ? partial : nullptr;
     if (t.n > 0 || part) {
         if (cull)
-            GN_KSET(kset, (launch_backward_variant<true, KS>(nblocks, vol, dau, cul, t, offs, gstep, ghit,
+            GN_KSET(kset, (launch_backward_variant<true, KS>(nblocks, nd, vol, dau, cul, t, offs, gstep, ghit,
                                                              g_o, g_d, part, st)));
         else
-            GN_KSET(kset, (launch_backward_variant<false, KS>(nblocks, vol, dau, cul, t, offs, gstep, ghit,
+            GN_KSET(kset, (launch_backward_variant<false, KS>(nblocks, nd, vol, dau, cul, t, offs, gstep, ghit,
                                                               g_o, g_d, part, st)));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
