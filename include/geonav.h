@@ -232,11 +232,9 @@ int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t wave
 
 /* Culling in the navigators (basket, batched, backward): a daughter is not
  * evaluated for a track whose line cannot enter the daughter's bounding
- * sphere (radius enlarged by 1e-6 relative + 1e-6) before the mother's exit
- * (the backward kernel: before the track's current best step, skipping the
- * daughter for the whole wavefront when no lane needs it). The forward
- * navigators queue the (track, daughter) pairs that pass in LDS and evaluate
- * them one pair per lane. A culled daughter could neither lower a step nor
+ * sphere (radius enlarged by 1e-6 relative + 1e-6) before the mother's exit.
+ * The (track, daughter) pairs that pass are queued in LDS and evaluated one
+ * pair per lane. A culled daughter could neither lower a step nor
  * win a tie, so results are bit-identical with culling on or off; only the
  * work done changes. Applies likewise to geo_navigate_safety (a daughter
  * whose sphere is farther than the mother's safety) and geo_locate (a point
