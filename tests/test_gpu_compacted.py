@@ -187,3 +187,42 @@ def test_tangent_to_culling_spheres_in_a_large_mother(gv, orc):
     step, hit = _all_paths(gv, [vol], tr)
     print(check_nav(orc, vol, tr, step, hit, what="tangent lines, large mother"))
     assert (hit >= 0).any()
+
+
+def test_the_largest_volume(gv, orc):
+    """A volume with the most daughters the library accepts (1024 boxes on a
+    16 x 16 x 4 grid): basket and batched navigation with culling on and
+    off, safety and localization on and off, the adjoint on and off (its
+    offset-gradient sort holds 1024 bins), and the oracle on a sample."""
+    import torch
+    n_d = gv.GEO_MAX_DAUGHTERS
+    ii = np.arange(n_d)
+    centres = np.stack([-150.0 + 20.0 * (ii % 16), -150.0 + 20.0 * ((ii // 16) % 16),
+                        -60.0 + 40.0 * (ii // 256)], axis=1)
+    rng = np.random.default_rng(1705)
+    halves = rng.uniform(2.0, 8.0, (n_d, 3))
+    vol = _volume((200.0, 200.0, 200.0), centres, halves)
+    tr = W.tracks_in_mother(rng, vol, 20000)
+    step, hit = _all_paths(gv, [vol], tr)
+    idx = np.sort(rng.choice(tr.shape[1], 3000, replace=False))
+    print(check_nav(orc, vol, np.ascontiguousarray(tr[:, idx]), step[idx], hit[idx], what="1024 daughters"))
+    assert len(np.unique(hit)) > 500
+    g = gv.Geometry([vol])
+    p = torch.from_numpy(np.ascontiguousarray(tr[:3])).cuda()
+    d = torch.from_numpy(np.ascontiguousarray(tr[3:])).cuda()
+    gh = torch.from_numpy(rng.normal(size=(3, tr.shape[1]))).cuda()
+    offs = torch.zeros((n_d, 3), dtype=torch.float64, device="cuda")
+    out = {}
+    for cull in (True, False):
+        g.culling = cull
+        s = gv.geo_navigate_safety(g, 0, p).cpu().numpy()
+        w = gv.geo_locate(g, 0, p).cpu().numpy()
+        go, gd, goff = gv.geo_navigate_backward(g, 0, p, d, offs, None, gh)
+        out[cull] = [s.view(np.int64), w, _bits(go), _bits(gd), _bits(goff)]
+    g.close()
+    for a, b in zip(out[True], out[False]):
+        assert np.array_equal(a, b)
+    ps = np.ascontiguousarray(tr[:3, idx])
+    ref = orc.navigate_safety(vol, ps, None, "d")
+    assert np.all(np.abs(out[True][0].view(np.float64)[idx] - ref) <= 1e-12 * np.maximum(ref, 1.0))
+    assert np.array_equal(out[True][1][idx], orc.locate(vol, ps, None, "d"))
