@@ -242,6 +242,18 @@ int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t wave
 int geo_set_culling(geo_geometry *g, int32_t enable);
 int geo_get_culling(const geo_geometry *g, int32_t *enabled);
 
+/* Timing of the batched navigator kernel alone, for measurement. With
+ * enable != 0, the graph of geo_navigate_batched records two events of its
+ * own, just before and just after the navigator kernel (the tile expansion
+ * before it is outside the interval); geo_batched_kernel_ms then waits for
+ * the most recent such call to finish and returns that kernel's duration in
+ * milliseconds. Enabling creates the two events (GEO_ERR_HIP if that
+ * fails); the graph is rebuilt on the next call. Results do not change.
+ * geo_batched_kernel_ms fails with GEO_ERR_INVALID_ARG when timing is off or
+ * no batched call has run since it was enabled. */
+int geo_set_kernel_timing(geo_geometry *g, int32_t enable);
+int geo_batched_kernel_ms(geo_geometry *g, float *ms);
+
 /* Message for a status code; for the most recent failure on the calling
  * thread it includes that failure's detail. Never NULL. */
 const char *geo_strerror(int status);

@@ -336,7 +336,12 @@ struct geo_geometry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node_build = nullptr, node_nav = nullptr;
-    int graph_U = 0, graph_grid = 0, graph_cull = -1, graph_mode = -1;
+    int graph_U = 0, graph_grid = 0, graph_cull = -1, graph_mode = -1, graph_ktime = -1;
+    // optional timing of the navigator kernel alone: event-record nodes
+    // before and after it in the batched graph
+    bool ktime = false;
+    bool ktime_recorded = false;
+    hipEvent_t kt_before = nullptr, kt_after = nullptr;
     std::vector<BasketRec> sorted;   // reused host scratch
     std::vector<int> sort_count;
 };
@@ -350,7 +355,7 @@ void destroy_graph(geo_geometry *g) {
     g->graph = nullptr;
     g->node_build = g->node_nav = nullptr;
     g->graph_U = g->graph_grid = 0;
-    g->graph_cull = g->graph_mode = -1;
+    g->graph_cull = g->graph_mode = g->graph_ktime = -1;
 }
 
 int check_device(const geo_geometry *g) {
@@ -518,6 +523,8 @@ int geo_geometry_destroy(geo_geometry *g) {
     if (dev != g->device) (void)hipSetDevice(g->device);
     (void)hipDeviceSynchronize();
     destroy_graph(g);
+    if (g->kt_before) (void)hipEventDestroy(g->kt_before);
+    if (g->kt_after) (void)hipEventDestroy(g->kt_after);
     for (auto &gr : g->group)
         if (gr.done) (void)hipEventDestroy(gr.done);
     for (auto &st : g->stage)
@@ -766,7 +773,8 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     kn.blockDim = dim3(kBlock);
     kn.kernelParams = pargs;
     const int mode = persistent ? 1 : 0;
-    bool rebuild = !g->exec || g->graph_U != U || g->graph_cull != (int)g->cull || g->graph_mode != mode;
+    bool rebuild = !g->exec || g->graph_U != U || g->graph_cull != (int)g->cull || g->graph_mode != mode ||
+                   g->graph_ktime != (int)g->ktime;
     if (!rebuild) {
         // same kernels: update arguments (and the grid, which the hardware-
         // scheduled form sizes by tile count); rebuild if the update is refused
@@ -780,14 +788,23 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
         destroy_graph(g);
         GN_HIP(hipGraphCreate(&g->graph, 0));
         GN_HIP(hipGraphAddKernelNode(&g->node_build, g->graph, nullptr, 0, &kb));
-        GN_HIP(hipGraphAddKernelNode(&g->node_nav, g->graph, &g->node_build, 1, &kn));
+        if (g->ktime) {
+            hipGraphNode_t before = nullptr, after = nullptr;
+            GN_HIP(hipGraphAddEventRecordNode(&before, g->graph, &g->node_build, 1, g->kt_before));
+            GN_HIP(hipGraphAddKernelNode(&g->node_nav, g->graph, &before, 1, &kn));
+            GN_HIP(hipGraphAddEventRecordNode(&after, g->graph, &g->node_nav, 1, g->kt_after));
+        } else {
+            GN_HIP(hipGraphAddKernelNode(&g->node_nav, g->graph, &g->node_build, 1, &kn));
+        }
         GN_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
         g->graph_U = U;
         g->graph_cull = (int)g->cull;
         g->graph_mode = mode;
+        g->graph_ktime = (int)g->ktime;
     }
     g->graph_grid = grid;
     GN_HIP(hipGraphLaunch(g->exec, stream));
+    g->ktime_recorded = g->ktime;
     return advance_stage(g, stream);
 }
 
@@ -875,6 +892,30 @@ int geo_set_culling(geo_geometry *g, int32_t enable) {
 int geo_get_culling(const geo_geometry *g, int32_t *enabled) {
     if (!g || !enabled) return fail(GEO_ERR_INVALID_ARG, "NULL argument");
     *enabled = g->cull ? 1 : 0;
+    return GEO_OK;
+}
+
+int geo_set_kernel_timing(geo_geometry *g, int32_t enable) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    int rc = check_device(g);
+    if (rc) return rc;
+    if (enable && !g->kt_before) {
+        GN_HIP(hipEventCreate(&g->kt_before));
+        GN_HIP(hipEventCreate(&g->kt_after));
+    }
+    g->ktime = enable != 0;
+    g->ktime_recorded = false;
+    return GEO_OK;
+}
+
+int geo_batched_kernel_ms(geo_geometry *g, float *ms) {
+    if (!g || !ms) return fail(GEO_ERR_INVALID_ARG, "NULL argument");
+    if (!g->ktime || !g->ktime_recorded)
+        return fail(GEO_ERR_INVALID_ARG, "no batched call with kernel timing enabled since it was set");
+    int rc = check_device(g);
+    if (rc) return rc;
+    GN_HIP(hipEventSynchronize(g->kt_after));
+    GN_HIP(hipEventElapsedTime(ms, g->kt_before, g->kt_after));
     return GEO_OK;
 }
 

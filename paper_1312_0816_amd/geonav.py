@@ -67,7 +67,7 @@ EXPORTS = ("geo_geometry_create", "geo_geometry_destroy", "geo_shape_query",
            "geo_navigate_basket", "geo_navigate_batched", "geo_navigate_backward",
            "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_set_culling",
            "geo_get_culling", "geo_navigate_batched_census", "geo_navigate_safety",
-           "geo_locate", "geo_strerror")
+           "geo_locate", "geo_set_kernel_timing", "geo_batched_kernel_ms", "geo_strerror")
 
 _lib = None
 
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.geo_navigate_batched_census.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P, P,
                                                 C.POINTER(C.c_uint64), P]
     lib.geo_get_culling.argtypes = [P, C.POINTER(I32)]
+    lib.geo_set_kernel_timing.argtypes = [P, I32]
+    lib.geo_batched_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
     lib.geo_strerror.argtypes = [C.c_int]
     lib.geo_strerror.restype = C.c_char_p
     for name in EXPORTS:
@@ -251,6 +253,17 @@ class Geometry:
     @culling.setter
     def culling(self, enable: bool):
         _check(self._lib.geo_set_culling(self._h, 1 if enable else 0))
+
+    def set_kernel_timing(self, enable: bool):
+        """Record events around the batched navigator kernel (measurement)."""
+        _check(self._lib.geo_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def batched_kernel_ms(self) -> float:
+        """Duration of the navigator kernel of the latest batched call (waits
+        for it); needs set_kernel_timing(True) first."""
+        v = C.c_float()
+        _check(self._lib.geo_batched_kernel_ms(self._h, C.byref(v)))
+        return float(v.value)
 
 
 def geo_geometry_create(volumes) -> Geometry:

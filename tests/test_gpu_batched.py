@@ -157,3 +157,34 @@ def test_autotune_and_cache(gv, small, tmp_path, monkeypatch):
     g.close()
     g2.close()
     assert os.path.exists(path)
+
+
+def test_kernel_timing_events(gv, small):
+    """The graph's timing events around the navigator kernel: a positive
+    duration below the whole call's, the same outputs with them, and a clear
+    error before any timed call."""
+    import time
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    args = (small.basket_volume, small.basket_offset, small.basket_n, t)
+    s0, h0 = gv.geo_navigate_batched(g, *args)
+    with pytest.raises(gv.GeoError):
+        g.batched_kernel_ms()
+    g.set_kernel_timing(True)
+    with pytest.raises(gv.GeoError):
+        g.batched_kernel_ms()
+    for _ in range(3):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        s1, h1 = gv.geo_navigate_batched(g, *args)
+        ms = g.batched_kernel_ms()
+        wall = 1e3 * (time.perf_counter() - w0)
+        assert 0.0 < ms < wall
+        assert torch.equal(s0.view(torch.int64), s1.view(torch.int64)) and torch.equal(h0, h1)
+    g.set_kernel_timing(False)
+    s2, h2 = gv.geo_navigate_batched(g, *args)
+    assert torch.equal(s0.view(torch.int64), s2.view(torch.int64)) and torch.equal(h0, h2)
+    with pytest.raises(gv.GeoError):
+        g.batched_kernel_ms()
+    g.close()
