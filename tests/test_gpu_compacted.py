@@ -226,3 +226,45 @@ def test_the_largest_volume(gv, orc):
     ref = orc.navigate_safety(vol, ps, None, "d")
     assert np.all(np.abs(out[True][0].view(np.float64)[idx] - ref) <= 1e-12 * np.maximum(ref, 1.0))
     assert np.array_equal(out[True][1][idx], orc.locate(vol, ps, None, "d"))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_mixed_detectors_bitwise(gv, seed):
+    """Mixed detectors (all six kinds) from several seeds, with random
+    offsets: every culled (compacted) path equals its sequential
+    counterpart bit for bit: basket with hit points, batched at a random
+    launch shape, safety, localization and the adjoint."""
+    import torch
+    rng = np.random.default_rng(1800 + seed)
+    vols = [W.mixed_detector_volume(1250 + 10 * seed + i) for i in range(3)]
+    sizes = [int(x) for x in rng.integers(1, 3000, 5)]
+    parts, bv, bo, off = [], [], [], 0
+    for b, m in enumerate(sizes):
+        parts.append(W.tracks_in_mother(rng, vols[b % 3], m))
+        bv.append(b % 3)
+        bo.append(off)
+        off += m
+    tr = np.ascontiguousarray(np.concatenate(parts, axis=1))
+    t = torch.from_numpy(tr).cuda()
+    g = gv.Geometry(vols)
+    u, w = [(1, 0), (2, 0), (4, 0), (8, 0), (2, 3), (4, 2)][seed]
+    g.set_launch_config(u, w)
+    v0 = vols[0]
+    t0 = t[:, :sizes[0]].contiguous()
+    offs = torch.from_numpy(rng.uniform(-1.5, 1.5, (v0.nd, 3))).cuda()
+    gh = torch.from_numpy(rng.normal(size=(3, sizes[0]))).cuda()
+    out = {}
+    for cull in (True, False):
+        g.culling = cull
+        r = []
+        r += [_bits(x) for x in gv.geo_navigate_basket(g, 0, t0, offsets=offs, hitpt=True)]
+        r += [_bits(x) for x in gv.geo_navigate_batched(g, bv, bo, sizes, t)]
+        r.append(_bits(gv.geo_navigate_safety(g, 0, t0[:3].contiguous(), offs)))
+        r.append(_bits(gv.geo_locate(g, 0, t0[:3].contiguous(), offs)))
+        o = t0[:3].contiguous()
+        d = t0[3:].contiguous()
+        r += [_bits(x) for x in gv.geo_navigate_backward(g, 0, o, d, offs, None, gh)]
+        out[cull] = r
+    g.close()
+    for a, b in zip(out[True], out[False]):
+        assert np.array_equal(a, b)
