@@ -447,7 +447,7 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             {
                 // threshold of the expanded culling test, widened by its rounding bound
                 const double tt = dr.tr[0] * dr.tr[0] + dr.tr[1] * dr.tr[1] + dr.tr[2] * dr.tr[2];
-                const double span = 3.0 * mother_r + std::sqrt(tt);
+                const double span = 3.0 * mother_r + 2.0 * std::sqrt(tt);
                 const double q = dr.cull_r2 - tt + 64.0 * DBL_EPSILON * span * span;
                 cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2, std::sqrt(dr.cull_r2), q});
             }

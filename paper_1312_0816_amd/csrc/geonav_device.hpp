@@ -93,9 +93,10 @@ static_assert(sizeof(DaughterRec) == 368, "DaughterRec layout");
 // culling radius (bounding radius enlarged by 1e-6 relative + 1e-6) and its
 // square, and the threshold q of the expanded test of the compacted
 // navigator: that test evaluates |p - T + tau d|^2 - |T|^2 as
-// |p|^2 - 2 p.T + tau (2 (p - T).d + tau |d|^2), whose rounding error is
-// below 16 eps (3 R + |T|)^2 for a segment inside the mother (R the
-// mother's bounding radius); q = r2 - |T|^2 + 64 eps (3 R + |T|)^2.
+// |p|^2 - 2 p.T + tau (2 (p - T).d + tau |d|^2), with tau at most the foot
+// of the perpendicular from T (|tau d| <= |p - T|), whose rounding error is
+// below 16 eps (2 R + 2 |T|)^2 for a track inside the mother (R the
+// mother's bounding radius); q = r2 - |T|^2 + 64 eps (3 R + 2 |T|)^2.
 struct alignas(16) CullRec {
     double tx, ty, tz, r2;
     double r;    // the enlarged radius itself
@@ -1068,9 +1069,14 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 
 // ------------------------------------------------ compacted navigator
 // Culling: a (track, daughter) pair needs evaluating only when the track's
-// segment from p to p + reach d passes within the daughter's culling radius
-// (its bounding radius enlarged by 1e-6 relative + 1e-6) of the sphere's
-// centre T. Skipping a daughter for a whole wavefront unless some lane needs
+// half-line from p passes within the daughter's culling radius (its
+// bounding radius enlarged by 1e-6 relative + 1e-6) of the sphere's centre
+// T; otherwise the daughter cannot be entered at any t >= 0, so it could
+// neither lower the step nor win a tie. (The mother's exit would bound the
+// half-line further, but the daughters lie inside the mother and no line
+// comes back near them after leaving a convex mother: on the batched
+// workload that bound removes no pair, and leaving it out saves a min per
+// test.) Skipping a daughter for a whole wavefront unless some lane needs
 // it would leave all 64 lanes evaluating it for the one lane or two that do
 // (with random tracks about one lane in 64). The compacted form separates the
 // two: the wavefront first runs the culling tests of its tracks against
@@ -1091,11 +1097,6 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // (reset first when the batch lowered the key). After every batch the slot
 // holds the lexicographic minimum of all candidates merged so far, whatever
 // the order of the batches.
-//
-// The culling tests use the mother's step as the track's reach (the sphere
-// must meet the segment from p to p + s_mother d); that is at least the
-// final step, so a culled daughter could not have lowered the step or won
-// a tie: the results equal those of evaluating every daughter.
 //
 // Queue entries pack the daughter index (bits 10..31), the track's round
 // within the tile (bits 6..9) and its lane (bits 0..5). All LDS traffic of
@@ -1225,10 +1226,8 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
         if (COUNT && lane == 0) atomicAdd(&census[kCensusTracks], (unsigned long long)__popcll(amask));
         int sid;
-        // (canonicalized once here rather than by every fmin below)
-        const double reach =
-            __builtin_canonicalize(any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid));
-        lds_store(&S.key[j], step_key(reach, true));
+        const double ms = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
+        lds_store(&S.key[j], step_key(ms, true));
         lds_store(&S.hit[j], -1);
         // per-track constants of the culling test: |d|^2, 1 / (2 |d|^2), and
         // for the expanded form (no offsets) |p|^2, 2 p.d, -2 p, -2 d
@@ -1279,7 +1278,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                     g = fma(ctz[kk], mpz, fma(cty[kk], mpy, fma(ctx[kk], mpx, pp)));
                 }
                 const double lim = clim[kk];
-                const double tau = fmax(fmin(-b2 * hdd, reach), 0.0);
+                const double tau = fmax(-b2 * hdd, 0.0);  // nearest point of the half-line
                 const double f = fma(tau, fma(tau, dd, b2), g);             // |w + tau d|^2 - shift
                 // every lane's f is defined; lanes past the tile's end are masked out
                 cm[kk] = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
