@@ -45,8 +45,10 @@ BYTES_PER_TRACK = 60             # 6 x 8 B in (x, y, z, ux, uy, uz) + 8 B step +
 # launch does comes from the library's census (geo_navigate_batched_census):
 # lane-evaluations per daughter kind, culling tests and tracks.
 FLOPS_MOTHER_BOX = 6             # box DistFromInside: 3 x (sub, div)
-FLOPS_TRACK_CULL = 9             # |d|^2 (5), 1 / (2 |d|^2) (1), 2 d (3), once per track
-FLOPS_CULL_TEST = 18             # w = p - T (3), 2 w.d (5), |w|^2 (5), tau (1), |w + tau d|^2 (4)
+FLOPS_TRACK_CULL = 23            # once per track: |d|^2 (5), 1 / (4 |d|^2) (1), |p|^2 (5),
+                                 # 2 p.d (6), -2 p (3), -2 d (3)
+FLOPS_CULL_TEST = 15             # 2 (p - T).d (3 fma), |p|^2 - 2 p.T (3 fma), the half-line's
+                                 # distance term (mul, fma)
 FLOPS_ROTATION = 30              # R^T w and R^T d (2 x 3 x (mul + 2 fma))
 FLOPS_DIST_OUT = [               # census slot 2 * kind + hole
     21, 21,                      # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)
@@ -76,7 +78,7 @@ def census_flops(counts, cull: bool, pcon_sections: float = 0.0) -> float:
     from paper_1312_0816_amd import geonav as gv
     f = counts[gv.CENSUS_TRACKS] * (FLOPS_MOTHER_BOX + (FLOPS_TRACK_CULL if cull else 0))
     f += counts[gv.CENSUS_CULL] * FLOPS_CULL_TEST
-    per_eval_extra = FLOPS_ROTATION + (0 if cull else 3)   # with culling, w = p - T belongs to the test
+    per_eval_extra = FLOPS_ROTATION + 3                    # w = p - T, then R^T w and R^T d
     for slot in range(len(FLOPS_DIST_OUT)):
         f += counts[slot] * (per_eval_extra + FLOPS_DIST_OUT[slot])
     for slot in range(10, 14):

@@ -92,11 +92,12 @@ static_assert(sizeof(DaughterRec) == 368, "DaughterRec layout");
 // loop): the centre of the bounding sphere in the mother frame (T), the
 // culling radius (bounding radius enlarged by 1e-6 relative + 1e-6) and its
 // square, and the threshold q of the expanded test of the compacted
-// navigator: that test evaluates |p - T + tau d|^2 - |T|^2 as
-// |p|^2 - 2 p.T + tau (2 (p - T).d + tau |d|^2), with tau at most the foot
-// of the perpendicular from T (|tau d| <= |p - T|), whose rounding error is
-// below 16 eps (2 R + 2 |T|)^2 for a track inside the mother (R the
-// mother's bounding radius); q = r2 - |T|^2 + 64 eps (3 R + 2 |T|)^2.
+// navigator: that test evaluates the squared distance from T to the
+// track's half-line, less |T|^2, as |p|^2 - 2 p.T - b^2 / (4 |d|^2) with
+// b = min(2 (p - T).d, 0); every term is at most (|p| + |T|)^2, so the
+// rounding error is below 16 eps (2 R + 2 |T|)^2 for a track inside the
+// mother (R the mother's bounding radius); q = r2 - |T|^2 +
+// 64 eps (3 R + 2 |T|)^2.
 struct alignas(16) CullRec {
     double tx, ty, tz, r2;
     double r;    // the enlarged radius itself
@@ -1229,10 +1230,10 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         const double ms = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
         lds_store(&S.key[j], step_key(ms, true));
         lds_store(&S.hit[j], -1);
-        // per-track constants of the culling test: |d|^2, 1 / (2 |d|^2), and
-        // for the expanded form (no offsets) |p|^2, 2 p.d, -2 p, -2 d
+        // per-track constants of the culling test: 1 / (4 |d|^2), and for
+        // the expanded form (no offsets) |p|^2, 2 p.d, -2 p, -2 d
         const double dd = fma(uz, uz, fma(uy, uy, ux * ux));
-        const double hdd = dd > 0.0 ? fdiv(0.5, dd) : 0.0;
+        const double qd = dd > 0.0 ? fdiv(0.25, dd) : 0.0;
         const double pp = fma(z, z, fma(y, y, x * x));
         const double pd2 = 2.0 * fma(z, uz, fma(y, uy, x * ux));
         const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
@@ -1278,8 +1279,11 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                     g = fma(ctz[kk], mpz, fma(cty[kk], mpy, fma(ctx[kk], mpx, pp)));
                 }
                 const double lim = clim[kk];
-                const double tau = fmax(-b2 * hdd, 0.0);  // nearest point of the half-line
-                const double f = fma(tau, fma(tau, dd, b2), g);             // |w + tau d|^2 - shift
+                // squared distance from T to the half-line, less the shift:
+                // |w|^2 - (w.d)^2 / |d|^2 when the line's nearest point lies
+                // ahead (w.d < 0), else |w|^2
+                const double bn = fmin(b2, 0.0);
+                const double f = fma(-bn * qd, bn, g);
                 // every lane's f is defined; lanes past the tile's end are masked out
                 cm[kk] = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
             }
