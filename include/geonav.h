@@ -116,7 +116,9 @@ typedef struct geo_geometry geo_geometry;
  * 0 <= rmin <= rmax with rmax > 0 (cone: at both ends, rmax1 + rmax2 > 0),
  * dz > 0, segments and polycones 0 < dphi <= 2 pi, polycone planes as
  * above (each section with rmax > 0 at one of its planes at least),
- * rotations proper to 1e-12. Errors: GEO_ERR_INVALID_ARG,
+ * rotations proper to 1e-12. A tube or tube-segment daughter is held as
+ * the equal-radii cone (segment), the same solid, and evaluated by the
+ * cone's code in the navigators. Errors: GEO_ERR_INVALID_ARG,
  * GEO_ERR_NOMEM, GEO_ERR_HIP; *out is NULL on error. */
 int geo_geometry_create(const geo_volume_desc *volumes, int32_t nvol, geo_geometry **out);
 

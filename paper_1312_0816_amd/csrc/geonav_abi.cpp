@@ -199,6 +199,20 @@ int make_base(int kind, const double *p, ShapeRec &out, double *bound_r, const c
 // Validate a shape and derive its device record (and, for a polycone, its
 // sections in *pc, which must then be non-NULL). A segment or polycone whose
 // range is a full turn (dphi == 2 pi) is stored uncut.
+// The equal-radii cone (segment) of a tube (segment): the same solid.
+geo_shape as_cone(const geo_shape &s) {
+    geo_shape c = s;
+    c.kind = s.kind == GEO_TUBE ? GEO_CONE : GEO_CONS;
+    c.par[0] = s.par[2];  // dz
+    c.par[1] = c.par[3] = s.par[0];  // rmin at both ends
+    c.par[2] = c.par[4] = s.par[1];  // rmax at both ends
+    if (s.kind == GEO_TUBS) {
+        c.par[5] = s.par[3];  // phi1
+        c.par[6] = s.par[4];  // dphi
+    }
+    return c;
+}
+
 int make_shape(const geo_shape &s, ShapeRec &out, PconRec *pc, double *bound_r, const char *what) {
     std::memset(&out, 0, sizeof out);
     const int np = nparams(s);
@@ -427,6 +441,14 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             snprintf(what, sizeof what, "volume %d daughter %d", iv, k);
             rc = make_shape(d.daughters[k], dr.shape, &pc, &dr.bound_r, what);
             if (rc) return rc;
+            // A tube (segment) daughter is stored as the equal-radii cone
+            // (segment), the same solid: the batches of queued pairs of the
+            // culled navigators then hold one kind fewer, each batch running
+            // every kind's code once.
+            if (d.daughters[k].kind == GEO_TUBE || d.daughters[k].kind == GEO_TUBS) {
+                rc = make_shape(as_cone(d.daughters[k]), dr.shape, &pc, &dr.bound_r, what);
+                if (rc) return rc;
+            }
             if (dr.shape.kind == kPcon || dr.shape.kind == kPcons) {
                 pcons.push_back(pc);
                 pcon_owner.push_back(-1 - (int64_t)dau.size());
