@@ -45,10 +45,10 @@ BYTES_PER_TRACK = 60             # 6 x 8 B in (x, y, z, ux, uy, uz) + 8 B step +
 # launch does comes from the library's census (geo_navigate_batched_census):
 # lane-evaluations per daughter kind, culling tests and tracks.
 FLOPS_MOTHER_BOX = 6             # box DistFromInside: 3 x (sub, div)
-FLOPS_TRACK_CULL = 23            # once per track: |d|^2 (5), 1 / (4 |d|^2) (1), |p|^2 (5),
-                                 # 2 p.d (6), -2 p (3), -2 d (3)
-FLOPS_CULL_TEST = 15             # 2 (p - T).d (3 fma), |p|^2 - 2 p.T (3 fma), the half-line's
-                                 # distance term (mul, fma)
+FLOPS_TRACK_CULL = 24            # once per track: |d|^2 (5), 1 / |d| (sqrt, div), |p|^2 (5),
+                                 # p.e with e = d / |d| (6), -2 p (3), -e (3)
+FLOPS_CULL_TEST = 14             # (p - T).e (3 fma), |p|^2 - 2 p.T (3 fma), the half-line's
+                                 # distance term (fma)
 FLOPS_ROTATION = 30              # R^T w and R^T d (2 x 3 x (mul + 2 fma))
 FLOPS_DIST_OUT = [               # census slot 2 * kind + hole
     21, 21,                      # box: 3 slab excesses + 3 faces x (div, mul, 2 fma)

@@ -93,11 +93,11 @@ static_assert(sizeof(DaughterRec) == 368, "DaughterRec layout");
 // culling radius (bounding radius enlarged by 1e-6 relative + 1e-6) and its
 // square, and the threshold q of the expanded test of the compacted
 // navigator: that test evaluates the squared distance from T to the
-// track's half-line, less |T|^2, as |p|^2 - 2 p.T - b^2 / (4 |d|^2) with
-// b = min(2 (p - T).d, 0); every term is at most (|p| + |T|)^2, so the
-// rounding error is below 16 eps (2 R + 2 |T|)^2 for a track inside the
-// mother (R the mother's bounding radius); q = r2 - |T|^2 +
-// 64 eps (3 R + 2 |T|)^2.
+// track's half-line, less |T|^2, as |p|^2 - 2 p.T - b^2 with
+// b = min((p - T).e, 0) and e = d / |d| (1 / |d| to a few ulp); every term
+// is at most (|p| + |T|)^2, so the rounding error is below
+// 16 eps (2 R + 2 |T|)^2 for a track inside the mother (R the mother's
+// bounding radius); q = r2 - |T|^2 + 64 eps (3 R + 2 |T|)^2.
 struct alignas(16) CullRec {
     double tx, ty, tz, r2;
     double r;    // the enlarged radius itself
@@ -143,6 +143,21 @@ __device__ __forceinline__ double fdiv(double n, double d) {
     e = fma(-d, r, 1.0);
     r = fma(r, e, r);
     return n * r;
+}
+
+// 1 / sqrt(x) for finite x > 0, within a few ulp: the hardware estimate
+// refined by two Newton steps (each squares the relative error, so an
+// estimate within 2^-13 reaches full precision). x below 2^-960, subnormals
+// included, is scaled by 2^1000 first.
+__device__ __forceinline__ double rsqrt_fine(double x) {
+    const bool tiny = x < 0x1p-960;
+    const double xs = tiny ? x * 0x1p1000 : x;
+    double z = __builtin_amdgcn_rsq(xs);
+    double e = fma(-xs * z, z, 1.0);  // 1 - x z^2
+    z = fma(0.5 * z, e, z);
+    e = fma(-xs * z, z, 1.0);
+    z = fma(0.5 * z, e, z);
+    return tiny ? z * 0x1p500 : z;
 }
 
 // sqrt(x) from the hardware reciprocal square root with a Goldschmidt step
@@ -1230,14 +1245,16 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         const double ms = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
         lds_store(&S.key[j], step_key(ms, true));
         lds_store(&S.hit[j], -1);
-        // per-track constants of the culling test: 1 / (4 |d|^2), and for
-        // the expanded form (no offsets) |p|^2, 2 p.d, -2 p, -2 d
+        // per-track constants of the culling test: the unit direction e
+        // (as -e), and for the expanded form (no offsets) |p|^2, p.e, -2 p;
+        // a zero direction, or one whose |d|^2 overflows, gives e = 0 (the
+        // test then takes the start point)
         const double dd = fma(uz, uz, fma(uy, uy, ux * ux));
-        const double qd = dd > 0.0 ? fdiv(0.25, dd) : 0.0;
+        const double il = (dd > 0.0 && dd < __builtin_inf()) ? rsqrt_fine(dd) : 0.0;
         const double pp = fma(z, z, fma(y, y, x * x));
-        const double pd2 = 2.0 * fma(z, uz, fma(y, uy, x * ux));
+        const double pe = fma(z, uz, fma(y, uy, x * ux)) * il;
         const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
-        const double mux = -2.0 * ux, muy = -2.0 * uy, muz = -2.0 * uz;
+        const double mex = -ux * il, mey = -uy * il, mez = -uz * il;
         // Daughters in chunks of kCullChunk (the tables are padded to whole
         // chunks with records that never pass): the queue is flushed between
         // chunks when a chunk could overflow it, so the tests of a chunk run
@@ -1263,7 +1280,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 const int k = k0 + kk;
-                double b2, g;  // 2 w.d and |w|^2 - shift, with w = p - centre
+                double b, g;  // w.e and |w|^2 - shift, with w = p - centre
                 if (HAS_OFFS) {
                     // the centre moves with the offset: w formed explicitly, shift 0,
                     // limit r2
@@ -1271,19 +1288,19 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                     const double wx = x - ctx[kk] - offs[3 * ko + 0];
                     const double wy = y - cty[kk] - offs[3 * ko + 1];
                     const double wz = z - ctz[kk] - offs[3 * ko + 2];
-                    b2 = fma(wz, -muz, fma(wy, -muy, wx * -mux));
+                    b = fma(wz, -mez, fma(wy, -mey, wx * -mex));
                     g = fma(wz, wz, fma(wy, wy, wx * wx));
                 } else {
                     // shift |T|^2, limit q (its rounding bound included)
-                    b2 = fma(ctz[kk], muz, fma(cty[kk], muy, fma(ctx[kk], mux, pd2)));
+                    b = fma(ctz[kk], mez, fma(cty[kk], mey, fma(ctx[kk], mex, pe)));
                     g = fma(ctz[kk], mpz, fma(cty[kk], mpy, fma(ctx[kk], mpx, pp)));
                 }
                 const double lim = clim[kk];
                 // squared distance from T to the half-line, less the shift:
-                // |w|^2 - (w.d)^2 / |d|^2 when the line's nearest point lies
-                // ahead (w.d < 0), else |w|^2
-                const double bn = fmin(b2, 0.0);
-                const double f = fma(-bn * qd, bn, g);
+                // |w|^2 - (w.e)^2 when the line's nearest point lies ahead
+                // (w.e < 0), else |w|^2
+                const double bn = fmin(b, 0.0);
+                const double f = fma(-bn, bn, g);
                 // every lane's f is defined; lanes past the tile's end are masked out
                 cm[kk] = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
             }
