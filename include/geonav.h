@@ -37,7 +37,13 @@
  *            like the segments (dphi = 2 pi: uncut).
  *   Parameters beyond those a kind reads are ignored.
  *   Shapes are closed sets. Directions are not renormalised: distances are
- *   the ray parameter t of p + t*d (the length when |d| = 1).
+ *   the ray parameter t of p + t*d (the length when |d| = 1). Every
+ *   finite t must stay below GEO_BIG, the value of a miss, so |d| is at
+ *   least 1e-30 times the largest extent of the geometry; and |d| is at
+ *   most 1e100 (the ray-surface quadratics square products of |d| with
+ *   coordinates and section slopes: at |d| near 1e150 a steep polycone
+ *   section far from the track overflows them). Outside that range the
+ *   results are not specified.
  *   A line that never reaches the boundary gives GEO_BIG.
  */
 #ifndef GEONAV_H

@@ -494,6 +494,23 @@ def test_navigator_matches_ray_marching(orc):
 
 # ------------------------------------------------------ adjoint (FD) pins
 
+def test_navigator_direction_scaling_over_the_supported_range(orc):
+    """The navigator's step is a ray parameter: scaling each track's
+    direction by a power of two s from about 1e-20 to 1e100 scales its step
+    by exactly 1 / s and keeps its hit, on both detectors (all six kinds):
+    every term of the ray-surface equations scales by a power of s."""
+    for vol in (W.toy_detector_volume(), W.mixed_detector_volume()):
+        rng = np.random.default_rng(77)
+        tr = W.tracks_in_mother(rng, vol, 2000)
+        s0, h0, _ = orc.navigate(vol, tr)
+        scale = np.ldexp(1.0, rng.choice([-66, -27, 27, 166, 332], tr.shape[1]))
+        t2 = tr.copy()
+        t2[3:] *= scale
+        s1, h1, _ = orc.navigate(vol, np.ascontiguousarray(t2))
+        assert np.array_equal(h0, h1)
+        assert np.array_equal(s1 * scale, s0)
+
+
 def test_fd_matches_closed_form_plane_hit(orc):
     """Box daughter (identity rotation) at T = (100, 0, 0), half-lengths
     (10, 20, 30): a ray from o with d_x > 0 enters the face x = 90 + delta_x
