@@ -11,7 +11,8 @@ one wavefront per tile, whichever the autotuner finds faster). The timed
 steps follow enough warmup steps for the GPU to reach its full clock.
 
 Printed: one JSON line with tracks/s, the plain per-basket comparison (512
-separate geo_navigate_basket launches doing the same work), the roofline of
+separate geo_navigate_basket launches doing the same work, issued one by one
+and, beside that, captured in one HIP graph), the roofline of
 the dominant kernel (the batched navigator, FP64-ALU-bound; its duration
 from HIP events that the graph records around the kernel node, and beside
 it the rate over the whole graph launch), the HBM fraction, and the CPU
@@ -485,6 +486,37 @@ def main():
         torch.cuda.synchronize()
         plain_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
+    # the plain form with its launches captured in one HIP graph and the
+    # graph replayed once per step: the per-basket kernels without the
+    # host's cost of 512 launches
+    plain_graph_ms, plain_graph_same = None, None
+    if not args.no_plain:
+        cg = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        with torch.cuda.graph(cg, stream=cs):
+            hcap = gv._stream(cs)
+            for v, tb, s_, h_ in plain:
+                gv._check(lib.geo_navigate_basket(g.handle, v, tb, None, s_, h_, None, hcap))
+        stream.wait_stream(cs)
+        pstep.fill_(-1.0)
+        phit.fill_(-2)
+        cg.replay()
+        torch.cuda.synchronize()
+        plain_graph_same = bool(torch.equal(step.view(torch.int64), pstep.view(torch.int64))
+                                and torch.equal(hit, phit))
+        for _ in range(args.warmup):
+            cg.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cg.replay()
+        torch.cuda.synchronize()
+        plain_graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        plain_graph_same = plain_graph_same and bool(
+            torch.equal(step.view(torch.int64), pstep.view(torch.int64)) and torch.equal(hit, phit))
+        del cg
+
     value = n / (ms_per_step * 1e-3)
     flops = census_flops(counts, True)
     flops_nocull = census_flops(counts_nocull, False)
@@ -534,6 +566,10 @@ def main():
             "value": n / (plain_ms * 1e-3), "unit": "tracks/s", "ms_per_step": plain_ms,
             "launches": len(plain)},
         "batched_over_plain": None if plain_ms is None else plain_ms / ms_per_step,
+        "plain_per_basket_graph": None if plain_graph_ms is None else {
+            "value": n / (plain_graph_ms * 1e-3), "unit": "tracks/s", "ms_per_step": plain_graph_ms,
+            "launches": len(plain), "equals_batched_bitwise": plain_graph_same},
+        "batched_over_plain_graph": None if plain_graph_ms is None else plain_graph_ms / ms_per_step,
         "batched_without_culling": {"value": n / (nocull_ms * 1e-3), "unit": "tracks/s",
                                     "ms_per_step": nocull_ms, "flops_per_launch": flops_nocull,
                                     "achieved_TFLOPs": flops_nocull / (nocull_ms * 1e-3) / 1e12,

@@ -115,6 +115,44 @@ def test_graph_replays_interleaved(gv, small):
     g.close()
 
 
+def test_basket_calls_in_a_captured_graph(gv, small):
+    """geo_navigate_basket calls captured in one HIP graph (torch.cuda.graph)
+    and replayed three times, with output clearing, other device work and
+    host synchronisation between the replays: every replay equals the eager
+    per-basket result bit for bit."""
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    s0, h0 = per_basket(gv, g, small, t)
+    subs = []
+    for b in range(len(small.basket_n)):
+        o, m = int(small.basket_offset[b]), int(small.basket_n[b])
+        if m > 0:
+            subs.append((o, m, int(small.basket_volume[b]), t[:, o:o + m].contiguous()))
+    torch.cuda.synchronize()
+    cg = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    outs = []
+    with torch.cuda.graph(cg, stream=cs):
+        for o, m, v, sub in subs:
+            outs.append((o, m) + tuple(gv.geo_navigate_basket(g, v, sub, stream=cs)))
+    torch.cuda.current_stream().wait_stream(cs)
+    for rep in range(3):
+        for _, _, st, ht in outs:
+            st.fill_(-1.0)
+            ht.fill_(-7)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()
+        cg.replay()
+        junk.item()
+        torch.cuda.synchronize()
+        for o, m, st, ht in outs:
+            assert np.array_equal(st.cpu().numpy().view(np.int64), s0[o:o + m].view(np.int64)), (rep, o)
+            assert np.array_equal(ht.cpu().numpy(), h0[o:o + m]), (rep, o)
+    del cg
+    g.close()
+
+
 def test_full_workload_bit_identical(gv):
     """The full 512-basket, 64-volume workload (about 4.4M tracks)."""
     import torch
