@@ -350,8 +350,9 @@ def main():
                     help="run one 1 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the navigator has no multi-GPU path in this "
-              "build (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the navigator has no multi-GPU path (tracks "
+              "are independent, so each GPU would take its own share of the baskets); run "
+              "with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -107,7 +107,7 @@ def test_suite_full_size_sampled(gv, orc, kind):
 
 def test_tube_equals_equal_radii_cone_on_gpu(gv):
     """cone(dz, a, b, a, b) and tube(a, b, dz) go through different kernels and
-    must agree (C12)."""
+    must agree."""
     _, par, t = W.shape_suite_c1(W.TUBE, n=50000, seed=5)
     cpar = [par[2], par[0], par[1], par[0], par[1]]
     for q in QUERIES:
@@ -131,7 +131,7 @@ def test_hole_free_and_pointed_shapes(gv, orc):
 
 
 def test_axis_aligned_and_unnormalised_directions(gv, orc):
-    """Directions with exact zero components and non-unit lengths (C6, C7)."""
+    """Directions with exact zero components and non-unit lengths."""
     rng = np.random.default_rng(3)
     for kind in (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON):
         par = W.SUITE_SHAPES[kind]

@@ -61,7 +61,7 @@ def test_constructed_inside_points_are_contained(orc, kind):
 def test_safety_is_min_over_directions(orc, kind):
     """Safety(p) = min over unit directions of DistFromInside (p inside) or
     DistFromOutside (p outside): a lower bound for every direction and
-    attained along the direction to the nearest boundary point (C3)."""
+    attained along the direction to the nearest boundary point."""
     _, par, t = _suite(kind, 240, 4242 + kind)
     _check_safety_variational(orc, kind, par, t)
 
@@ -150,7 +150,7 @@ def _check_ray_marching(orc, kind, par, t):
 
 @pytest.mark.parametrize("prec", ["d", "ld"])
 def test_tube_is_cone_with_equal_radii(orc, prec):
-    """cone(dz, a, b, a, b) is the tube (a, b, dz) (C12)."""
+    """cone(dz, a, b, a, b) is the tube (a, b, dz)."""
     _, par, t = _suite(W.TUBE, 20000, 31)
     rmin, rmax, dz = par[:3]
     cpar = [dz, rmin, rmax, rmin, rmax]
@@ -166,7 +166,7 @@ def test_tube_is_cone_with_equal_radii(orc, prec):
 
 @pytest.mark.parametrize("kind", ALL_KINDS)
 def test_direction_scaling(orc, kind):
-    """Directions are not renormalised: scaling d by lam scales t by 1/lam (C6)."""
+    """Directions are not renormalised: scaling d by lam scales t by 1/lam."""
     _, par, t = _suite(kind, 5000, 55 + kind)
     for q in (orc.DIST_IN, orc.DIST_OUT):
         a = orc.shape_query(kind, par, q, t)
@@ -181,7 +181,7 @@ def test_direction_scaling(orc, kind):
 
 @pytest.mark.parametrize("kind", ALL_KINDS)
 def test_hit_point_on_surface_and_entry_exit(orc, kind):
-    """The entry point p + t d lies on the surface (Safety there ~ 0, C17),
+    """The entry point p + t d lies on the surface (Safety there ~ 0),
     and leaving from just inside the entry point is consistent."""
     _, par, t = _suite(kind, 20000, 99 + kind)
     dout = orc.dist_out(kind, par, t)
@@ -215,7 +215,7 @@ def test_convex_chord_reversibility(orc):
 
 def test_long_double_rerun_agrees(orc):
     """The double and long-double builds agree to 1e-12 except on a tiny
-    fraction of ill-conditioned tracks (C15)."""
+    fraction of ill-conditioned tracks."""
     for kind in ALL_KINDS:
         _, par, t = _suite(kind, 50000, 123 + kind)
         for q in (orc.SAFETY, orc.DIST_IN, orc.DIST_OUT):
@@ -434,8 +434,8 @@ def test_navigator_rotation_convention(orc):
 
 
 def test_navigator_ties_and_offsets(orc):
-    """Mother first, then the lowest daughter index, win ties (C8); an offset
-    delta acts exactly as an extra translation (C10)."""
+    """Mother first, then the lowest daughter index, win ties; an offset
+    delta acts exactly as an extra translation."""
     vol = W.Volume(W.BOX, np.array([100.0, 100.0, 100.0, 0, 0]), np.array([0, 0], np.int32),
                    np.array([[10, 10, 10, 0, 0], [10, 10, 10, 0, 0]], float),
                    np.stack([np.eye(3).reshape(9)] * 2), np.array([[50.0, 0, 0], [50.0, 0, 0]]),
