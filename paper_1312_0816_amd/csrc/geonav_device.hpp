@@ -1364,20 +1364,29 @@ __device__ __forceinline__ unsigned long long safety_key(double s) {
     return s == s ? step_key(s) : ~0ull;
 }
 
+// Scratch of the compacted safety and localization: the navigator's, plus
+// the wavefront's points, which the queued pairs read back from LDS instead
+// of global memory (each lane stores its own point; the batches read them
+// later in the same wavefront's program order).
+template <int U>
+struct PointScratch : NavScratch<U> {
+    double px[U * 64], py[U * 64], pz[U * 64];
+};
+
 template <int MODE, bool HAS_OFFS, int KSET, int U>  // MODE 0: safety, 1: locate
 __device__ __forceinline__ void point_flush(const DaughterRec *__restrict__ dau,
                                             const CullRec *__restrict__ cul,
-                                            const double *__restrict__ offs, const TracksDev &t,
-                                            int64_t base, NavScratch<U> &S, int qn, int lane) {
+                                            const double *__restrict__ offs, PointScratch<U> &S,
+                                            int qn, int lane) {
     for (int e0 = 0; e0 < qn; e0 += 64) {
         const int e = e0 + lane;
         if (e < qn) {
             const unsigned int q = S.queue[e];
             const int j = (int)(q & 1023u);
             const int k = (int)(q >> 10);
-            const int64_t i = base + j;
             const CullRec &Q = cul[k];
-            double wx = t.x[i] - Q.tx, wy = t.y[i] - Q.ty, wz = t.z[i] - Q.tz;
+            double wx = lds_load(&S.px[j]) - Q.tx, wy = lds_load(&S.py[j]) - Q.ty,
+                   wz = lds_load(&S.pz[j]) - Q.tz;
             if (HAS_OFFS) {
                 wx -= offs[3 * k + 0];
                 wy -= offs[3 * k + 1];
@@ -1405,7 +1414,7 @@ template <int MODE, bool HAS_OFFS, int KSET, int U>
 __device__ __forceinline__ void point_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                               const CullRec *__restrict__ cul,
                                               const double *__restrict__ offs, const TracksDev &t,
-                                              int64_t base, int count, NavScratch<U> &S, int lane,
+                                              int64_t base, int count, PointScratch<U> &S, int lane,
                                               double *__restrict__ out_s,
                                               int32_t *__restrict__ out_w) {
     int qn = 0;
@@ -1418,6 +1427,9 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
         const bool act = j < count;
         const int64_t i = base + (act ? j : 0);
         const double x = t.x[i], y = t.y[i], z = t.z[i];
+        lds_store(&S.px[j], x);
+        lds_store(&S.py[j], y);
+        lds_store(&S.pz[j], z);
         double reach = 0.0;
         bool in_m = false;
         if (MODE == 0) {
@@ -1431,9 +1443,14 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
         }
         const unsigned long long amask = __builtin_amdgcn_ballot_w64(MODE == 0 ? act : (act && in_m));
         if (amask == 0ull) continue;
+        // per-point constants of the expanded test (no offsets): |p|^2, -2 p,
+        // and for the safety 2 reach and reach^2
+        const double pp = fma(z, z, fma(y, y, x * x));
+        const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
+        const double reach2 = 2.0 * reach, rr = reach * reach;
         for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
             if (qn > kQueueCap - 64 * kCullChunk) {
-                point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, t, base, S, qn, lane);
+                point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, S, qn, lane);
                 qn = 0;
             }
             unsigned long long cm[kCullChunk];
@@ -1441,20 +1458,33 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 const int k = k0 + kk;
                 const CullRec &Q = cul[k];
-                double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
-                if (HAS_OFFS) {
-                    const int ko = k < nd ? k : 0;
-                    wx -= offs[3 * ko + 0];
-                    wy -= offs[3 * ko + 1];
-                    wz -= offs[3 * ko + 2];
-                }
-                const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
                 bool pass;
-                if (MODE == 0) {
-                    const double lim = reach + Q.r;
-                    pass = ww < lim * lim;
+                if (HAS_OFFS) {
+                    // the centre moves with the offset: |w|^2 formed explicitly
+                    const int ko = k < nd ? k : 0;
+                    const double wx = x - Q.tx - offs[3 * ko + 0];
+                    const double wy = y - Q.ty - offs[3 * ko + 1];
+                    const double wz = z - Q.tz - offs[3 * ko + 2];
+                    const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
+                    if (MODE == 0) {
+                        const double lim = reach + Q.r;
+                        pass = ww < lim * lim;
+                    } else {
+                        pass = ww <= Q.r2;
+                    }
                 } else {
-                    pass = ww <= Q.r2;
+                    // |w|^2 - |T|^2 = |p|^2 - 2 p.T against the thresholds less
+                    // |T|^2: r^2 - |T|^2 (q, its rounding bound included) for
+                    // the containment, (reach + r)^2 - |T|^2 = q + 2 r reach +
+                    // reach^2 for a daughter that may be nearer than reach
+                    // (reach is at most the mother's bounding radius R for a
+                    // point inside the mother, so every term stays within the
+                    // (3 R + 2 |T|)^2 that the bound of q covers)
+                    const double g = fma(Q.tz, mpz, fma(Q.ty, mpy, fma(Q.tx, mpx, pp)));
+                    if (MODE == 0)
+                        pass = g < fma(Q.r, reach2, Q.q) + rr;
+                    else
+                        pass = g <= Q.q;
                 }
                 // padding records (k >= nd) are excluded here: their radius is 0
                 cm[kk] = __builtin_amdgcn_ballot_w64(pass) & (k < nd ? amask : 0ull);
@@ -1469,7 +1499,7 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
             }
         }
     }
-    point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, t, base, S, qn, lane);
+    point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, S, qn, lane);
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;

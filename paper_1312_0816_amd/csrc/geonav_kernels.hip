@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restri
                                                        const double *__restrict__ offs,
                                                        double *__restrict__ out) {
     if constexpr (CULL) {
-        __shared__ NavScratch<U> scr[kBlock / 64];
+        __shared__ PointScratch<U> scr[kBlock / 64];
         const int wave = threadIdx.x >> 6;
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         if (base >= t.n) return;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restri
                                                        const double *__restrict__ offs,
                                                        int32_t *__restrict__ out) {
     if constexpr (CULL) {
-        __shared__ NavScratch<U> scr[kBlock / 64];
+        __shared__ PointScratch<U> scr[kBlock / 64];
         const int wave = threadIdx.x >> 6;
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         if (base >= t.n) return;
