@@ -21,12 +21,30 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-def test_traffic_is_read_only_for_the_profiled_source_and_shape():
-    digest = bench.kernel_source_digest()
-    b = bench.read_traffic(digest, "4,0")
-    assert b is not None and 255e6 < b < 1e9     # at least the algorithmic 255.5 MB
-    assert bench.read_traffic(digest, "3,1") is None
+def test_traffic_is_read_only_for_the_profiled_source_and_shape(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "k_nav_tiles_batched512.md").write_text(
+        "# summary\n\ntraffic: kernel_source=abcdef0123456789 launch=4,0 bytes_per_launch=387000000\n"
+        "traffic: kernel_source=abcdef0123456789 launch=2,0 bytes_per_launch=322000000\n"
+        "traffic: kernel_source=1111111111111111 launch=4,0 bytes_per_launch=1\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.read_traffic("abcdef0123456789", "4,0") == 387e6
+    assert bench.read_traffic("abcdef0123456789", "2,0") == 322e6
+    assert bench.read_traffic("abcdef0123456789", "3,1") is None
     assert bench.read_traffic("0" * 16, "4,0") is None
+    (tmp_path / "profiles" / "k_nav_tiles_batched512.md").unlink()
+    assert bench.read_traffic("abcdef0123456789", "4,0") is None
+
+
+def test_committed_summary_names_a_digest_and_both_shapes():
+    path = os.path.join(ROOT, "profiles", "k_nav_tiles_batched512.md")
+    lines = [ln.split() for ln in open(path) if ln.startswith("traffic:")]
+    shapes = {dict(kv.split("=", 1) for kv in ln[1:])["launch"] for ln in lines}
+    assert {"4,0", "2,0"} <= shapes
+    for ln in lines:
+        vals = dict(kv.split("=", 1) for kv in ln[1:])
+        assert len(vals["kernel_source"]) == 16
+        assert 255e6 < float(vals["bytes_per_launch"]) < 1e9   # at least the algorithmic 255.5 MB
 
 
 def test_digest_ignores_comments_and_layout_only(tmp_path, monkeypatch):
