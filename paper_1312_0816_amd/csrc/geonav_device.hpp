@@ -1109,7 +1109,8 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // the sequential loop, whose strict < keeps the earlier of equal steps.
 // Each track's running minimum sits in LDS as a 64-bit key (an
 // order-preserving map of the double, -0 taken as +0, so that a step of -0
-// is reported as +0 as in the sequential loop) and an index; a
+// is reported as +0 as in the sequential loop) and an index (packed with the
+// surface that set the step, see hit_pack); a
 // batch merges into it with a 64-bit LDS min on the key, then, for the
 // pairs whose key equals the new minimum, an integer min on the index
 // (reset first when the batch lowered the key). After every batch the slot
@@ -1179,17 +1180,26 @@ __device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const 
     return any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
 }
 
-// Merges candidate (s, k) into track slot j's running minimum. Lanes of one
-// call may share a slot; whatever the order of calls, the slot ends at the
-// lexicographic minimum of all candidates merged.
+// A hit slot holds the candidate's index k (-1 for the mother) and the
+// surface that set its step (sid, -1 .. 254) as k * 256 + sid + 1: ordered
+// by k, since each index has one candidate per track, and the adjoint reads
+// the winner's surface back without evaluating it again.
+__device__ __forceinline__ int hit_pack(int k, int sid) { return k * 256 + (sid + 1); }
+__device__ __forceinline__ int hit_index(int v) { return v >> 8; }
+__device__ __forceinline__ int hit_surface(int v) { return (v & 255) - 1; }
+
+// Merges candidate (s, k) with surface sid into track slot j's running
+// minimum. Lanes of one call may share a slot; whatever the order of calls,
+// the slot ends at the lexicographic minimum of all candidates merged.
 template <int U>
-__device__ __forceinline__ void merge_step(NavScratch<U> &S, int j, double s, int k) {
+__device__ __forceinline__ void merge_step(NavScratch<U> &S, int j, double s, int k, int sid) {
     const unsigned long long key = step_key(s);
     const unsigned long long before = lds_load(&S.key[j]);
     __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     const unsigned long long now = lds_load(&S.key[j]);
     if (now < before) lds_store(&S.hit[j], 0x7fffffff);
-    if (key == now) __hip_atomic_fetch_min(&S.hit[j], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (key == now)
+        __hip_atomic_fetch_min(&S.hit[j], hit_pack(k, sid), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 template <int U, bool HAS_OFFS, bool COUNT, int KSET>
@@ -1216,7 +1226,7 @@ __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
             int sid;
             const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, t.x[i], t.y[i],
                                                                t.z[i], t.ux[i], t.uy[i], t.uz[i], sid);
-            merge_step(S, j, s, k);
+            merge_step(S, j, s, k, sid);
         }
     }
 }
@@ -1246,7 +1256,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         int sid;
         const double ms = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
         lds_store(&S.key[j], step_key(ms, true));
-        lds_store(&S.hit[j], -1);
+        lds_store(&S.hit[j], hit_pack(-1, sid));
         // per-track constants of the culling test: the unit direction e
         // (as -e), and for the expanded form (no offsets) |p|^2, p.e, -2 p;
         // a zero direction, or one whose |d|^2 overflows, gives e = 0 (the
@@ -1339,7 +1349,7 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
             const int64_t i = base + j;
             const double s = key_step(lds_load(&S.key[j]));
             step[i] = s;
-            hit[i] = lds_load(&S.hit[j]);
+            hit[i] = hit_index(lds_load(&S.hit[j]));
             if (HITPT) {
                 const int64_t n = t.n;
                 hitpt[i] = fma(s, t.ux[i], t.x[i]);

@@ -464,13 +464,12 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             double best;
             int sid;
             if constexpr (CULL) {
-                // the surface that set the step: the winner evaluated again
-                // (the same function on the same inputs, hence the same
-                // candidate)
+                // the step, the winner and the surface that set its step, as
+                // the compacted navigator left them
                 best = key_step(lds_load(&scr[wave].key[lane]));
-                h = lds_load(&scr[wave].hit[lane]);
-                if (h < 0) (void)any_dist_in<KSET>(vol->mother, vol->pcon, x, y, z, ux, uy, uz, sid);
-                else (void)daughter_dist_out<HAS_OFFS, KSET>(dau[h], cul[h], offs, h, x, y, z, ux, uy, uz, sid);
+                const int v = lds_load(&scr[wave].hit[lane]);
+                h = hit_index(v);
+                sid = hit_surface(v);
             } else {
                 nav_track<HAS_OFFS, true, false, KSET>(*vol, dau, cul, offs, x, y, z, ux, uy, uz, best,
                                                        h, sid);
