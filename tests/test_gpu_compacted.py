@@ -289,3 +289,20 @@ def test_direction_length_over_the_supported_range(gv, orc, mixed):
     # and long double builds disagree)
     check_nav(orc, vol, tr, step * scale, hit, what=f"scaled directions, mixed={mixed}",
               max_exempt_frac=5e-3)
+
+
+@pytest.mark.parametrize("with_offsets", [False, True])
+def test_wide_basket_of_every_kind(gv, orc, with_offsets):
+    """A basket of 2^20 + 37 tracks in a volume holding every kind (the wide
+    compacted form, 8 rounds of 64 tracks per wavefront): culled and
+    sequential paths agree bit for bit, hit points included, with and
+    without offsets; a sample matches the oracle."""
+    vol = W.mixed_detector_volume()
+    rng = np.random.default_rng(1601 + int(with_offsets))
+    n = (1 << 20) + 37
+    tr = W.tracks_in_mother(rng, vol, n)
+    offs = rng.uniform(-0.5, 0.5, (vol.nd, 3)) if with_offsets else None
+    step, hit = _all_paths(gv, [vol], tr, offs)
+    idx = np.sort(rng.choice(n, size=4000, replace=False))
+    print(check_nav(orc, vol, np.ascontiguousarray(tr[:, idx]), step[idx], hit[idx], offsets=offs,
+                    what=f"wide basket, offsets={with_offsets}", max_exempt_frac=5e-3))
