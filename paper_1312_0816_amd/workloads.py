@@ -390,6 +390,17 @@ def tracks_in_mother(rng, vol: Volume, n: int) -> np.ndarray:
     return pack_tracks(out[0], out[1], out[2], *u)
 
 
+def tracks_uniform_in_mother(rng, vol: Volume, n: int) -> np.ndarray:
+    """n tracks uniform in the box mother with no rejection at all (origins
+    fill the daughters too, and come arbitrarily close to their surfaces);
+    isotropic directions. A track that starts inside a daughter has step 0
+    and that daughter as its hit."""
+    h = np.asarray(vol.mother_par, np.float64)[:3]
+    p = rng.uniform(-1.0, 1.0, (3, n)) * h[:, None]
+    u = isotropic(rng, n)
+    return pack_tracks(p[0], p[1], p[2], *u)
+
+
 def toy_detector_c2(seed: int = 1200, n: int = 1 << 22):
     """Toy-detector navigator workload: the 32-daughter volume and n tracks.
     Returns (volume, tracks)."""
@@ -408,12 +419,16 @@ class BatchedWorkload:
 
 
 def batched_c3(seed: int = 1300, nvol: int = 64, nb: int = 512,
-               nmin: int = 32, nmax: int = 65536, scale: float = 1.0) -> BatchedWorkload:
+               nmin: int = 32, nmax: int = 65536, scale: float = 1.0,
+               reject: bool = True) -> BatchedWorkload:
     """Batched workload: nvol volumes (mother box (200)^3, 1..64 daughters
     each, uniform), nb baskets with volume = b mod nvol and size
     floor(nmin * (nmax / nmin)^u), u ~ U[0, 1) (log-uniform). The track pool
     is the concatenation of the baskets. ``scale`` shrinks every basket
-    (at least one track) for small test cases."""
+    (at least one track) for small test cases. With ``reject`` False the
+    tracks are uniform in the mother with no rejection
+    (``tracks_uniform_in_mother``); the geometry and basket sizes are the
+    same."""
     rng = np.random.default_rng(seed)
     vols = []
     for _ in range(nvol):
@@ -428,7 +443,8 @@ def batched_c3(seed: int = 1300, nvol: int = 64, nb: int = 512,
     offs[1:] = np.cumsum(sizes)[:-1]
     parts = []
     for b in range(nb):
-        parts.append(tracks_in_mother(rng, vols[bvol[b]], int(sizes[b])))
+        draw = tracks_in_mother if reject else tracks_uniform_in_mother
+        parts.append(draw(rng, vols[bvol[b]], int(sizes[b])))
     pool = np.ascontiguousarray(np.concatenate(parts, axis=1))
     return BatchedWorkload(vols, bvol, offs, sizes, pool)
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_1312_0816_amd import workloads as W
-from tests.parity import check_values, ill_conditioned
+from tests.parity import batched_parity, check_ties, check_values, ill_conditioned
 
 pytestmark = pytest.mark.gpu
 
@@ -80,6 +80,7 @@ def test_batched_matches_oracle(gv, orc, small):
         check_values(s[o:o + m], ref, ill, f"basket {b}")
         _, rh, gap = orc.navigate(vol, tr, None, "ld")
         assert np.array_equal(h[o:o + m][gap >= 1e-9], rh[gap >= 1e-9])
+        check_ties(orc, vol, tr, s[o:o + m], h[o:o + m], gap, what=f"basket {b}")
     g.close()
 
 
@@ -165,6 +166,28 @@ def test_full_workload_bit_identical(gv):
     assert np.array_equal(s1.view(np.int64), s0.view(np.int64))
     assert np.array_equal(h1, h0)
     g.close()
+
+
+THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+@pytest.mark.parametrize("reject", [True, False])
+def test_full_workload_every_track_matches_oracle(gv, orc, reject):
+    """The full batched workload (512 baskets, 64 volumes), every track
+    against the oracle's long-double build; with reject=False the tracks are
+    uniform in each mother with no rejection (some start inside daughters,
+    many near their surfaces)."""
+    import torch
+    wl = W.batched_c3(reject=reject)
+    g = gv.Geometry(wl.volumes)
+    t = torch.from_numpy(wl.tracks).cuda()
+    s, h = batched(gv, g, wl, t)
+    g.close()
+    rep = batched_parity(orc, wl, s, h, threads=THREADS)
+    print(f"batched workload, reject={reject}, every track:", rep)
+    assert rep["ok"], rep
+    assert rep["exempt"] <= max(8, 2e-3 * rep["tracks"])
+    assert rep["hit_ties"] <= max(8, 1e-3 * rep["tracks"])
 
 
 def test_empty_baskets_and_errors(gv, small):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1312_0816_amd import workloads as W
-from tests.parity import check_values, ill_conditioned
+from tests.parity import check_ties, check_values, ill_conditioned
 
 pytestmark = pytest.mark.gpu
 
@@ -32,6 +32,7 @@ def test_paper_toy_navigator_parity(gv, orc):
     print(check_values(s, ref, ill, "paper toy"))
     _, rh, gap = orc.navigate(vol, tr, None, "ld")
     assert np.array_equal(h[gap >= 1e-9], rh[gap >= 1e-9])
+    print("ties", check_ties(orc, vol, tr, s, h, gap, what="paper toy"))
     assert len(np.unique(h)) == vol.nd + 1
     g.close()
 
@@ -64,4 +65,8 @@ def test_paper_toy_basket_scan(gv, orc, N):
         ref, ill = ill_conditioned(lambda x: orc.navigate(vol, x, None, "d")[0],
                                    lambda x: orc.navigate(vol, x, None, "ld")[0], tr)
         check_values(s[o:o + tr.shape[1]], ref, ill, f"N={N} basket {b}")
+        _, rh, gap = orc.navigate(vol, tr, None, "ld")
+        m = tr.shape[1]
+        assert np.array_equal(h[o:o + m][gap >= 1e-9], rh[gap >= 1e-9])
+        check_ties(orc, vol, tr, s[o:o + m], h[o:o + m], gap, what=f"N={N} basket {b}")
     g.close()

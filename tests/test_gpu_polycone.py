@@ -54,7 +54,9 @@ def test_tracks_along_section_planes(gv, orc):
             d /= np.linalg.norm(d, axis=0)
             parts.append(np.concatenate([o, d]))
         t = np.ascontiguousarray(np.concatenate(parts, axis=1))
-        print(compare(gv, orc, W.PCON, par, t, f"section planes variant {v}", max_exempt_frac=0.25))
+        # at most 0.0746 of one variant's tracks exempt for one query (the
+        # oracle's classification of these seeded inputs), plus 0.01
+        print(compare(gv, orc, W.PCON, par, t, f"section planes variant {v}", max_exempt_frac=0.0846))
 
 
 def test_two_plane_polycone_matches_cone_on_gpu(gv):

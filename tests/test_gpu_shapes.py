@@ -1,9 +1,11 @@
 """Parity of the HIP shape queries (geo_shape_query) with the oracle."""
+import os
+
 import numpy as np
 import pytest
 
 from paper_1312_0816_amd import workloads as W
-from tests.parity import BIG, check_values, ill_conditioned, rel_diff
+from tests.parity import BIG, check_values, ill_conditioned, rel_diff, shape_parity
 from tests.util import load_closed_forms
 
 pytestmark = pytest.mark.gpu
@@ -45,6 +47,21 @@ def compare(gv, orc, kind, par, tracks, what, max_exempt_frac=2e-3):
                                    lambda t: orc.shape_query(kind, par, q, t, "ld"), tracks)
         reps.append(check_values(got, ref, ill, f"{what} {QNAME[q]}", max_exempt_frac))
     return reps
+
+
+@pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON])
+def test_suite_full_size_every_output(gv, orc, kind):
+    """The 2^20-track shape-suite workload, all four queries, every output
+    against the oracle's long-double build (Contains bit-exact except within
+    1e-9 of the surface; the rest within 1e-12 except ill-conditioned
+    tracks, classified among those beyond the tolerance)."""
+    _, par, t = W.shape_suite_c1(kind)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    for q in QUERIES:
+        rep = shape_parity(orc, kind, par, q, t, gpu_query(gv, kind, par, q, t), threads=threads)
+        print(W.KIND_NAMES[kind], QNAME[q], rep)
+        assert rep["ok"], rep
+        assert rep["exempt"] <= max(8, 2e-3 * t.shape[1])
 
 
 def test_box_small_workload(gv, orc):
@@ -197,6 +214,13 @@ def _edge_points(rng, kind, par, m):
     return np.stack([r * np.cos(ph), r * np.sin(ph), z])
 
 
+# Exempt fraction of the edge-aimed tracks per kind: the largest over the
+# queries as the oracle alone classifies these seeded inputs (DistFromOutside
+# dominates: box 0.408, tube 0.279, cone 0.266, tube segment 0.435, cone
+# segment 0.515), plus 0.01.
+EDGE_EXEMPT = {W.BOX: 0.418, W.TUBE: 0.289, W.CONE: 0.277, W.TUBS: 0.445, W.CONS: 0.526}
+
+
 @pytest.mark.parametrize("kind", [W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS])
 def test_tracks_aimed_at_edges(gv, orc, kind):
     """Lines from random origins through points of the shape's edges (rims,
@@ -206,13 +230,27 @@ def test_tracks_aimed_at_edges(gv, orc, kind):
     the distance only slightly, so these tracks are not exempt as
     ill-conditioned unless they merely touch the solid (a line through an
     edge of a convex solid from outside does so about half the time, and
-    more often at a segment's face edges)."""
+    more often at a segment's face edges). The exempt tracks are still
+    checked: a line that touches the closed solid at the aimed edge point q
+    is a hit at most at |q - o| or a miss, and where both sides report a hit
+    they agree to 1e-9."""
     rng = np.random.default_rng(61 + kind)
     par = W.SUITE_SHAPES[kind]
     m = 6000
     q = _edge_points(rng, kind, par, m)
     o = rng.uniform(-45, 45, (3, m))
     d = q - o
-    d /= np.linalg.norm(d, axis=0)
+    tq = np.linalg.norm(d, axis=0)
+    d /= tq
     t = np.ascontiguousarray(np.concatenate([o, d]))
-    print(compare(gv, orc, kind, par, t, f"{W.KIND_NAMES[kind]} edges", max_exempt_frac=0.6))
+    print(compare(gv, orc, kind, par, t, f"{W.KIND_NAMES[kind]} edges", max_exempt_frac=EDGE_EXEMPT[kind]))
+    got = gpu_query(gv, kind, par, 3, t)
+    ref, ill = ill_conditioned(lambda x: orc.dist_out(kind, par, x, "d"),
+                               lambda x: orc.dist_out(kind, par, x, "ld"), t)
+    ex = np.asarray(ill, bool)
+    g, r, lim = got[ex], ref[ex], tq[ex]
+    assert np.all((g == BIG) | (g <= lim * (1 + 1e-9) + 1e-9)), "a hit beyond the aimed edge point"
+    both = (g < BIG) & (r < BIG)
+    assert np.all(np.abs(g[both] - r[both]) <= 1e-9 * np.maximum(np.abs(r[both]), 1.0))
+    print(f"{W.KIND_NAMES[kind]} edges: {int(ex.sum())} exempt DistFromOutside, {int(both.sum())} hits on "
+          f"both sides, {int(((g == BIG) != (r == BIG)).sum())} hit/miss flips")
