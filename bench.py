@@ -27,7 +27,7 @@ of the headline step (and of the rows' workloads) against the oracle's
 long-double build. The headline value is null unless that parity passes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
-                       [--launch U,W | --no-autotune] [--no-rows] [--no-plain]
+                       [--launch U,W | --no-autotune] [--no-rows] [--no-scan] [--no-plain]
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ BYTES_PER_TRACK = 60             # 6 x 8 B in (x, y, z, ux, uy, uz) + 8 B step +
 # daughter (transform, DistFromOutside with its divisions and square roots).
 DENSE_FP64_BASE, DENSE_FP64_PER_DAUGHTER = 60, 130
 RAMP_MS = 200.0                  # back-to-back steps before the timed region
-FLUSH_BYTES = 1 << 30            # written between launches for the cold-cache timing
+FLUSH_BYTES = 1 << 30            # read between launches for the cold-cache timing
 CPU_PASSES = 3                   # whole-workload passes of the oracle on all threads
 PROFILE = "k_nav_tiles_batched512.md"
 
@@ -171,7 +171,7 @@ def cpu_threads(info: dict) -> int:
     return max(1, min(16, n))
 
 
-def measure_rows(gv, W, dev, steps):
+def measure_rows(gv, W, dev, steps, scan=True):
     """The other rows of the hot path, each on its own workload (not part of
     the step above): the shape queries on the shape-suite distribution tiled
     to 2^26 tracks (3.2 GB, far above the 256 MB last-level cache), the plain
@@ -280,7 +280,8 @@ def measure_rows(gv, W, dev, steps):
                                         "outputs": "g_o, g_d (3 x n) and g_off (32 x 3)"}
     g.close()
     del o, d, gh
-    rows["paper_toy_detector_basket_scan"] = basket_scan(gv, W, dev)
+    if scan:
+        rows["paper_toy_detector_basket_scan"] = basket_scan(gv, W, dev)
     return rows, keep
 
 
@@ -446,6 +447,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the parity check")
     ap.add_argument("--no-rows", action="store_true", help="skip the per-row measurements")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the basket-size scan among the rows (tens of thousands of launches)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip timing the plain per-basket form (for profiling the batched kernel)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -539,6 +542,7 @@ def main():
     for _ in range(args.warmup):
         batched_step()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -561,13 +565,14 @@ def main():
         batched_step()
         kms.append(g.batched_kernel_ms())
     kernel_ms = float(np.mean(kms))
-    # the same with every cache flushed first: a 1 GiB write between launches
+    # the same with every cache flushed first: a 1 GiB read between launches
     # evicts the workload (255 MB) from L2 and the 256 MB last-level cache,
-    # so the kernel reads its tracks from HBM
-    flush = torch.empty(FLUSH_BYTES // 8, dtype=torch.float64, device=dev)
+    # so the kernel reads its tracks from HBM (a read leaves clean lines: a
+    # write would charge the kernel for writing the flush buffer back)
+    flush = torch.ones(FLUSH_BYTES // 8, dtype=torch.float64, device=dev)
     kms_cold = []
-    for i in range(min(k_launches, 50)):
-        flush.fill_(float(i))
+    for _ in range(min(k_launches, 50)):
+        flush.sum()
         batched_step()
         kms_cold.append(g.batched_kernel_ms())
     del flush
@@ -710,7 +715,7 @@ def main():
             "timing": f"HIP events recorded by the graph around the kernel node, mean over {k_launches} launches",
             "cold_caches": {"kernel_ms_per_launch": kernel_ms_cold, "achieved": hbm_cold,
                             "frac": hbm_cold / HBM_PEAK_GBS,
-                            "timing": f"the same events, a 1 GiB write before each of {len(kms_cold)} launches"},
+                            "timing": f"the same events, a 1 GiB read before each of {len(kms_cold)} launches"},
             "graph_launch_ms": float(ev_ms),
             "achieved_over_graph_launch": BYTES_PER_TRACK * n / (ev_ms * 1e-3) / 1e9,
             "valu_issue": None if valu is None else {
@@ -755,7 +760,7 @@ def main():
     torch.cuda.empty_cache()
     keep = {}
     if not args.no_rows:
-        out["rows"], keep = measure_rows(gv, W, dev, args.steps)
+        out["rows"], keep = measure_rows(gv, W, dev, args.steps, scan=not args.no_scan)
     if not args.no_cpu:
         base, parity, parity_rows = oracle_leg(wl, out_step, out_hit, info, keep, unrejected)
         out["cpu_baseline"] = base

@@ -53,6 +53,7 @@ constexpr double kEdgeSlack = 1e-12;
 
 // Parameters each kind reads (the rest of par[] is ignored).
 static_assert(GEO_CENSUS_SLOTS == kCensusSlots, "census layout");
+static_assert(GEO_MAX_DAUGHTERS == kMaxDaughters, "daughters per volume");
 
 int nparams(const geo_shape &s) {
     switch (s.kind) {

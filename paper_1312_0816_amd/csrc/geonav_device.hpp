@@ -23,6 +23,7 @@
 namespace gn {
 
 constexpr double kBig = 1e30;
+constexpr int kMaxDaughters = 1024;  // daughters per volume (GEO_MAX_DAUGHTERS)
 constexpr int kCensusSlots = 16, kCensusCull = 14, kCensusTracks = 15;
 // kPcon is an uncut polycone, kPcons one cut to an azimuth range.
 enum : int32_t { kBox = 0, kTube = 1, kCone = 2, kTubs = 3, kCons = 4, kPcon = 5, kPcons = 6 };
@@ -1110,22 +1111,47 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // Each track's running minimum sits in LDS as a 64-bit key (an
 // order-preserving map of the double, -0 taken as +0, so that a step of -0
 // is reported as +0 as in the sequential loop) and an index (packed with the
-// surface that set the step, see hit_pack); a
-// batch merges into it with a 64-bit LDS min on the key, then, for the
-// pairs whose key equals the new minimum, an integer min on the index
-// (reset first when the batch lowered the key). After every batch the slot
-// holds the lexicographic minimum of all candidates merged so far, whatever
-// the order of the batches.
+// surface that set the step, see hit_pack); a batch merges into it with a
+// 64-bit LDS min on the key, then, for the pairs whose key equals the new
+// minimum, an integer min on the index (reset first when the batch lowered
+// the key). After every batch the slot holds the lexicographic minimum of
+// all candidates merged so far, whatever the order of the batches.
 //
-// Queue entries pack the daughter index (bits 10..31), the track's round
-// within the tile (bits 6..9) and its lane (bits 0..5). All LDS traffic of
-// a queue is the wavefront's own, whose LDS instructions execute in program
-// order, so no barrier is needed.
+// At the end of its round, each track that queued a pair takes a slot of
+// the wavefront's track cache in LDS, which holds its six coordinates; the
+// batches read their tracks from there rather than from global memory,
+// where the six component arrays put each track on six cache lines, long
+// evicted from L2 by the time its batch runs. (Pairs flushed within their
+// own round, when the queue fills or the slots run out, read their track
+// from global memory while it is still cached.) A flush empties the queue
+// and the slots. The queue is flushed when a chunk's pairs could overflow
+// it, when a round's tracks would overflow the slots, and at the end of the
+// tile.
+//
+// Queue entries pack the daughter index (bits 10..31) and the track's index
+// within the tile, round * 64 + lane (bits 0..9). All LDS traffic of the
+// queue, the slots and the minima is the wavefront's own, whose LDS
+// instructions execute in program order, so no barrier is needed.
 constexpr int kQueueCap = 512;
+constexpr int kSlots = 48;
+constexpr unsigned char kNoSlot = 255;
 template <int U>
 struct NavScratch {
-    unsigned long long key[U * 64];
-    int hit[U * 64];
+    unsigned long long key[U * 64];   // running minimum per track: key of the step
+    int hit[U * 64];                  // and the packed index of its candidate
+    unsigned char slot_of[U * 64];    // the track's slot, kNoSlot if none
+    double x[kSlots], y[kSlots], z[kSlots], ux[kSlots], uy[kSlots], uz[kSlots];
+    unsigned int queue[kQueueCap];    // (daughter << 10) | round * 64 + lane
+    static_assert(U * 64 <= 1024, "track index within the tile: 10 bits");
+};
+static_assert(kSlots < kNoSlot, "slot numbers");
+
+// Scratch of the compacted safety and localization (one round of 64 points
+// per wavefront): running minima per point and the queue of (point,
+// daughter) pairs, (daughter << 10) | point.
+struct PointQueue {
+    unsigned long long key[64];
+    int hit[64];
     unsigned int queue[kQueueCap];
 };
 
@@ -1141,7 +1167,7 @@ __device__ __forceinline__ double key_step(unsigned long long k) {
 }
 
 // Accesses to the running minima, which other lanes of the wavefront update
-// atomically.
+// atomically, and to the slots, which other lanes read.
 template <typename T>
 __device__ __forceinline__ T lds_load(const T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -1188,11 +1214,11 @@ __device__ __forceinline__ int hit_pack(int k, int sid) { return k * 256 + (sid 
 __device__ __forceinline__ int hit_index(int v) { return v >> 8; }
 __device__ __forceinline__ int hit_surface(int v) { return (v & 255) - 1; }
 
-// Merges candidate (s, k) with surface sid into track slot j's running
-// minimum. Lanes of one call may share a slot; whatever the order of calls,
-// the slot ends at the lexicographic minimum of all candidates merged.
-template <int U>
-__device__ __forceinline__ void merge_step(NavScratch<U> &S, int j, double s, int k, int sid) {
+// Merges candidate (s, k) with surface sid into running minimum j of S.
+// Lanes of one call may share a minimum; whatever the order of calls, it
+// ends at the lexicographic minimum of all candidates merged.
+template <typename Scratch>
+__device__ __forceinline__ void merge_step(Scratch &S, int j, double s, int k, int sid) {
     const unsigned long long key = step_key(s);
     const unsigned long long before = lds_load(&S.key[j]);
     __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -1202,33 +1228,74 @@ __device__ __forceinline__ void merge_step(NavScratch<U> &S, int j, double s, in
         __hip_atomic_fetch_min(&S.hit[j], hit_pack(k, sid), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// Runs the qn queued pairs in batches of 64 (one pair per lane), each
+// reading its track from its slot, or from global memory if the track has
+// none (pairs flushed within their own round), then empties the queue and
+// the slots.
 template <int U, bool HAS_OFFS, bool COUNT, int KSET>
 __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, const TracksDev &t,
-                                          int64_t base, NavScratch<U> &S, int qn, int lane,
+                                          int64_t base, NavScratch<U> &S, int &qn, int &ns, int lane,
                                           unsigned long long *census) {
     for (int e0 = 0; e0 < qn; e0 += 64) {
         const int e = e0 + lane;
         const bool on = e < qn;
         const unsigned int q = on ? S.queue[e] : 0u;
-        const int j = (int)(q & 1023u);  // round * 64 + lane of the track
+        const int j = (int)(q & 1023u);
         const int k = (int)(q >> 10);
         if (COUNT) {
-            const int slot = 2 * dau[k].shape.kind + dau[k].shape.hole;
-            for (int sl = 0; sl < 2 * (kPcons + 1); ++sl) {
-                const unsigned long long m = __ballot(on && slot == sl);
-                if (m != 0ull && lane == __ffsll(m) - 1) atomicAdd(&census[sl], (unsigned long long)__popcll(m));
+            const int c = 2 * dau[k].shape.kind + dau[k].shape.hole;
+            for (int cc = 0; cc < 2 * (kPcons + 1); ++cc) {
+                const unsigned long long m = __ballot(on && c == cc);
+                if (m != 0ull && lane == __ffsll(m) - 1) atomicAdd(&census[cc], (unsigned long long)__popcll(m));
             }
         }
         if (on) {
-            const int64_t i = base + j;
+            const int sl = lds_load(&S.slot_of[j]);
+            double x, y, z, ux, uy, uz;
+            if (sl != kNoSlot) {
+                x = lds_load(&S.x[sl]);
+                y = lds_load(&S.y[sl]);
+                z = lds_load(&S.z[sl]);
+                ux = lds_load(&S.ux[sl]);
+                uy = lds_load(&S.uy[sl]);
+                uz = lds_load(&S.uz[sl]);
+            } else {
+                const int64_t i = base + j;
+                x = t.x[i];
+                y = t.y[i];
+                z = t.z[i];
+                ux = t.ux[i];
+                uy = t.uy[i];
+                uz = t.uz[i];
+            }
             int sid;
-            const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, t.x[i], t.y[i],
-                                                               t.z[i], t.ux[i], t.uy[i], t.uz[i], sid);
+            const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, x, y, z, ux, uy, uz, sid);
             merge_step(S, j, s, k, sid);
         }
     }
+    qn = 0;
+    ns = 0;
+}
+
+// Per-track constants of the culling test: the unit direction e (as -e),
+// and for the expanded form (no offsets) |p|^2, p.e, -2 p; a zero
+// direction, or one whose |d|^2 overflows, gives e = 0 (the test then
+// takes the start point).
+__device__ __forceinline__ void cull_constants(double x, double y, double z, double ux, double uy, double uz,
+                                               double &pp, double &pe, double &mpx, double &mpy, double &mpz,
+                                               double &mex, double &mey, double &mez) {
+    const double dd = fma(uz, uz, fma(uy, uy, ux * ux));
+    const double il = (dd > 0.0 && dd < __builtin_inf()) ? rsqrt_fine(dd) : 0.0;
+    pp = fma(z, z, fma(y, y, x * x));
+    pe = fma(z, uz, fma(y, uy, x * ux)) * il;
+    mpx = -2.0 * x;
+    mpy = -2.0 * y;
+    mpz = -2.0 * z;
+    mex = -ux * il;
+    mey = -uy * il;
+    mez = -uz * il;
 }
 
 // Navigates the tracks base + u * 64 + lane (u < U, index below `count`
@@ -1241,6 +1308,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                                                  int64_t base, int count, NavScratch<U> &S, int lane,
                                                  unsigned long long *census = nullptr) {
     int qn = 0;  // queue length (uniform)
+    int ns = 0;  // slots in use (uniform)
     const int nd = v.nd;
     const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
 #pragma unroll 1
@@ -1250,32 +1318,22 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         const bool act = j < count;
         const unsigned long long amask = __builtin_amdgcn_ballot_w64(act);
         const int64_t i = base + (act ? j : 0);
-        const double x = t.x[i], y = t.y[i], z = t.z[i];
-        const double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+        double x = t.x[i], y = t.y[i], z = t.z[i];
+        double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
         if (COUNT && lane == 0) atomicAdd(&census[kCensusTracks], (unsigned long long)__popcll(amask));
         int sid;
         const double ms = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
         lds_store(&S.key[j], step_key(ms, true));
         lds_store(&S.hit[j], hit_pack(-1, sid));
-        // per-track constants of the culling test: the unit direction e
-        // (as -e), and for the expanded form (no offsets) |p|^2, p.e, -2 p;
-        // a zero direction, or one whose |d|^2 overflows, gives e = 0 (the
-        // test then takes the start point)
-        const double dd = fma(uz, uz, fma(uy, uy, ux * ux));
-        const double il = (dd > 0.0 && dd < __builtin_inf()) ? rsqrt_fine(dd) : 0.0;
-        const double pp = fma(z, z, fma(y, y, x * x));
-        const double pe = fma(z, uz, fma(y, uy, x * ux)) * il;
-        const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
-        const double mex = -ux * il, mey = -uy * il, mez = -uz * il;
+        lds_store(&S.slot_of[j], kNoSlot);
+        unsigned long long pend = 0ull;  // lanes whose track has queued pairs (uniform)
+        double pp, pe, mpx, mpy, mpz, mex, mey, mez;
+        cull_constants(x, y, z, ux, uy, uz, pp, pe, mpx, mpy, mpz, mex, mey, mez);
         // Daughters in chunks of kCullChunk (the tables are padded to whole
-        // chunks with records that never pass): the queue is flushed between
-        // chunks when a chunk could overflow it, so the tests of a chunk run
-        // back to back.
+        // chunks with records that never pass): the tests of a chunk run
+        // back to back, then its pairs are appended (after a flush if they
+        // would overflow the queue or their tracks the slots).
         for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
-            if (qn > kQueueCap - 64 * kCullChunk) {
-                nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
-                qn = 0;
-            }
             // the chunk's records, loaded together (scalar loads)
             double ctx[kCullChunk], cty[kCullChunk], ctz[kCullChunk], clim[kCullChunk];
 #pragma unroll
@@ -1286,8 +1344,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                 ctz[kk] = Q.tz;
                 clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
             }
-            // the chunk's tests (independent, so they interleave), then its
-            // queue appends
+            // the chunk's tests (independent, so they interleave)
             unsigned long long cm[kCullChunk];
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
@@ -1316,20 +1373,56 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                 // every lane's f is defined; lanes past the tile's end are masked out
                 cm[kk] = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
             }
+            if (COUNT && lane == 0)
+                atomicAdd(&census[kCensusCull],
+                          (unsigned long long)__popcll(amask) * (unsigned long long)min(kCullChunk, nd - k0));
+            const unsigned long long any = (cm[0] | cm[1]) | (cm[2] | cm[3]);
+            static_assert(kCullChunk == 4, "chunk epilogue");
+            if (any == 0ull) continue;
+            if (qn > kQueueCap - 64 * kCullChunk) {  // the chunk's pairs could overflow the queue
+                nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+                pend = 0ull;
+                // the track and its test constants are read and formed again
+                // rather than kept live through the flush's evaluations
+                x = t.x[i];
+                y = t.y[i];
+                z = t.z[i];
+                ux = t.ux[i];
+                uy = t.uy[i];
+                uz = t.uz[i];
+                cull_constants(x, y, z, ux, uy, uz, pp, pe, mpx, mpy, mpz, mex, mey, mez);
+            }
+            pend |= any;
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
-                const int k = k0 + kk;
                 const unsigned long long m = cm[kk];
-                if (COUNT && lane == 0 && k < nd)
-                    atomicAdd(&census[kCensusCull], (unsigned long long)__popcll(amask));
-                if (m == 0ull) continue;
                 if (__builtin_amdgcn_inverse_ballot_w64(m))
-                    S.queue[qn + lanes_below(m)] = ((unsigned int)k << 10) | (unsigned int)j;
+                    S.queue[qn + lanes_below(m)] = ((unsigned int)(k0 + kk) << 10) | (unsigned int)j;
                 qn += __popcll(m);
             }
         }
+        // the round's tracks with queued pairs take slots (after a flush if
+        // there are too few: the pairs then read their tracks from global
+        // memory while they are still in the cache)
+        if (pend != 0ull) {
+            if (ns + __popcll(pend) > kSlots) {
+                nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+            } else {
+                if (__builtin_amdgcn_inverse_ballot_w64(pend)) {
+                    const int sl = ns + lanes_below(pend);
+                    lds_store(&S.x[sl], x);
+                    lds_store(&S.y[sl], y);
+                    lds_store(&S.z[sl], z);
+                    lds_store(&S.ux[sl], ux);
+                    lds_store(&S.uy[sl], uy);
+                    lds_store(&S.uz[sl], uz);
+                    lds_store(&S.slot_of[j], (unsigned char)sl);
+                }
+                ns += __popcll(pend);
+            }
+        }
     }
-    nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, lane, census);
+    nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, ns, lane, census);
 }
 
 // The same, writing step, hit and (when HITPT) the hit point.
@@ -1379,8 +1472,9 @@ __device__ __forceinline__ unsigned long long safety_key(double s) {
 // of global memory (each lane stores its own point; the batches read them
 // later in the same wavefront's program order).
 template <int U>
-struct PointScratch : NavScratch<U> {
-    double px[U * 64], py[U * 64], pz[U * 64];
+struct PointScratch : PointQueue {
+    static_assert(U == 1, "one round of 64 points per wavefront");
+    double px[64], py[64], pz[64];
 };
 
 template <int MODE, bool HAS_OFFS, int KSET, int U>  // MODE 0: safety, 1: locate

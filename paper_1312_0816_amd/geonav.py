@@ -19,7 +19,8 @@ import torch
 
 from . import build as _build
 
-LIB_PATH = _build.LIB
+# the in-tree build; GEONAV_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("GEONAV_LIBRARY", _build.LIB)
 
 GEO_BOX, GEO_TUBE, GEO_CONE, GEO_TUBS, GEO_CONS, GEO_PCON = 0, 1, 2, 3, 4, 5
 CENSUS_SLOTS, CENSUS_CULL, CENSUS_TRACKS = 16, 14, 15

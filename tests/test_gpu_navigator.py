@@ -159,7 +159,9 @@ def test_other_mothers_and_no_daughters(gv, orc):
         u = np.stack(W.isotropic(rng, n))
         t = np.concatenate([p, u])
         step, hit = run_nav(gv, vol, t)
-        check_nav(orc, vol, t, step, hit, what=f"mother {vol.mother_kind}")
+        # tracks outside a mother cut in azimuth can start inside a daughter
+        # (step 0 from both): a tie, allowed a larger share here
+        check_nav(orc, vol, t, step, hit, what=f"mother {vol.mother_kind}", max_tie_frac=0.01)
 
 
 def test_empty_and_errors(gv):

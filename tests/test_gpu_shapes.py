@@ -231,9 +231,13 @@ def test_tracks_aimed_at_edges(gv, orc, kind):
     ill-conditioned unless they merely touch the solid (a line through an
     edge of a convex solid from outside does so about half the time, and
     more often at a segment's face edges). The exempt tracks are still
-    checked: a line that touches the closed solid at the aimed edge point q
-    is a hit at most at |q - o| or a miss, and where both sides report a hit
-    they agree to 1e-9."""
+    checked: such a line touches the closed solid at the aimed edge point q,
+    a hit or a miss by rounding, so the GPU's distance must be the oracle's,
+    or the distance |q - o| to q itself, or the line's next entry after q
+    (the oracle's distance from just past q, plus that offset), or a miss
+    when there is no next entry; compared to 1e-7 relative (through a
+    nappe's apex the touch is a double root of its quadratic, resolved to
+    about the square root of the rounding unit)."""
     rng = np.random.default_rng(61 + kind)
     par = W.SUITE_SHAPES[kind]
     m = 6000
@@ -248,9 +252,19 @@ def test_tracks_aimed_at_edges(gv, orc, kind):
     ref, ill = ill_conditioned(lambda x: orc.dist_out(kind, par, x, "d"),
                                lambda x: orc.dist_out(kind, par, x, "ld"), t)
     ex = np.asarray(ill, bool)
+    te = np.ascontiguousarray(t[:, ex])
     g, r, lim = got[ex], ref[ex], tq[ex]
-    assert np.all((g == BIG) | (g <= lim * (1 + 1e-9) + 1e-9)), "a hit beyond the aimed edge point"
-    both = (g < BIG) & (r < BIG)
-    assert np.all(np.abs(g[both] - r[both]) <= 1e-9 * np.maximum(np.abs(r[both]), 1.0))
-    print(f"{W.KIND_NAMES[kind]} edges: {int(ex.sum())} exempt DistFromOutside, {int(both.sum())} hits on "
-          f"both sides, {int(((g == BIG) != (r == BIG)).sum())} hit/miss flips")
+    eps = 1e-6
+    after = orc.dist_out(kind, par, np.ascontiguousarray(np.concatenate([te[:3] + (lim + eps) * te[3:], te[3:]])),
+                         "ld")
+    nxt = np.where(after >= BIG, BIG, lim + eps + after)
+
+    def close(a, b):
+        return np.abs(a - b) <= 1e-7 * np.maximum(np.abs(b), 1.0)
+
+    ok = close(g, r) | close(g, lim) | close(g, nxt) | ((g >= BIG) & (nxt >= BIG))
+    assert ok.all(), (f"{int((~ok).sum())} exempt tracks off every valid answer: gpu, oracle, |q - o|, next "
+                      f"entry = {list(zip(g[~ok][:3], r[~ok][:3], lim[~ok][:3], nxt[~ok][:3]))}")
+    print(f"{W.KIND_NAMES[kind]} edges: {int(ex.sum())} exempt DistFromOutside: {int(close(g, r).sum())} "
+          f"equal to the oracle, {int((close(g, lim) & ~close(g, r)).sum())} at the touch point, "
+          f"{int((~close(g, r) & ~close(g, lim)).sum())} at the next entry or a miss")
