@@ -203,6 +203,21 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
                           const double *gstep, const double *ghit, double *g_o, double *g_d,
                           double *g_off, hipStream_t stream);
 
+/* geo_navigate_backward for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same arguments, kernels and results (bit for bit), but the partial sums of
+ * the offset gradient live in a static device buffer of the library (3 MiB,
+ * one per GPU, held until the process ends) instead of the handle's, and
+ * the call allocates nothing. The buffer holds 2048 * 3 * 64 doubles: any
+ * track count with up to 64 daughters; with more, a call whose partial sums
+ * (min(ceil(n / 256), 2048) rows of 3 * ndaughters) do not fit fails with
+ * GEO_ERR_INVALID_ARG before launching anything. Every call on one GPU shares
+ * that GPU's buffer (nothing in it needs to start at zero): calls that
+ * overlap on one GPU (concurrent streams, host threads) race; order them. */
+int geo_navigate_backward_noalloc(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                                  const double *gstep, const double *ghit, double *g_o, double *g_d,
+                                  double *g_off, hipStream_t stream);
+
 /* Instrumented run of geo_navigate_batched (same outputs, not for timing):
  * launches directly (no graph) a variant of the batched kernel that tallies
  * the work it does. counts (host uint64_t[GEO_CENSUS_SLOTS]):

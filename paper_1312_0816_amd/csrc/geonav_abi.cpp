@@ -625,6 +625,40 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
     return GEO_OK;
 }
 
+int geo_navigate_backward_noalloc(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
+                                  const double *gstep, const double *ghit, double *g_o, double *g_d,
+                                  double *g_off, hipStream_t stream) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (volume < 0 || volume >= g->nvol) return fail(GEO_ERR_INVALID_ARG, "volume %d out of range", volume);
+    int rc = check_tracks(t, true, "tracks");
+    if (rc) return rc;
+    if ((rc = check_opt(offsets, 8, "offsets")) || (rc = check_opt(gstep, 8, "gstep")) ||
+        (rc = check_opt(ghit, 8, "ghit")) || (rc = check_opt(g_o, 8, "g_o")) ||
+        (rc = check_opt(g_d, 8, "g_d")) || (rc = check_opt(g_off, 8, "g_off")))
+        return rc;
+    const int nd = g->h_vols[volume].nd;
+    if (t.n == 0 && !(g_off && nd > 0)) return GEO_OK;
+    if ((rc = check_device(g))) return rc;
+    double *part = nullptr;
+    if (g_off && nd > 0) {
+        const size_t need = (size_t)backward_blocks(t.n) * 3 * (size_t)nd;
+        if (need > kScratchDoubles)
+            return fail(GEO_ERR_INVALID_ARG,
+                        "geo_navigate_backward_noalloc: %d daughters over %lld tracks need %zu partial sums, "
+                        "the static buffer holds %zu (%d daughters at any track count)",
+                        nd, (long long)t.n, need, kScratchDoubles, (int)(kScratchDoubles / (3 * kBackwardMaxBlocks)));
+        hipError_t e = scratch_partials(&part);
+        if (e != hipSuccess) return hip_fail(e, "static partial-sum buffer");
+    }
+    const int first = g->h_vols[volume].first;
+    hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
+                                   g->d_cull ? g->d_cull + first : nullptr, nd, to_dev(t),
+                                   nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, part,
+                                   nd > 0 ? g_off : nullptr, g->cull, g->vol_kset[volume], stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return GEO_OK;
+}
+
 namespace {
 
 int point_call_checks(const geo_geometry *g, int32_t volume, const geo_tracks &t, const double *offsets,

@@ -75,6 +75,16 @@ const void *build_tiles_kernel();
 // one wavefront per tile (waves_per_simd == 0).
 int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles);
 
+// Workgroups of an adjoint launch over n tracks (each writes one row of
+// 3 * nd partial sums of the offset gradient).
+int backward_blocks(int64_t n);
+
+// The static partial-sum buffer of the allocation-free adjoint: doubles it
+// holds, and its device address on the current device (looked up once per
+// device).
+constexpr size_t kScratchDoubles = (size_t)kBackwardMaxBlocks * 3 * 64;  // 3 MiB
+hipError_t scratch_partials(double **out);
+
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,

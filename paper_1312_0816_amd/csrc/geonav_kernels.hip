@@ -17,6 +17,8 @@
 //                    gradient of the surface that set the step) with
 //                    per-workgroup partial sums of the offset gradient;
 //  k_reduce_partials fixed-order reduction of those partials.
+#include <mutex>
+
 #include "geonav_internal.hpp"
 
 namespace gn {
@@ -628,12 +630,16 @@ static void launch_backward_variant(int nblocks, int nd, const VolumeRec *vol, c
                            offs, gstep, ghit, g_o, g_d, part);
 }
 
+int backward_blocks(int64_t n) {
+    const int64_t need = (n + kBlock - 1) / kBlock;
+    return (int)(need < kBackwardMaxBlocks ? (need > 0 ? need : 1) : kBackwardMaxBlocks);
+}
+
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
                            double *g_off, bool cull, int kset, hipStream_t st) {
-    const int64_t need = (t.n + kBlock - 1) / kBlock;
-    const int nblocks = (int)(need < kBackwardMaxBlocks ? (need > 0 ? need : 1) : kBackwardMaxBlocks);
+    const int nblocks = backward_blocks(t.n);
     double *part = (g_off && nd > 0) ? partial : nullptr;
     if (t.n > 0 || part) {
         if (cull)
@@ -650,6 +656,38 @@ hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const C
                            g_off);
         return hipGetLastError();
     }
+    return hipSuccess;
+}
+
+// ------------------------------------------------ allocation-free adjoint
+// The offset gradient's per-workgroup partial sums for the adjoint entry
+// point that allocates nothing: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends. In host code the name
+// `scratch` is a host-side stand-in, not a device address: host code uses
+// only the address hipGetSymbolAddress returns for the current device,
+// looked up at the first call on each device and kept.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_partials(double **out) {
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return hipSuccess;
 }
 

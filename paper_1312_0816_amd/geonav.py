@@ -68,7 +68,8 @@ EXPORTS = ("geo_geometry_create", "geo_geometry_destroy", "geo_shape_query",
            "geo_navigate_basket", "geo_navigate_batched", "geo_navigate_backward",
            "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_set_culling",
            "geo_get_culling", "geo_navigate_batched_census", "geo_navigate_safety",
-           "geo_locate", "geo_set_kernel_timing", "geo_batched_kernel_ms", "geo_strerror")
+           "geo_locate", "geo_set_kernel_timing", "geo_batched_kernel_ms", "geo_navigate_backward_noalloc",
+           "geo_strerror")
 
 _lib = None
 
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib.geo_navigate_basket.argtypes = [P, I32, GeoTracks, P, P, P, P, P]
     lib.geo_navigate_batched.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P, P, P]
     lib.geo_navigate_backward.argtypes = [P, I32, GeoTracks, P, P, P, P, P, P, P]
+    lib.geo_navigate_backward_noalloc.argtypes = [P, I32, GeoTracks, P, P, P, P, P, P, P]
     lib.geo_autotune.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P]
     lib.geo_get_launch_config.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     lib.geo_set_launch_config.argtypes = [P, I32, I32]
@@ -389,6 +391,24 @@ def geo_navigate_backward(g: Geometry, volume: int, o: torch.Tensor, d: torch.Te
     if want_off and nd == 0:
         g_off = torch.zeros((0, 3), dtype=torch.float64, device=dev)
     return g_o, g_d, g_off
+
+
+def geo_navigate_backward_noalloc(g: Geometry, volume: int, o: torch.Tensor, d: torch.Tensor,
+                                  offsets: torch.Tensor | None, gstep: torch.Tensor | None,
+                                  ghit: torch.Tensor | None, g_o: torch.Tensor | None, g_d: torch.Tensor | None,
+                                  g_off: torch.Tensor | None, stream=None):
+    """geo_navigate_backward into caller-provided outputs (None to skip):
+    g_o, g_d (3, n) and g_off (nd, 3) float64 on the tracks' device. Neither
+    this wrapper nor the library allocates anything."""
+    t = tracks_struct(o, d)
+    n = t.n
+    nd = g.nd[volume]
+    for name, x, shape in (("offsets", offsets, (nd, 3)), ("gstep", gstep, (n,)), ("ghit", ghit, (3, n)),
+                           ("g_o", g_o, (3, n)), ("g_d", g_d, (3, n)), ("g_off", g_off, (nd, 3))):
+        if x is not None:
+            _need(x, name, shape)
+    _check(g._lib.geo_navigate_backward_noalloc(g.handle, int(volume), t, _ptr(offsets), _ptr(gstep), _ptr(ghit),
+                                                _ptr(g_o), _ptr(g_d), _ptr(g_off), _stream(stream)))
 
 
 class Navigate(torch.autograd.Function):
