@@ -144,11 +144,11 @@ static void launch_basket_variant(dim3 grid, const VolumeRec *vol, const Daughte
 }
 
 // Baskets of at least kBasketWide tracks run 4 rounds per wavefront (still
-// about 4096 wavefronts, several per SIMD), or 8 when the volume holds every
-// kind (each batch of queued pairs then runs five kinds' code in turn, and
-// fuller batches pay for it fewer times: 5 % on a 2^22-track basket of the
-// mixed detector, none on the box/tube/cone toy detector); smaller baskets
-// one round.
+// about 4096 wavefronts, several per SIMD); smaller baskets one round. (8
+// rounds when the volume holds every kind, which fills each batch of queued
+// pairs better, gave 5 % with the running minima in LDS alone; with the
+// track cache beside them its LDS allows 3 wavefronts per SIMD instead of
+// 5: 162 against 141 us on a 2^22-track basket of the mixed detector.)
 constexpr int64_t kBasketWide = (int64_t)1 << 20;
 
 hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul,
@@ -156,10 +156,7 @@ hipError_t launch_nav_basket(const VolumeRec *vol, const DaughterRec *dau, const
                              double *hitpt, bool cull, int kset, hipStream_t st) {
     if (t.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((t.n + kBlock - 1) / kBlock));
-    if (cull && t.n >= kBasketWide && kset == kSetAll) {
-        const dim3 grid8((unsigned)((t.n + 8 * kBlock - 1) / (8 * kBlock)));
-        launch_basket_variant<true, kSetAll, 8>(grid8, vol, dau, cul, t, offs, step, hit, hitpt, st);
-    } else if (cull && t.n >= kBasketWide) {
+    if (cull && t.n >= kBasketWide) {
         const dim3 grid4((unsigned)((t.n + 4 * kBlock - 1) / (4 * kBlock)));
         GN_KSET(kset, (launch_basket_variant<true, KS, 4>(grid4, vol, dau, cul, t, offs, step, hit, hitpt, st)));
     } else if (cull) {

@@ -294,7 +294,7 @@ def test_direction_length_over_the_supported_range(gv, orc, mixed):
 @pytest.mark.parametrize("with_offsets", [False, True])
 def test_wide_basket_of_every_kind(gv, orc, with_offsets):
     """A basket of 2^20 + 37 tracks in a volume holding every kind (the wide
-    compacted form, 8 rounds of 64 tracks per wavefront): culled and
+    compacted form, 4 rounds of 64 tracks per wavefront): culled and
     sequential paths agree bit for bit, hit points included, with and
     without offsets; a sample matches the oracle."""
     vol = W.mixed_detector_volume()
