@@ -1329,6 +1329,9 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         unsigned long long pend = 0ull;  // lanes whose track has queued pairs (uniform)
         double pp, pe, mpx, mpy, mpz, mex, mey, mez;
         cull_constants(x, y, z, ux, uy, uz, pp, pe, mpx, mpy, mpz, mex, mey, mez);
+        // a lane past the tile's end gets |p|^2 = +inf: its expanded tests
+        // never pass, so their ballots need no mask
+        if (!act) pp = __builtin_inf();
         // Daughters in chunks of kCullChunk (the tables are padded to whole
         // chunks with records that never pass): the tests of a chunk run
         // back to back, then its pairs are appended (after a flush if they
@@ -1370,8 +1373,10 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                 // (w.e < 0), else |w|^2
                 const double bn = fmin(b, 0.0);
                 const double f = fma(-bn, bn, g);
-                // every lane's f is defined; lanes past the tile's end are masked out
-                cm[kk] = __builtin_amdgcn_ballot_w64(f <= lim) & amask;
+                // lanes past the tile's end are masked out (the expanded form
+                // excludes them through |p|^2)
+                const unsigned long long pass = __builtin_amdgcn_ballot_w64(f <= lim);
+                cm[kk] = HAS_OFFS ? (pass & amask) : pass;
             }
             if (COUNT && lane == 0)
                 atomicAdd(&census[kCensusCull],
@@ -1391,6 +1396,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
                 uy = t.uy[i];
                 uz = t.uz[i];
                 cull_constants(x, y, z, ux, uy, uz, pp, pe, mpx, mpy, mpz, mex, mey, mez);
+                if (!act) pp = __builtin_inf();
             }
             pend |= any;
 #pragma unroll
