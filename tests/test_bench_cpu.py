@@ -36,15 +36,32 @@ def test_traffic_is_read_only_for_the_profiled_source_and_shape(tmp_path, monkey
     assert bench.read_traffic("abcdef0123456789", "4,0") is None
 
 
-def test_committed_summary_names_a_digest_and_both_shapes():
+def test_committed_summary_names_a_digest_and_the_default_shape():
     path = os.path.join(ROOT, "profiles", "k_nav_tiles_batched512.md")
     lines = [ln.split() for ln in open(path) if ln.startswith("traffic:")]
     shapes = {dict(kv.split("=", 1) for kv in ln[1:])["launch"] for ln in lines}
-    assert {"4,0", "2,0"} <= shapes
+    assert "4,0" in shapes                                        # the autotuned launch shape
     for ln in lines:
         vals = dict(kv.split("=", 1) for kv in ln[1:])
         assert len(vals["kernel_source"]) == 16
         assert 255e6 < float(vals["bytes_per_launch"]) < 1e9   # at least the algorithmic 255.5 MB
+    valu = [dict(kv.split("=", 1) for kv in ln.split()[1:]) for ln in open(path) if ln.startswith("valu:")]
+    assert {v["launch"] for v in valu} >= {"4,0", "4,0,nocull"}
+    for v in valu:
+        assert 0 < float(v["f64_per_launch"]) < float(v["valu_per_launch"])
+
+
+def test_profile_figures_are_read_for_their_source_only(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "k_nav_tiles_batched512.md").write_text(
+        "valu: kernel_source=abcdef0123456789 launch=4,0 valu_per_launch=100 f64_per_launch=40\n"
+        "valu: kernel_source=abcdef0123456789 launch=4,0,nocull valu_per_launch=900 f64_per_launch=500\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.read_profile("valu", "abcdef0123456789", "4,0", "f64_per_launch") == 40
+    assert bench.read_profile("valu", "abcdef0123456789", "4,0,nocull", "valu_per_launch") == 900
+    assert bench.read_profile("valu", "abcdef0123456789", "2,0", "f64_per_launch") is None
+    assert bench.read_profile("valu", "0" * 16, "4,0", "f64_per_launch") is None
+    assert bench.read_profile("traffic", "abcdef0123456789", "4,0", "bytes_per_launch") is None
 
 
 def test_digest_ignores_comments_and_layout_only(tmp_path, monkeypatch):
