@@ -266,6 +266,20 @@ __device__ __forceinline__ double box_dist_out(const double *c, double x, double
 }
 
 // Leaving: the first face the line reaches on each axis.
+// The same distance without the surface that sets it, for callers that only
+// need the value: the three exits taken with fmin, which skips the NaN of an
+// axis the direction does not move along (fdiv by 0); the result equals
+// box_dist_in's bit for bit (the smallest exit below kBig, else kBig; 0
+// outside).
+__device__ __forceinline__ double box_exit(const double *c, double x, double y, double z, double ux,
+                                           double uy, double uz) {
+    const double tx = fdiv(c[0] - (ux > 0.0 ? x : -x), fabs(ux));
+    const double ty = fdiv(c[1] - (uy > 0.0 ? y : -y), fabs(uy));
+    const double tz = fdiv(c[2] - (uz > 0.0 ? z : -z), fabs(uz));
+    const double best = fmin(kBig, fmin(tx, fmin(ty, tz)));
+    return box_contains(c, x, y, z) ? best : 0.0;
+}
+
 __device__ __forceinline__ double box_dist_in(const double *c, double x, double y, double z,
                                               double ux, double uy, double uz, int &sid) {
     const bool inside = box_contains(c, x, y, z);
@@ -988,6 +1002,18 @@ __device__ __forceinline__ double any_dist_in(const ShapeRec &s, const PconRec *
 }
 #undef GN_KIND_SWITCH
 
+// The mother's DistFromInside for the navigators; SURF false: the surface
+// that sets it is not wanted (sid = -1), and a box mother takes box_exit.
+template <bool SURF, int KSET>
+__device__ __forceinline__ double mother_step(const VolumeRec &v, double x, double y, double z, double ux,
+                                              double uy, double uz, int &sid) {
+    if (!SURF && v.mother.kind == kBox) {
+        sid = -1;
+        return box_exit(v.mother.c, x, y, z, ux, uy, uz);
+    }
+    return any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
+}
+
 // Outward-or-inward normal (any scale/sign) of surface `sid` at local point h.
 __device__ __forceinline__ void surface_normal(const ShapeRec &s, const PconRec *pc, int sid,
                                                double hx, double hy, double hz, double &nx,
@@ -1055,7 +1081,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
                                           unsigned long long *census = nullptr) {
     int sid;
     if (COUNT) census_add(census, kCensusTracks);
-    best = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
+    best = mother_step<TRACK_SURF, KSET>(v, x, y, z, ux, uy, uz, sid);
     hit = -1;
     bsid = sid;
     const int nd = v.nd;
@@ -1232,7 +1258,7 @@ __device__ __forceinline__ void merge_step(Scratch &S, int j, double s, int k, i
 // reading its track from its slot, or from global memory if the track has
 // none (pairs flushed within their own round), then empties the queue and
 // the slots.
-template <int U, bool HAS_OFFS, bool COUNT, int KSET>
+template <int U, bool HAS_OFFS, bool COUNT, int KSET, bool SURF>
 __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
                                           const CullRec *__restrict__ cul,
                                           const double *__restrict__ offs, const TracksDev &t,
@@ -1272,7 +1298,7 @@ __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
             }
             int sid;
             const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, x, y, z, ux, uy, uz, sid);
-            merge_step(S, j, s, k, sid);
+            merge_step(S, j, s, k, SURF ? sid : -1);  // (a surface not wanted is not tracked)
         }
     }
     qn = 0;
@@ -1300,8 +1326,9 @@ __device__ __forceinline__ void cull_constants(double x, double y, double z, dou
 
 // Navigates the tracks base + u * 64 + lane (u < U, index below `count`
 // past base) of one volume, leaving each track's step (as a key) and hit
-// index in S.
-template <int U, bool HAS_OFFS, bool COUNT, int KSET>
+// index in S; with SURF, the hit slot also carries the surface that set the
+// step (for the adjoint).
+template <int U, bool HAS_OFFS, bool COUNT, int KSET, bool SURF = true>
 __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                                  const CullRec *__restrict__ cul,
                                                  const double *__restrict__ offs, const TracksDev &t,
@@ -1322,7 +1349,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
         if (COUNT && lane == 0) atomicAdd(&census[kCensusTracks], (unsigned long long)__popcll(amask));
         int sid;
-        const double ms = any_dist_in<KSET>(v.mother, v.pcon, x, y, z, ux, uy, uz, sid);
+        const double ms = mother_step<SURF, KSET>(v, x, y, z, ux, uy, uz, sid);
         lds_store(&S.key[j], step_key(ms, true));
         lds_store(&S.hit[j], hit_pack(-1, sid));
         lds_store(&S.slot_of[j], kNoSlot);
@@ -1385,7 +1412,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
             static_assert(kCullChunk == 4, "chunk epilogue");
             if (any == 0ull) continue;
             if (qn > kQueueCap - 64 * kCullChunk) {  // the chunk's pairs could overflow the queue
-                nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+                nav_flush<U, HAS_OFFS, COUNT, KSET, SURF>(dau, cul, offs, t, base, S, qn, ns, lane, census);
                 pend = 0ull;
                 // the track and its test constants are read and formed again
                 // rather than kept live through the flush's evaluations
@@ -1412,7 +1439,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
         // memory while they are still in the cache)
         if (pend != 0ull) {
             if (ns + __popcll(pend) > kSlots) {
-                nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+                nav_flush<U, HAS_OFFS, COUNT, KSET, SURF>(dau, cul, offs, t, base, S, qn, ns, lane, census);
             } else {
                 if (__builtin_amdgcn_inverse_ballot_w64(pend)) {
                     const int sl = ns + lanes_below(pend);
@@ -1428,7 +1455,7 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
             }
         }
     }
-    nav_flush<U, HAS_OFFS, COUNT, KSET>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+    nav_flush<U, HAS_OFFS, COUNT, KSET, SURF>(dau, cul, offs, t, base, S, qn, ns, lane, census);
 }
 
 // The same, writing step, hit and (when HITPT) the hit point.
@@ -1440,7 +1467,7 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
                                             double *__restrict__ step, int32_t *__restrict__ hit,
                                             double *__restrict__ hitpt,
                                             unsigned long long *census = nullptr) {
-    nav_compact_core<U, HAS_OFFS, COUNT, KSET>(v, dau, cul, offs, t, base, count, S, lane, census);
+    nav_compact_core<U, HAS_OFFS, COUNT, KSET, false>(v, dau, cul, offs, t, base, count, S, lane, census);
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;
