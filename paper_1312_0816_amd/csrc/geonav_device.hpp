@@ -940,16 +940,17 @@ __device__ __forceinline__ double shape_dist_in(const ShapeRec &s, const PconRec
 // loop body stays small, which the instruction cache rewards.
 enum : int { kSetBasic = 0, kSetSeg = 1, kSetAll = 2 };
 
-#define GN_KIND_SWITCH(CALL)                \
+#define GN_KIND_SWITCH(CALL) GN_KIND_SWITCH_ON(s.kind, CALL)
+#define GN_KIND_SWITCH_ON(KIND, CALL)       \
     if (KSET == kSetBasic) {                \
-        switch (s.kind) {                   \
+        switch (KIND) {                     \
             case kBox: return CALL(kBox);   \
             case kTube: return CALL(kTube); \
             default: return CALL(kCone);    \
         }                                   \
     }                                       \
     if (KSET == kSetSeg) {                  \
-        switch (s.kind) {                   \
+        switch (KIND) {                     \
             case kBox: return CALL(kBox);   \
             case kTube: return CALL(kTube); \
             case kCone: return CALL(kCone); \
@@ -957,7 +958,7 @@ enum : int { kSetBasic = 0, kSetSeg = 1, kSetAll = 2 };
             default: return CALL(kCons);    \
         }                                   \
     }                                       \
-    switch (s.kind) {                       \
+    switch (KIND) {                         \
         case kBox: return CALL(kBox);       \
         case kTube: return CALL(kTube);     \
         case kCone: return CALL(kCone);     \
@@ -1000,7 +1001,30 @@ __device__ __forceinline__ double any_dist_in(const ShapeRec &s, const PconRec *
     GN_KIND_SWITCH(GN_CALL)
 #undef GN_CALL
 }
+
+// Number of kind classes a kind set tells apart (kinds beyond them take the
+// last class's code, as in the switch above), and the class of a kind.
+template <int KSET>
+__device__ __forceinline__ constexpr int kind_classes() {
+    return KSET == kSetBasic ? 3 : (KSET == kSetSeg ? 5 : 7);
+}
+template <int KSET>
+__device__ __forceinline__ int kind_class(int kind) {
+    return kind < kind_classes<KSET>() - 1 ? kind : kind_classes<KSET>() - 1;
+}
+
+// DistFromOutside for a class known to be uniform over the wavefront (a
+// scalar branch instead of one path per kind present).
+template <int KSET>
+__device__ __forceinline__ double class_dist_out(int cls, const ShapeRec &s, const PconRec *pc, double x,
+                                                 double y, double z, double ux, double uy, double uz,
+                                                 int &sid) {
+#define GN_CALL(K) shape_dist_out<K>(s, pc, x, y, z, ux, uy, uz, sid)
+    GN_KIND_SWITCH_ON(cls, GN_CALL)
+#undef GN_CALL
+}
 #undef GN_KIND_SWITCH
+#undef GN_KIND_SWITCH_ON
 
 // The mother's DistFromInside for the navigators; SURF false: the surface
 // that sets it is not wanted (sid = -1), and a box mother takes box_exit.
@@ -1159,6 +1183,7 @@ __device__ __forceinline__ void nav_track(const VolumeRec &v, const DaughterRec 
 // queue, the slots and the minima is the wavefront's own, whose LDS
 // instructions execute in program order, so no barrier is needed.
 constexpr int kQueueCap = 512;
+constexpr int kPoolMax = 128;
 constexpr int kSlots = 48;
 constexpr unsigned char kNoSlot = 255;
 template <int U>
@@ -1167,8 +1192,16 @@ struct NavScratch {
     int hit[U * 64];                  // and the packed index of its candidate
     unsigned char slot_of[U * 64];    // the track's slot, kNoSlot if none
     double x[kSlots], y[kSlots], z[kSlots], ux[kSlots], uy[kSlots], uz[kSlots];
-    unsigned int queue[kQueueCap];    // (daughter << 10) | round * 64 + lane
+    union {
+        unsigned int queue[kQueueCap];  // (daughter << 10) | round * 64 + lane
+        struct {                        // a pooled flush of at most kPoolMax pairs:
+            unsigned int entry[kPoolMax];          // the queue's entries
+            unsigned long long key[kPoolMax];      // each pair's step key
+            int hit[kPoolMax];                     // and packed hit
+        } pooled;
+    };
     static_assert(U * 64 <= 1024, "track index within the tile: 10 bits");
+    static_assert(sizeof(pooled) <= sizeof(queue), "pooled results within the queue");
 };
 static_assert(kSlots < kNoSlot, "slot numbers");
 
@@ -1210,12 +1243,13 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 }
 
 // DistFromOutside of daughter k (records D, Q) for a mother-frame track;
-// sid receives the surface that set it.
+// sid receives the surface that set it. With a class cls >= 0 (uniform over
+// the wavefront), the daughter is known to be of that kind class.
 template <bool HAS_OFFS, int KSET>
 __device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const CullRec &Q,
                                                     const double *__restrict__ offs, int k, double x,
                                                     double y, double z, double ux, double uy,
-                                                    double uz, int &sid) {
+                                                    double uz, int &sid, int cls = -1) {
     double wx = x - Q.tx, wy = y - Q.ty, wz = z - Q.tz;
     if (HAS_OFFS) {
         wx -= offs[3 * k + 0];
@@ -1229,6 +1263,7 @@ __device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const 
     const double lux = fma(R[6], uz, fma(R[3], uy, R[0] * ux));
     const double luy = fma(R[7], uz, fma(R[4], uy, R[1] * ux));
     const double luz = fma(R[8], uz, fma(R[5], uy, R[2] * ux));
+    if (cls >= 0) return class_dist_out<KSET>(cls, D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
     return any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
 }
 
@@ -1240,18 +1275,21 @@ __device__ __forceinline__ int hit_pack(int k, int sid) { return k * 256 + (sid 
 __device__ __forceinline__ int hit_index(int v) { return v >> 8; }
 __device__ __forceinline__ int hit_surface(int v) { return (v & 255) - 1; }
 
-// Merges candidate (s, k) with surface sid into running minimum j of S.
-// Lanes of one call may share a minimum; whatever the order of calls, it
-// ends at the lexicographic minimum of all candidates merged.
+// Merges a candidate (its step's key and packed hit) into running minimum j
+// of S, the wavefront's own. Lanes of one call may share a minimum; whatever
+// the order of calls, it ends at the lexicographic minimum of all candidates
+// merged. merge_step: the same for candidate (s, k) with surface sid.
 template <typename Scratch>
-__device__ __forceinline__ void merge_step(Scratch &S, int j, double s, int k, int sid) {
-    const unsigned long long key = step_key(s);
+__device__ __forceinline__ void merge_key(Scratch &S, int j, unsigned long long key, int hp) {
     const unsigned long long before = lds_load(&S.key[j]);
     __hip_atomic_fetch_min(&S.key[j], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     const unsigned long long now = lds_load(&S.key[j]);
     if (now < before) lds_store(&S.hit[j], 0x7fffffff);
-    if (key == now)
-        __hip_atomic_fetch_min(&S.hit[j], hit_pack(k, sid), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (key == now) __hip_atomic_fetch_min(&S.hit[j], hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+template <typename Scratch>
+__device__ __forceinline__ void merge_step(Scratch &S, int j, double s, int k, int sid) {
+    merge_key(S, j, step_key(s), hit_pack(k, sid));
 }
 
 // Runs the qn queued pairs in batches of 64 (one pair per lane), each
@@ -1328,12 +1366,15 @@ __device__ __forceinline__ void cull_constants(double x, double y, double z, dou
 // past base) of one volume, leaving each track's step (as a key) and hit
 // index in S; with SURF, the hit slot also carries the surface that set the
 // step (for the adjoint).
-template <int U, bool HAS_OFFS, bool COUNT, int KSET, bool SURF = true>
-__device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const DaughterRec *__restrict__ dau,
-                                                 const CullRec *__restrict__ cul,
-                                                 const double *__restrict__ offs, const TracksDev &t,
-                                                 int64_t base, int count, NavScratch<U> &S, int lane,
-                                                 unsigned long long *census = nullptr) {
+//
+// Without FINAL the last flush is left to the caller: the queue's length is
+// returned, its tracks holding slots.
+template <int U, bool HAS_OFFS, bool COUNT, int KSET, bool SURF = true, bool FINAL = true>
+__device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                                const CullRec *__restrict__ cul,
+                                                const double *__restrict__ offs, const TracksDev &t,
+                                                int64_t base, int count, NavScratch<U> &S, int lane,
+                                                unsigned long long *census = nullptr) {
     int qn = 0;  // queue length (uniform)
     int ns = 0;  // slots in use (uniform)
     const int nd = v.nd;
@@ -1455,19 +1496,16 @@ __device__ __forceinline__ void nav_compact_core(const VolumeRec &v, const Daugh
             }
         }
     }
-    nav_flush<U, HAS_OFFS, COUNT, KSET, SURF>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+    if (FINAL) nav_flush<U, HAS_OFFS, COUNT, KSET, SURF>(dau, cul, offs, t, base, S, qn, ns, lane, census);
+    return qn;
 }
 
-// The same, writing step, hit and (when HITPT) the hit point.
-template <int U, bool HAS_OFFS, bool HITPT, bool COUNT, int KSET>
-__device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
-                                            const CullRec *__restrict__ cul,
-                                            const double *__restrict__ offs, const TracksDev &t,
-                                            int64_t base, int count, NavScratch<U> &S, int lane,
-                                            double *__restrict__ step, int32_t *__restrict__ hit,
-                                            double *__restrict__ hitpt,
-                                            unsigned long long *census = nullptr) {
-    nav_compact_core<U, HAS_OFFS, COUNT, KSET, false>(v, dau, cul, offs, t, base, count, S, lane, census);
+// Writes step, hit and (when HITPT) the hit point of the tile's tracks
+// from their running minima.
+template <int U, bool HITPT>
+__device__ __forceinline__ void nav_write(const NavScratch<U> &S, const TracksDev &t, int64_t base,
+                                          int count, int lane, double *__restrict__ step,
+                                          int32_t *__restrict__ hit, double *__restrict__ hitpt) {
 #pragma unroll 1
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;
@@ -1484,6 +1522,189 @@ __device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRe
             }
         }
     }
+}
+
+// The navigator of one wavefront's tile, writing its outputs.
+template <int U, bool HAS_OFFS, bool HITPT, bool COUNT, int KSET>
+__device__ __forceinline__ void nav_compact(const VolumeRec &v, const DaughterRec *__restrict__ dau,
+                                            const CullRec *__restrict__ cul,
+                                            const double *__restrict__ offs, const TracksDev &t,
+                                            int64_t base, int count, NavScratch<U> &S, int lane,
+                                            double *__restrict__ step, int32_t *__restrict__ hit,
+                                            double *__restrict__ hitpt,
+                                            unsigned long long *census = nullptr) {
+    nav_compact_core<U, HAS_OFFS, COUNT, KSET, false>(v, dau, cul, offs, t, base, count, S, lane, census);
+    nav_write<U, HITPT>(S, t, base, count, lane, step, hit, hitpt);
+}
+
+// --------------------------------------------- workgroup-pooled last flush
+// A tile's last flush holds a few dozen pairs (about 0.12 per track on the
+// toy detectors), one batch whose lanes meet every daughter kind the volume
+// holds, so that batch runs each kind's code in turn, each on a few lanes.
+// Instead, the W wavefronts of a workgroup pool their last queues: each
+// sorts its own queue by kind class; after a barrier the workgroup's pairs
+// of each class are cut into batches of 64, and the batches, in class order,
+// are dealt to the wavefronts in turn, so that each batch runs one class's
+// code. A pair's result (key and packed hit) goes back to its place in the
+// owner's queue; after a second barrier each wavefront merges its own
+// queue's results into its running minima, as a flush of its own would.
+// Without `shared` (uniform over the workgroup: its wavefronts' work is too
+// uneven to wait for each other) each wavefront flushes its own queue
+// alone, with no barrier. (Sorting a single wavefront's queue by class
+// saves nothing: its classes still run one after another.)
+constexpr int kClassSlots = 8;
+template <int W>
+struct PoolInfo {
+    int cnt[W][kClassSlots];  // pairs of each kind class in each wavefront's sorted queue
+    int64_t base[W];          // the wavefront's first track
+    int first[W];             // its volume's first daughter and culling record
+};
+
+template <int U, int W, bool HAS_OFFS, int KSET, bool SURF>
+__device__ __forceinline__ void pool_flush(const DaughterRec *__restrict__ dau_all,
+                                           const CullRec *__restrict__ cul_all,
+                                           const double *__restrict__ offs, const TracksDev &t,
+                                           NavScratch<U> *scr, PoolInfo<W> &P, bool shared, int wave,
+                                           int first, int64_t base, int qn, int lane) {
+    constexpr int NK = kind_classes<KSET>();
+    static_assert(NK <= kClassSlots, "class slots");
+    static_assert(kPoolMax == 128, "two entries per lane");
+    wave = __builtin_amdgcn_readfirstlane(wave);  // (uniform: the batch loop runs on scalars)
+    NavScratch<U> &S = scr[wave];
+    if (!shared || qn > kPoolMax) {
+        // a longer queue is run by its wavefront alone
+        int ns = 0;
+        nav_flush<U, HAS_OFFS, false, KSET, SURF>(dau_all + first, cul_all + first, offs, t, base, S, qn,
+                                                 ns, lane, nullptr);
+        if (!shared) return;
+    }
+    // sort the queue by class (stable, in place: both entries are read first)
+    {
+        const bool on0 = lane < qn, on1 = lane + 64 < qn;
+        const unsigned int e0 = on0 ? S.queue[lane] : 0u;
+        const unsigned int e1 = on1 ? S.queue[lane + 64] : 0u;
+        const DaughterRec *dau = dau_all + first;
+        const int c0 = on0 ? kind_class<KSET>(dau[e0 >> 10].shape.kind) : -1;
+        const int c1 = on1 ? kind_class<KSET>(dau[e1 >> 10].shape.kind) : -1;
+        int d0 = 0, d1 = 0, off = 0;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const unsigned long long m0 = __builtin_amdgcn_ballot_w64(c0 == c);
+            const unsigned long long m1 = __builtin_amdgcn_ballot_w64(c1 == c);
+            if (c0 == c) d0 = off + lanes_below(m0);
+            if (c1 == c) d1 = off + __popcll(m0) + lanes_below(m1);
+            const int n = __popcll(m0) + __popcll(m1);
+            if (lane == c) P.cnt[wave][c] = n;
+            off += n;
+        }
+        if (on0) S.pooled.entry[d0] = e0;
+        if (on1) S.pooled.entry[d1] = e1;
+        if (lane == 0) {
+            P.base[wave] = base;
+            P.first[wave] = first;
+        }
+    }
+    __syncthreads();
+    // per class: each wavefront's share, the pooled count and the number of
+    // batches (uniform values)
+    int cn[W][NK], tot[NK], nbc[NK], nb = 0;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int n = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            cn[w][c] = __builtin_amdgcn_readfirstlane(P.cnt[w][c]);
+            n += cn[w][c];
+        }
+        tot[c] = n;
+        nbc[c] = (n + 63) >> 6;
+        nb += nbc[c];
+    }
+    for (int b = wave; b < nb; b += W) {
+        // the batch's class and its part within the class
+        int c = 0, p = b;
+#pragma unroll
+        for (int cc = 0; cc < NK - 1; ++cc)
+            if (c == cc && p >= nbc[cc]) {
+                p -= nbc[cc];
+                c = cc + 1;
+            }
+        const int l = p * 64 + lane;  // the lane's pair within the class
+        // the class's pairs run through the wavefronts' sorted queues in
+        // order: the owner and the pair's place in its queue
+        int own = 0, pos = 0, pre = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            int before = 0, n = 0;
+#pragma unroll
+            for (int cc = 0; cc < NK; ++cc) {
+                if (cc < c) before += cn[w][cc];
+                if (cc == c) n = cn[w][cc];
+            }
+            if (l >= pre && l < pre + n) {
+                own = w;
+                pos = before + (l - pre);
+            }
+            pre += n;
+        }
+        if (l < pre) {
+            NavScratch<U> &O = scr[own];
+            const unsigned int e = O.pooled.entry[pos];
+            const int j = (int)(e & 1023u);
+            const int k = (int)(e >> 10);
+            const int sl = lds_load(&O.slot_of[j]);
+            double x, y, z, ux, uy, uz;
+            if (sl != kNoSlot) {
+                x = lds_load(&O.x[sl]);
+                y = lds_load(&O.y[sl]);
+                z = lds_load(&O.z[sl]);
+                ux = lds_load(&O.ux[sl]);
+                uy = lds_load(&O.uy[sl]);
+                uz = lds_load(&O.uz[sl]);
+            } else {
+                const int64_t i = P.base[own] + j;
+                x = t.x[i];
+                y = t.y[i];
+                z = t.z[i];
+                ux = t.ux[i];
+                uy = t.uy[i];
+                uz = t.uz[i];
+            }
+            const int f = P.first[own];
+            int sid;
+            const double s = daughter_dist_out<HAS_OFFS, KSET>(dau_all[f + k], cul_all[f + k], offs, k, x, y,
+                                                               z, ux, uy, uz, sid, c);
+            O.pooled.key[pos] = step_key(s);
+            O.pooled.hit[pos] = hit_pack(k, SURF ? sid : -1);
+        }
+    }
+    __syncthreads();
+    // each wavefront merges its own pairs' results
+    for (int e0 = 0; e0 < qn; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < qn) merge_key(S, (int)(S.pooled.entry[e] & 1023u), S.pooled.key[e], S.pooled.hit[e]);
+    }
+}
+
+// The navigator of the W tiles of a workgroup (wavefront `wave` holds
+// `count` tracks from `base` of volume v, whose records start at `first`;
+// count may be 0, the wavefront then only taking part in the pooled flush),
+// the last flush pooled over the workgroup when `shared`.
+template <int U, int W, bool HAS_OFFS, bool HITPT, int KSET>
+__device__ __forceinline__ void nav_compact_pooled(const VolumeRec &v, const DaughterRec *__restrict__ dau_all,
+                                                   const CullRec *__restrict__ cul_all, int first,
+                                                   const double *__restrict__ offs, const TracksDev &t,
+                                                   int64_t base, int count, NavScratch<U> *scr,
+                                                   PoolInfo<W> &P, bool shared, int wave, int lane,
+                                                   double *__restrict__ step, int32_t *__restrict__ hit,
+                                                   double *__restrict__ hitpt) {
+    int qn = 0;
+    if (count > 0)
+        qn = nav_compact_core<U, HAS_OFFS, false, KSET, false, false>(v, dau_all + first, cul_all + first, offs,
+                                                                     t, base, count, scr[wave], lane);
+    pool_flush<U, W, HAS_OFFS, KSET, false>(dau_all, cul_all, offs, t, scr, P, shared, wave, first, base, qn,
+                                            lane);
+    nav_write<U, HITPT>(scr[wave], t, base, count, lane, step, hit, hitpt);
 }
 
 // ---------------------------- compacted navigator safety and localization

@@ -102,7 +102,22 @@ __global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restri
                                                        double *__restrict__ step,
                                                        int32_t *__restrict__ hit,
                                                        double *__restrict__ hitpt) {
+    if constexpr (CULL && KSET != kSetBasic) {
+        // volumes of more kinds: the workgroup's wavefronts pool their last
+        // flush (a wavefront past the basket's end takes part with no tracks)
+        __shared__ NavScratch<U> scr[kBlock / 64];
+        __shared__ PoolInfo<kBlock / 64> pool;
+        const int wave = threadIdx.x >> 6;
+        const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
+        const int64_t left = t.n - base;
+        const int count = left <= 0 ? 0 : (left < 64 * U ? (int)left : 64 * U);
+        nav_compact_pooled<U, kBlock / 64, HAS_OFFS, HITPT, KSET>(*vol, dau, cul, 0, offs, t, base, count, scr,
+                                                                  pool, true, wave, (int)(threadIdx.x & 63),
+                                                                  step, hit, hitpt);
+        return;
+    }
     if constexpr (CULL) {
+        // (box, tube and cone only: pooling gains nothing measurable)
         __shared__ NavScratch<U> scr[kBlock / 64];
         const int wave = threadIdx.x >> 6;
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
@@ -333,6 +348,26 @@ __global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restric
     (void)cursors;
     __shared__ NavScratch<U> scr[CULL ? kBlock / 64 : 1];
     const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    if constexpr (CULL && !COUNT && KSET != kSetBasic) {
+        // volumes of more kinds: the workgroup's wavefronts pool their last
+        // flush when their four tiles belong to one volume (work of about
+        // the same length: tiles of one volume come together in the cost
+        // order); a wavefront past the last tile takes part with no tracks
+        __shared__ PoolInfo<kBlock / 64> pool;
+        const int w0 = (int)blockIdx.x * (kBlock / 64);
+        bool shared = w0 + kBlock / 64 <= ntiles;
+        for (int q = 1; shared && q < kBlock / 64; ++q) shared = tiles[w0 + q].volume == tiles[w0].volume;
+        Tile tl;
+        tl.volume = 0;
+        tl.count = 0;
+        tl.offset = 0;
+        if (w < ntiles) tl = tiles[w];
+        const VolumeRec &v = vols[tl.volume];
+        nav_compact_pooled<U, kBlock / 64, false, false, KSET>(v, dau_all, cul_all, v.first, nullptr, t, tl.offset,
+                                                               tl.count, scr, pool, shared, (int)(threadIdx.x >> 6),
+                                                               (int)(threadIdx.x & 63), step, hit, nullptr);
+        return;
+    }
     if (w >= ntiles) return;
     run_tile<U, CULL, COUNT, KSET>(tiles[w], vols, dau_all, cul_all, t, step, hit, census,
                                    (int)(threadIdx.x & 63), &scr[CULL ? (threadIdx.x >> 6) : 0]);

@@ -64,6 +64,50 @@ def _line_tracks(rng, n):
     return t
 
 
+def _mixed_line_volume(seed, nd=24):
+    """nd daughters of every kind (box, tube, cone, their segments,
+    polycones) in a row of 100-wide cells along x, mother box
+    (50 nd + 10, 60, 60)."""
+    rng = np.random.default_rng(seed)
+    centres = [(-50.0 * (nd - 1) + 100.0 * i, 0.0, 0.0) for i in range(nd)]
+    kinds, pars, rots, trs, bound = W._place_daughters(
+        rng, centres, 50.0, (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON))
+    return W.Volume(W.BOX, np.array([50.0 * nd + 10.0, 60.0, 60.0, 0.0, 0.0]), kinds, pars, rots, trs,
+                    bound)
+
+
+def _mixed_line_tracks(rng, vol, n, dense_frac=0.4):
+    """A fraction of the tracks near the row's axis, along +x or -x (each
+    passes the culling spheres of the daughters ahead of it), starting
+    outside every bounding sphere; the rest off the row (|y| in [52, 58])
+    moving away from it, which queue nothing."""
+    hx = vol.mother_par[0] - 1.0
+    dense = rng.uniform(size=n) < dense_frac
+    m = int(dense.sum())
+    x = rng.uniform(-hx, hx, m)
+    yz = rng.uniform(-3.0, 3.0, (2, m))
+    for _ in range(100):
+        p = np.stack([x, yz[0], yz[1]])
+        ins = np.zeros(m, bool)
+        for k in range(vol.nd):
+            ins |= np.linalg.norm(p - vol.trs[k][:, None], axis=0) < vol.bound_r[k]
+        if not ins.any():
+            break
+        x[ins] = rng.uniform(-hx, hx, int(ins.sum()))
+    assert not ins.any()
+    sgn = np.where(rng.uniform(size=m) < 0.5, 1.0, -1.0)
+    dd = np.stack([sgn, rng.normal(0, 0.01, m), rng.normal(0, 0.01, m)])
+    tr = np.zeros((6, n))
+    tr[:3, dense] = np.stack([x, yz[0], yz[1]])
+    tr[3:, dense] = dd / np.linalg.norm(dd, axis=0)
+    k = n - m
+    sy = np.where(rng.uniform(size=k) < 0.5, 1.0, -1.0)
+    tr[:3, ~dense] = np.stack([rng.uniform(-hx, hx, k), sy * rng.uniform(52, 58, k), rng.uniform(-40, 40, k)])
+    dd = np.stack([rng.normal(0, 0.3, k), sy, rng.normal(0, 0.3, k)])
+    tr[3:, ~dense] = dd / np.linalg.norm(dd, axis=0)
+    return np.ascontiguousarray(tr)
+
+
 def _all_paths(gv, vols, tr, offsets=None):
     """(step, hit) from the basket navigator with culling (compacted) and
     without (sequential), and from the batched navigator at every launch
@@ -289,6 +333,25 @@ def test_direction_length_over_the_supported_range(gv, orc, mixed):
     # and long double builds disagree)
     check_nav(orc, vol, tr, step * scale, hit, what=f"scaled directions, mixed={mixed}",
               max_exempt_frac=5e-3)
+
+
+@pytest.mark.parametrize("n", [(1 << 16) + 37, (1 << 20) + 37])
+def test_dense_queues_of_every_kind(gv, orc, n):
+    """A row of 24 daughters of every kind, 40 % of the tracks along it
+    (about 1.9 queued pairs per track): the workgroups' pooled last flushes
+    hold more than 64 pairs of one kind, and many wavefronts end with more
+    than 128 queued pairs (flushed by the wavefront alone) or flush within
+    the loop. One round of 64 tracks per wavefront at 2^16 tracks, four at
+    2^20. Culled and sequential paths agree bit for bit, at every batched
+    launch shape; a sample matches the oracle."""
+    vol = _mixed_line_volume(1900)
+    rng = np.random.default_rng(1910)
+    tr = _mixed_line_tracks(rng, vol, n)
+    step, hit = _all_paths(gv, [vol], tr)
+    idx = np.sort(rng.choice(n, size=4000, replace=False))
+    print(check_nav(orc, vol, np.ascontiguousarray(tr[:, idx]), step[idx], hit[idx],
+                    what=f"dense row of every kind, {n} tracks", max_exempt_frac=5e-3))
+    assert (hit >= 0).mean() > 0.1  # the tracks along the row end on a daughter
 
 
 @pytest.mark.parametrize("with_offsets", [False, True])
