@@ -94,8 +94,11 @@ hipError_t launch_shape_query(const ShapeRec &s, const PconRec &pc, int query, c
 // With culling, one wavefront takes U rounds of 64 tracks (compacted
 // evaluation; more tracks per wavefront fill more lanes of each batch of
 // queued pairs).
+// Volumes holding every kind: the polycone's code would take the kernel to
+// 102 VGPRs, 4 wavefronts per SIMD; held to 96 (5 wavefronts, a few bytes
+// spilled to scratch) the mixed detector's navigator runs 7 % faster.
 template <bool HAS_OFFS, bool HITPT, bool CULL, int KSET, int U = 1>
-__global__ __launch_bounds__(kBlock) void k_nav_basket(const VolumeRec *__restrict__ vol,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KSET == kSetAll ? 5 : 1))) void k_nav_basket(const VolumeRec *__restrict__ vol,
                                                        const DaughterRec *__restrict__ dau,
                                                        const CullRec *__restrict__ cul,
                                                        TracksDev t, const double *__restrict__ offs,
@@ -336,8 +339,10 @@ __global__ __launch_bounds__(kBlock) void k_nav_persistent(const VolumeRec *__re
 
 // Hardware-scheduled form: one wavefront per tile, workgroups dispatched in
 // tile order (same parameters as the persistent form; `cursors` unused).
+// Every kind: held to 5 wavefronts per SIMD as the basket navigator (up to
+// 4 rounds per wavefront; with 8 the LDS allows 3 anyway).
 template <int U, bool CULL, bool COUNT, int KSET>
-__global__ __launch_bounds__(kBlock) void k_nav_tiles(const VolumeRec *__restrict__ vols,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KSET == kSetAll && U <= 4 ? 5 : 1))) void k_nav_tiles(const VolumeRec *__restrict__ vols,
                                                       const DaughterRec *__restrict__ dau_all,
                                                       const CullRec *__restrict__ cul_all,
                                                       const Tile *__restrict__ tiles, int32_t ntiles,
