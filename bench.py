@@ -261,7 +261,8 @@ def measure_rows(gv, W, dev, steps, scan=True):
 
     mix = W.mixed_detector_volume()
     trm = W.tracks_in_mother(np.random.default_rng(1270), mix, 1 << 22)
-    g, t, _ = basket_row(mix, trm, "navigator_mixed_detector_2^22")
+    g, t, out = basket_row(mix, trm, "navigator_mixed_detector_2^22")
+    keep["mixed"] = (mix, trm) + out
     rows["navigator_mixed_detector_2^22"]["daughters"] = ("32: box, tube, cone, tube segment, cone segment, "
                                                           "polycone in turn")
     g.close()
@@ -429,11 +430,12 @@ def oracle_leg(wl, gpu_step, gpu_hit, info, keep, unrejected):
             name = W.KIND_NAMES[key[1]]
             for q, out in got.items():
                 rows[f"shape_suite_{name}_q{q}"] = shape_parity(oracle, key[1], par, q, tr, out, threads)
-        elif key in ("toy", "toy_uniform"):
+        elif key in ("toy", "toy_uniform", "mixed"):
             v, tr, s, h = val
-            rows["navigator_toy_detector_2^22" if key == "toy" else
-                 "navigator_toy_detector_uniform_in_mother_2^22"] = nav_parity(oracle, v, tr, s, h,
-                                                                                threads=threads)
+            name = {"toy": "navigator_toy_detector_2^22",
+                    "toy_uniform": "navigator_toy_detector_uniform_in_mother_2^22",
+                    "mixed": "navigator_mixed_detector_2^22"}[key]
+            rows[name] = nav_parity(oracle, v, tr, s, h, threads=threads)
     for r in list(rows.values()) + [parity]:
         if not r.get("not_exempt"):
             r.pop("not_exempt_examples", None)

@@ -85,6 +85,20 @@ def test_toy_detector_full_size_every_track(gv, orc):
     assert rep["exempt"] <= max(8, 2e-3 * t.shape[1])
 
 
+def test_mixed_detector_full_size_every_track(gv, orc):
+    """The mixed detector (daughters of all six kinds: the workgroup-pooled,
+    kind-sorted flush) at 2^22 tracks, every track against the oracle's
+    long-double build."""
+    vol = W.mixed_detector_volume()
+    t = W.tracks_in_mother(np.random.default_rng(1270), vol, 1 << 22)
+    step, hit = run_nav(gv, vol, t)
+    rep = nav_parity(orc, vol, t, step, hit, threads=THREADS)
+    print("mixed detector, every track:", rep)
+    assert rep["ok"], rep
+    # segments and polycones meet more tracks at grazing incidence
+    assert rep["exempt"] <= max(8, 5e-3 * t.shape[1])
+
+
 def test_uniform_in_mother_full_size_every_track(gv, orc):
     """Tracks uniform in the mother with no rejection (origins inside the
     daughters, and arbitrarily close to their surfaces, where culling lets
