@@ -1405,8 +1405,11 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
         // back to back, then its pairs are appended (after a flush if they
         // would overflow the queue or their tracks the slots).
         for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
-            // the chunk's records, loaded together (scalar loads)
+            // the chunk's records, loaded together (scalar loads), with
+            // their offsets (padding records take daughter 0's: they never
+            // pass)
             double ctx[kCullChunk], cty[kCullChunk], ctz[kCullChunk], clim[kCullChunk];
+            double cox[kCullChunk], coy[kCullChunk], coz[kCullChunk];
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 const CullRec &Q = cul[k0 + kk];
@@ -1414,20 +1417,24 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
                 cty[kk] = Q.ty;
                 ctz[kk] = Q.tz;
                 clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
+                if (HAS_OFFS) {
+                    const int ko = k0 + kk < nd ? k0 + kk : 0;
+                    cox[kk] = offs[3 * ko + 0];
+                    coy[kk] = offs[3 * ko + 1];
+                    coz[kk] = offs[3 * ko + 2];
+                }
             }
             // the chunk's tests (independent, so they interleave)
             unsigned long long cm[kCullChunk];
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
-                const int k = k0 + kk;
                 double b, g;  // w.e and |w|^2 - shift, with w = p - centre
                 if (HAS_OFFS) {
                     // the centre moves with the offset: w formed explicitly, shift 0,
                     // limit r2
-                    const int ko = k < nd ? k : 0;  // (padding records never pass)
-                    const double wx = x - ctx[kk] - offs[3 * ko + 0];
-                    const double wy = y - cty[kk] - offs[3 * ko + 1];
-                    const double wz = z - ctz[kk] - offs[3 * ko + 2];
+                    const double wx = x - ctx[kk] - cox[kk];
+                    const double wy = y - cty[kk] - coy[kk];
+                    const double wz = z - ctz[kk] - coz[kk];
                     b = fma(wz, -mez, fma(wy, -mey, wx * -mex));
                     g = fma(wz, wz, fma(wy, wy, wx * wx));
                 } else {
@@ -1811,6 +1818,18 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
                 point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, S, qn, lane);
                 qn = 0;
             }
+            // the chunk's offsets, loaded together before its tests (padding
+            // records take daughter 0's: they never pass)
+            double cox[kCullChunk], coy[kCullChunk], coz[kCullChunk];
+            if (HAS_OFFS) {
+#pragma unroll
+                for (int kk = 0; kk < kCullChunk; ++kk) {
+                    const int ko = k0 + kk < nd ? k0 + kk : 0;
+                    cox[kk] = offs[3 * ko + 0];
+                    coy[kk] = offs[3 * ko + 1];
+                    coz[kk] = offs[3 * ko + 2];
+                }
+            }
             unsigned long long cm[kCullChunk];
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
@@ -1819,10 +1838,9 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
                 bool pass;
                 if (HAS_OFFS) {
                     // the centre moves with the offset: |w|^2 formed explicitly
-                    const int ko = k < nd ? k : 0;
-                    const double wx = x - Q.tx - offs[3 * ko + 0];
-                    const double wy = y - Q.ty - offs[3 * ko + 1];
-                    const double wz = z - Q.tz - offs[3 * ko + 2];
+                    const double wx = x - Q.tx - cox[kk];
+                    const double wy = y - Q.ty - coy[kk];
+                    const double wz = z - Q.tz - coz[kk];
                     const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
                     if (MODE == 0) {
                         const double lim = reach + Q.r;
