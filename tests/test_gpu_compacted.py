@@ -64,14 +64,16 @@ def _line_tracks(rng, n):
     return t
 
 
-def _mixed_line_volume(seed, nd=24):
-    """nd daughters of every kind (box, tube, cone, their segments,
-    polycones) in a row of 100-wide cells along x, mother box
-    (50 nd + 10, 60, 60)."""
+EVERY_KIND = (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON)
+
+
+def _mixed_line_volume(seed, nd=24, kinds=EVERY_KIND):
+    """nd daughters of the given kinds in turn (by default every kind: box,
+    tube, cone, their segments, polycones) in a row of 100-wide cells along
+    x, mother box (50 nd + 10, 60, 60)."""
     rng = np.random.default_rng(seed)
     centres = [(-50.0 * (nd - 1) + 100.0 * i, 0.0, 0.0) for i in range(nd)]
-    kinds, pars, rots, trs, bound = W._place_daughters(
-        rng, centres, 50.0, (W.BOX, W.TUBE, W.CONE, W.TUBS, W.CONS, W.PCON))
+    kinds, pars, rots, trs, bound = W._place_daughters(rng, centres, 50.0, kinds)
     return W.Volume(W.BOX, np.array([50.0 * nd + 10.0, 60.0, 60.0, 0.0, 0.0]), kinds, pars, rots, trs,
                     bound)
 
@@ -336,15 +338,17 @@ def test_direction_length_over_the_supported_range(gv, orc, mixed):
 
 
 @pytest.mark.parametrize("n", [(1 << 16) + 37, (1 << 20) + 37])
-def test_dense_queues_of_every_kind(gv, orc, n):
-    """A row of 24 daughters of every kind, 40 % of the tracks along it
-    (about 1.9 queued pairs per track): the workgroups' pooled last flushes
-    hold more than 64 pairs of one kind, and many wavefronts end with more
-    than 128 queued pairs (flushed by the wavefront alone) or flush within
-    the loop. One round of 64 tracks per wavefront at 2^16 tracks, four at
-    2^20. Culled and sequential paths agree bit for bit, at every batched
-    launch shape; a sample matches the oracle."""
-    vol = _mixed_line_volume(1900)
+@pytest.mark.parametrize("polycones", [True, False])
+def test_dense_queues_of_every_kind(gv, orc, n, polycones):
+    """A row of 24 daughters of every kind (or every kind but the polycone:
+    the kernels for segments, five kind classes), 40 % of the tracks along
+    it (about 1.9 queued pairs per track): the workgroups' pooled last
+    flushes hold more than 64 pairs of one kind, and many wavefronts end
+    with more than 128 queued pairs (flushed by the wavefront alone) or
+    flush within the loop. One round of 64 tracks per wavefront at 2^16
+    tracks, four at 2^20. Culled and sequential paths agree bit for bit, at
+    every batched launch shape; a sample matches the oracle."""
+    vol = _mixed_line_volume(1900, kinds=EVERY_KIND if polycones else EVERY_KIND[:5])
     rng = np.random.default_rng(1910)
     tr = _mixed_line_tracks(rng, vol, n)
     step, hit = _all_paths(gv, [vol], tr)
