@@ -1809,8 +1809,11 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
         const unsigned long long amask = __builtin_amdgcn_ballot_w64(MODE == 0 ? act : (act && in_m));
         if (amask == 0ull) continue;
         // per-point constants of the expanded test (no offsets): |p|^2, -2 p,
-        // and for the safety 2 reach and reach^2
-        const double pp = fma(z, z, fma(y, y, x * x));
+        // and for the safety 2 reach and reach^2; a lane outside amask gets
+        // |p|^2 = +inf, so that none of its expanded tests passes and their
+        // ballots need no mask (nor do padding records, whose q is -inf)
+        double pp = fma(z, z, fma(y, y, x * x));
+        if (!((amask >> lane) & 1ull)) pp = __builtin_inf();
         const double mpx = -2.0 * x, mpy = -2.0 * y, mpz = -2.0 * z;
         const double reach2 = 2.0 * reach, rr = reach * reach;
         for (int k0 = 0; k0 < ndp; k0 += kCullChunk) {
@@ -1818,12 +1821,20 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
                 point_flush<MODE, HAS_OFFS, KSET, U>(dau, cul, offs, S, qn, lane);
                 qn = 0;
             }
-            // the chunk's offsets, loaded together before its tests (padding
-            // records take daughter 0's: they never pass)
+            // the chunk's records and offsets, loaded together before its
+            // tests (scalar loads; padding records take daughter 0's offsets:
+            // they never pass)
+            double ctx[kCullChunk], cty[kCullChunk], ctz[kCullChunk], cr[kCullChunk], clim[kCullChunk];
             double cox[kCullChunk], coy[kCullChunk], coz[kCullChunk];
-            if (HAS_OFFS) {
 #pragma unroll
-                for (int kk = 0; kk < kCullChunk; ++kk) {
+            for (int kk = 0; kk < kCullChunk; ++kk) {
+                const CullRec &Q = cul[k0 + kk];
+                ctx[kk] = Q.tx;
+                cty[kk] = Q.ty;
+                ctz[kk] = Q.tz;
+                cr[kk] = Q.r;
+                clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
+                if (HAS_OFFS) {
                     const int ko = k0 + kk < nd ? k0 + kk : 0;
                     cox[kk] = offs[3 * ko + 0];
                     coy[kk] = offs[3 * ko + 1];
@@ -1834,19 +1845,18 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 const int k = k0 + kk;
-                const CullRec &Q = cul[k];
                 bool pass;
                 if (HAS_OFFS) {
                     // the centre moves with the offset: |w|^2 formed explicitly
-                    const double wx = x - Q.tx - cox[kk];
-                    const double wy = y - Q.ty - coy[kk];
-                    const double wz = z - Q.tz - coz[kk];
+                    const double wx = x - ctx[kk] - cox[kk];
+                    const double wy = y - cty[kk] - coy[kk];
+                    const double wz = z - ctz[kk] - coz[kk];
                     const double ww = fma(wz, wz, fma(wy, wy, wx * wx));
                     if (MODE == 0) {
-                        const double lim = reach + Q.r;
+                        const double lim = reach + cr[kk];
                         pass = ww < lim * lim;
                     } else {
-                        pass = ww <= Q.r2;
+                        pass = ww <= clim[kk];
                     }
                 } else {
                     // |w|^2 - |T|^2 = |p|^2 - 2 p.T against the thresholds less
@@ -1856,14 +1866,16 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
                     // (reach is at most the mother's bounding radius R for a
                     // point inside the mother, so every term stays within the
                     // (3 R + 2 |T|)^2 that the bound of q covers)
-                    const double g = fma(Q.tz, mpz, fma(Q.ty, mpy, fma(Q.tx, mpx, pp)));
+                    const double g = fma(ctz[kk], mpz, fma(cty[kk], mpy, fma(ctx[kk], mpx, pp)));
                     if (MODE == 0)
-                        pass = g < fma(Q.r, reach2, Q.q) + rr;
+                        pass = g < fma(cr[kk], reach2, clim[kk]) + rr;
                     else
-                        pass = g <= Q.q;
+                        pass = g <= clim[kk];
                 }
-                // padding records (k >= nd) are excluded here: their radius is 0
-                cm[kk] = __builtin_amdgcn_ballot_w64(pass) & (k < nd ? amask : 0ull);
+                // with offsets, lanes outside amask and padding records (k >= nd,
+                // whose radius is 0) are masked here
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
+                cm[kk] = HAS_OFFS ? bal & (k < nd ? amask : 0ull) : bal;
             }
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
