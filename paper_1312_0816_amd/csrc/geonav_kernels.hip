@@ -472,24 +472,30 @@ int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles) {
 // With phi = gstep s + ghit . (p + s d) and c = gstep + ghit . d:
 //   g_p = ghit + c ds/dp,  g_d = s ghit + c ds/dd,  g_delta_hit += c ds/d delta.
 // The offset gradient of the workgroup's tracks is summed per daughter in a
-// fixed lane order into the workgroup's row of `partial`.
+// fixed lane order into the workgroup's row of `partial`, accumulated over
+// the workgroup's passes in LDS when lds_acc (3 nd doubles; else in the row
+// itself) and written once.
 template <bool HAS_OFFS, bool CULL, int KSET>
 __global__ __launch_bounds__(kBlock) void k_nav_backward(
     const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau,
     const CullRec *__restrict__ cul, TracksDev t, const double *__restrict__ offs,
     const double *__restrict__ gstep,
     const double *__restrict__ ghit, double *__restrict__ g_o, double *__restrict__ g_d,
-    double *__restrict__ partial) {
+    double *__restrict__ partial, bool lds_acc) {
     __shared__ double s_g[3][kBlock];
     __shared__ NavScratch<1> scr[CULL ? kBlock / 64 : 1];
-    extern __shared__ int s_bins[];  // 4 * nd + nd + 1 ints (see below)
+    // [3 nd] doubles of the row's accumulator when lds_acc, then 4 nd + nd + 1
+    // ints (see below)
+    extern __shared__ double s_dyn[];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int nd = vol->nd;
     const int nj = 3 * nd;
     double *prow = partial ? partial + (size_t)blockIdx.x * nj : nullptr;
+    double *acc_row = lds_acc ? s_dyn : prow;  // each entry j is thread (j mod kBlock)'s alone
+    int *s_bins = reinterpret_cast<int *>(s_dyn + (lds_acc ? nj : 0));
     if (prow)
-        for (int j = tid; j < nj; j += kBlock) prow[j] = 0.0;
+        for (int j = tid; j < nj; j += kBlock) acc_row[j] = 0.0;
     const int64_t n = t.n;
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t i = base + tid;
@@ -577,11 +583,13 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             // stable counting sort of the contributions by hit daughter,
             // then each (daughter, component) sums its run in track order,
             // the order of a plain scan over the workgroup's tracks.
-            int *cnt = s_bins;           // [4][nd]: per-wavefront counts, then offsets
+            int *cnt = s_bins;           // [4][nd]: per-wavefront counts
             int *run = s_bins + 4 * nd;  // [nd + 1]: start of each daughter's run
-            for (int j = tid; j < 4 * nd; j += kBlock) cnt[j] = 0;
-            __syncthreads();
-            // rank among the earlier lanes of the wavefront with the same daughter
+            // each wavefront clears its own row (the other wavefronts last
+            // read it before the barrier that ended the previous pass), then
+            // counts its tracks per daughter and ranks each among the
+            // earlier lanes with the same daughter
+            for (int k = lane; k < nd; k += 64) cnt[wave * nd + k] = 0;
             int rank = 0;
             unsigned long long rem = __builtin_amdgcn_ballot_w64(h >= 0);
             while (rem != 0ull) {
@@ -592,48 +600,52 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
                 rem &= ~m;
             }
             __syncthreads();
-            // runs: exclusive scan of the daughters' totals (wavefront 0, 64
-            // daughters a pass), then each wavefront's offset within a run
-            if (wave == 0) {
-                int carry = 0;
-                for (int k0 = 0; k0 < nd; k0 += 64) {
-                    const int k = k0 + lane;
-                    const int tot = k < nd ? cnt[k] + cnt[nd + k] + cnt[2 * nd + k] + cnt[3 * nd + k] : 0;
-                    int incl = tot;
-                    for (int dlt = 1; dlt < 64; dlt <<= 1) {
-                        const int v = __shfl_up(incl, dlt);
-                        if (lane >= dlt) incl += v;
+            // every wavefront forms the runs itself (an exclusive scan of the
+            // daughters' totals, 64 daughters a pass, lane = daughter) and
+            // its own offset within each run; wavefront 0 publishes the runs
+            int pos = 0;
+            int carry = 0;
+            for (int k0 = 0; k0 < nd; k0 += 64) {
+                const int k = k0 + lane;
+                int tot = 0, below = 0;
+                if (k < nd) {
+#pragma unroll
+                    for (int w = 0; w < kBlock / 64; ++w) {
+                        const int c = cnt[w * nd + k];
+                        tot += c;
+                        below += w < wave ? c : 0;
                     }
-                    if (k < nd) {
-                        int off = carry + incl - tot;
-                        run[k] = off;
-                        for (int w = 0; w < kBlock / 64; ++w) {
-                            const int c = cnt[w * nd + k];
-                            cnt[w * nd + k] = off;
-                            off += c;
-                        }
-                    }
-                    carry += __shfl(incl, 63);
                 }
-                if (lane == 0) run[nd] = carry;
+                int incl = tot;
+                for (int dlt = 1; dlt < 64; dlt <<= 1) {
+                    const int v = __shfl_up(incl, dlt);
+                    if (lane >= dlt) incl += v;
+                }
+                const int start = carry + incl - tot;
+                if (wave == 0 && k < nd) run[k] = start;
+                // a lane whose daughter falls in this pass takes its offset
+                const int off = __shfl(start + below, (h - k0) & 63);
+                if (h >= k0 && h < k0 + 64) pos = off + rank;
+                carry += __shfl(incl, 63);
             }
-            __syncthreads();
+            if (wave == 0 && lane == 0) run[nd] = carry;
             if (h >= 0) {
-                const int p = cnt[wave * nd + h] + rank;
-                s_g[0][p] = gdx;
-                s_g[1][p] = gdy;
-                s_g[2][p] = gdz;
+                s_g[0][pos] = gdx;
+                s_g[1][pos] = gdy;
+                s_g[2][pos] = gdz;
             }
             __syncthreads();
             for (int j = tid; j < nj; j += kBlock) {
                 const int k = j / 3, comp = j - 3 * k;
                 double acc = 0.0;
                 for (int q = run[k]; q < run[k + 1]; ++q) acc += s_g[comp][q];
-                prow[j] += acc;
+                acc_row[j] += acc;
             }
             __syncthreads();
         }
     }
+    if (prow && lds_acc)
+        for (int j = tid; j < nj; j += kBlock) prow[j] = acc_row[j];
 }
 
 // out[j] = sum over workgroups b of partial[b][j], in a fixed order.
@@ -653,18 +665,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__rest
     if (threadIdx.x == 0) out[j] = s[0];
 }
 
+constexpr int kBackwardLdsAcc = 256;
+
 template <bool CULL, int KSET>
 static void launch_backward_variant(int nblocks, int nd, const VolumeRec *vol, const DaughterRec *dau,
                                     const CullRec *cul, const TracksDev &t, const double *offs, const double *gstep,
                                     const double *ghit, double *g_o, double *g_d, double *part,
                                     hipStream_t st) {
-    const size_t bins = sizeof(int) * (size_t)(5 * nd + 1);  // the offset-gradient sort
+    // the offset-gradient sort's counts and runs; the row's accumulator in
+    // LDS up to kBackwardLdsAcc daughters (6 KB)
+    const bool lds_acc = part && nd <= kBackwardLdsAcc;
+    const size_t dyn = (lds_acc ? sizeof(double) * 3 * (size_t)nd : 0) + sizeof(int) * (size_t)(5 * nd + 1);
     if (offs)
-        hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET>), dim3(nblocks), dim3(kBlock), bins, st, vol, dau, cul, t,
-                           offs, gstep, ghit, g_o, g_d, part);
+        hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET>), dim3(nblocks), dim3(kBlock), dyn, st, vol, dau, cul, t,
+                           offs, gstep, ghit, g_o, g_d, part, lds_acc);
     else
-        hipLaunchKernelGGL((k_nav_backward<false, CULL, KSET>), dim3(nblocks), dim3(kBlock), bins, st, vol, dau, cul, t,
-                           offs, gstep, ghit, g_o, g_d, part);
+        hipLaunchKernelGGL((k_nav_backward<false, CULL, KSET>), dim3(nblocks), dim3(kBlock), dyn, st, vol, dau, cul, t,
+                           offs, gstep, ghit, g_o, g_d, part, lds_acc);
 }
 
 int backward_blocks(int64_t n) {
