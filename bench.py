@@ -6,8 +6,10 @@ each a box mother (200)^3 with 1..64 daughters (box/tube/cone) on a 4x4x4
 grid (about 4.26M tracks, FP64). The step runs the whole navigator path:
 basket load, geometry access, master-to-local transforms, every daughter's
 DistFromOutside, the mother's DistFromInside, min/argmin and the outputs,
-scheduled as one launch from a cached HIP graph (the persistent kernel, or
-one wavefront per tile, whichever the autotuner finds faster).
+in one navigator launch after the kernel that expands the baskets into
+tiles (the persistent kernel, or one wavefront per tile; the two kernels
+launched one after the other or replayed from a cached HIP graph; whichever
+the autotuner finds faster, the other submission timed beside it).
 
 Clock ramp: the GPU reaches its full clock only after some tens of
 milliseconds of sustained load, so before the W warmup steps and the K
@@ -18,8 +20,7 @@ Printed: one JSON line with tracks/s, the plain per-basket comparison (512
 separate geo_navigate_basket launches doing the same work, issued one by one
 and, beside that, captured in one HIP graph), the roofline of the dominant
 kernel (the batched navigator: its algorithmic HBM bytes, 60 per track,
-over its duration from HIP events that the graph records around the kernel
-node; beside it the same with every cache flushed before each launch, the
+over its duration from HIP events recorded around the kernel; beside it the same with every cache flushed before each launch, the
 counter traffic, the VALU issue and FP64 rates from the committed counter
 summary, and the flops the kernel issues), the rows of the other hot-path
 kernels, the CPU oracle timed on this host, and the parity of every output
@@ -27,7 +28,7 @@ of the headline step (and of the rows' workloads) against the oracle's
 long-double build. The headline value is null unless that parity passes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
-                       [--launch U,W | --no-autotune] [--no-rows] [--no-scan] [--no-plain]
+                       [--launch U,W[,graph|direct] | --no-autotune] [--no-rows] [--no-scan] [--no-plain]
 """
 from __future__ import annotations
 
@@ -492,11 +493,14 @@ def main():
     bv, bo, bn = wl.basket_volume, wl.basket_offset, wl.basket_n
 
     if args.launch:
-        u_, w_ = (int(v) for v in args.launch.split(","))
-        g.set_launch_config(u_, w_)
+        parts = args.launch.split(",")
+        g.set_launch_config(int(parts[0]), int(parts[1]))
+        if len(parts) > 2:
+            g.batched_graph = parts[2] == "graph"
     elif not args.no_autotune:
         gv.geo_autotune(g, bv, bo, bn, t)
     U, Wv = g.launch_config()
+    use_graph = g.batched_graph
 
     # Host-side call arguments are marshalled once; each step is then one C
     # call (batched) or one C call per basket (plain), on torch's stream.
@@ -556,9 +560,9 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     out_step, out_hit = step.cpu().numpy(), hit.cpu().numpy()
 
-    # the navigator kernel alone: events that the graph records right before
-    # and after its kernel node (the tile expansion and the gaps between graph
-    # launches fall outside), read after each launch
+    # the navigator kernel alone: events recorded right before and after it
+    # (on the stream, or as nodes of the graph; the tile expansion and the
+    # gaps between calls fall outside), read after each launch
     k_launches = max(args.steps, 100)
     g.set_kernel_timing(True)
     clock_ramp(batched_step, 50.0)
@@ -599,6 +603,19 @@ def main():
     torch.cuda.synchronize()
     nocull_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     g.culling = True
+    batched_step()
+
+    # the other submission of the two kernels (a graph replay instead of two
+    # launches, or the reverse), for the record
+    g.batched_graph = not use_graph
+    clock_ramp(batched_step, 20.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched_step()
+    torch.cuda.synchronize()
+    other_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    g.batched_graph = use_graph
     batched_step()
 
     # timed: plain per-basket launches (after W warmup steps of their own)
@@ -699,9 +716,10 @@ def main():
         "config": {
             "workload": f"batched navigation: {len(bn)} baskets (32-65536 tracks, log-uniform) over "
                         f"{len(wl.volumes)} volumes (box mother (200)^3, 1-64 box/tube/cone daughters), "
-                        f"{n} tracks, FP64, one graph launch",
+                        f"{n} tracks, FP64, one navigator launch",
             "baskets": int(len(bn)), "volumes": int(len(wl.volumes)), "tracks": n,
-            "launch": {"tracks_per_lane": U, "waves_per_simd": Wv, "autotuned": not (args.no_autotune or args.launch)},
+            "launch": {"tracks_per_lane": U, "waves_per_simd": Wv, "graph": bool(use_graph),
+                       "autotuned": not (args.no_autotune or args.launch)},
         },
         "roofline": {
             "bound": "hbm",
@@ -714,7 +732,7 @@ def main():
             "bytes_per_track": BYTES_PER_TRACK,
             "tracks_per_launch": n,
             "kernel_ms_per_launch": kernel_ms,
-            "timing": f"HIP events recorded by the graph around the kernel node, mean over {k_launches} launches",
+            "timing": f"HIP events recorded around the navigator kernel, mean over {k_launches} launches",
             "cold_caches": {"kernel_ms_per_launch": kernel_ms_cold, "achieved": hbm_cold,
                             "frac": hbm_cold / HBM_PEAK_GBS,
                             "timing": f"the same events, a 1 GiB read before each of {len(kms_cold)} launches"},
@@ -750,6 +768,8 @@ def main():
         "batched_without_culling": {"value": n / (nocull_ms * 1e-3), "unit": "tracks/s",
                                     "ms_per_step": nocull_ms, "kernel_ms": nocull_kernel_ms,
                                     "flops_per_launch": flops_nocull},
+        "batched_other_submission": {"graph": not use_graph, "value": n / (other_ms * 1e-3), "unit": "tracks/s",
+                                     "ms_per_step": other_ms},
         "batched_uniform_in_mother": unrej_row,
         "census": {"evaluations_by_kind_hole": counts[:14], "cull_tests": counts[gv.CENSUS_CULL],
                    "tracks": counts[gv.CENSUS_TRACKS],

@@ -172,8 +172,10 @@ int geo_navigate_safety(const geo_geometry *g, int32_t volume, geo_tracks t, con
 int geo_locate(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets, int32_t *where,
                hipStream_t stream);
 
-/* Many baskets of possibly different volumes in ONE persistent launch
- * (replayed from a cached HIP graph). baskets: host array of nb entries
+/* Many baskets of possibly different volumes in ONE navigator launch,
+ * after a small kernel that expands the baskets into tiles (the two as two
+ * launches on the stream, or as a replay of a cached HIP graph: see
+ * geo_set_batched_graph). baskets: host array of nb entries
  * indexing into the shared pool `all`; step and hit are indexed like the
  * pool (entry offset + j for track j of a basket); pool entries not covered
  * by any basket are left untouched. Results are bit-identical to
@@ -237,10 +239,11 @@ int geo_navigate_batched_census(geo_geometry *g, const geo_basket *baskets, int3
 
 /* Time the candidate launch shapes of the batched kernel (tracks per lane
  * 1/2/4/8 x waves per SIMD 0/2/3/4/6/8) on these baskets, as bursts of
- * back-to-back calls after a warm-up, and keep the fastest in the handle; also records
- * it in the JSON cache named by the GEONAV_AUTOTUNE_CACHE environment
- * variable, if set. Writes step/hit scratch internally; synchronises the
- * stream. */
+ * back-to-back calls after a warm-up, then, at the fastest shape, the two
+ * kernels as a graph replay against two launches; keep the fastest in the
+ * handle; also records it in the JSON cache named by the
+ * GEONAV_AUTOTUNE_CACHE environment variable, if set. Writes step/hit
+ * scratch internally; synchronises the stream. */
 int geo_autotune(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tracks all,
                  hipStream_t stream);
 
@@ -252,6 +255,15 @@ int geo_autotune(geo_geometry *g, const geo_basket *baskets, int32_t nb, geo_tra
  * autotuner may change them. Results do not depend on the launch shape. */
 int geo_get_launch_config(const geo_geometry *g, int32_t *tracks_per_lane, int32_t *waves_per_simd);
 int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t waves_per_simd);
+
+/* How geo_navigate_batched submits its two kernels: use_graph = 1 replays a
+ * HIP graph built on the first call (its kernel arguments updated in place
+ * on later calls), 0 launches them one after the other on the stream. The
+ * default is 0 (on an MI355X the replay measured about 6 us more per call);
+ * the autotuner may change it. Results do not depend on it. GEO_ERR_INVALID_ARG
+ * for a NULL handle or pointer, or use_graph other than 0 or 1. */
+int geo_get_batched_graph(const geo_geometry *g, int32_t *use_graph);
+int geo_set_batched_graph(geo_geometry *g, int32_t use_graph);
 
 /* Culling in the navigators (basket, batched, backward): a daughter is not
  * evaluated for a track whose line cannot enter the daughter's bounding

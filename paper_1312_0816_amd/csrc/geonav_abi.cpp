@@ -324,6 +324,7 @@ struct geo_geometry {
     // batched state
     int tracks_per_lane = 4;
     int waves_per_simd = 0;  // hardware-scheduled until geo_autotune picks
+    bool use_graph = false;  // batched kernels as two launches until geo_autotune picks
     bool cull = true;               // wavefront bounding-sphere culling in the navigators
     // Basket lists are staged in a ring of mapped pinned host buffers that the
     // tile-expansion kernel reads directly (no copy node). The ring holds
@@ -812,11 +813,19 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     void *bargs[] = {&ba};
     void *pargs[] = {&pa.vols, &pa.dau, &pa.cul, &pa.tiles, &pa.ntiles, &pa.cursors, &pa.t, &pa.step,
                      &pa.hit, &pa.census};
-    if (census) {  // instrumented run: direct launches, no graph
-        GN_HIP(hipMemsetAsync(census, 0, kCensusSlots * sizeof(unsigned long long), stream));
+    if (census || !g->use_graph) {
+        // two launches on the stream (the instrumented run always: its
+        // census kernel is not the graph's)
+        if (census) GN_HIP(hipMemsetAsync(census, 0, kCensusSlots * sizeof(unsigned long long), stream));
         GN_HIP(hipLaunchKernel(build_tiles_kernel(), dim3(kBuildTilesBlocks), dim3(kBlock), bargs, 0, stream));
-        GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, true, g->kset), dim3(grid), dim3(kBlock), pargs, 0,
-                               stream));
+        const bool kt = g->ktime && !census;
+        if (kt) GN_HIP(hipEventRecord(g->kt_before, stream));
+        GN_HIP(hipLaunchKernel(batched_kernel(U, g->cull, persistent, census != nullptr, g->kset), dim3(grid),
+                               dim3(kBlock), pargs, 0, stream));
+        if (kt) {
+            GN_HIP(hipEventRecord(g->kt_after, stream));
+            g->ktime_recorded = true;
+        }
         return advance_stage(g, stream);
     }
     hipKernelNodeParams kb = {};
@@ -940,6 +949,19 @@ int geo_set_launch_config(geo_geometry *g, int32_t tracks_per_lane, int32_t wave
     return GEO_OK;
 }
 
+int geo_get_batched_graph(const geo_geometry *g, int32_t *use_graph) {
+    if (!g || !use_graph) return fail(GEO_ERR_INVALID_ARG, "NULL argument");
+    *use_graph = g->use_graph ? 1 : 0;
+    return GEO_OK;
+}
+
+int geo_set_batched_graph(geo_geometry *g, int32_t use_graph) {
+    if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
+    if (use_graph != 0 && use_graph != 1) return fail(GEO_ERR_INVALID_ARG, "use_graph must be 0 or 1");
+    g->use_graph = use_graph != 0;
+    return GEO_OK;
+}
+
 int geo_set_culling(geo_geometry *g, int32_t enable) {
     if (!g) return fail(GEO_ERR_INVALID_ARG, "geometry is NULL");
     g->cull = enable != 0;
@@ -994,9 +1016,14 @@ std::string tune_key(const geo_geometry *g, const geo_basket *b, int nb) {
     return os.str();
 }
 
-// The cache is a flat JSON object: {"key": [tracks_per_lane, waves_per_simd], ...}
-std::vector<std::pair<std::string, std::pair<int, int>>> read_cache(const char *path) {
-    std::vector<std::pair<std::string, std::pair<int, int>>> out;
+// The cache is a flat JSON object:
+// {"key": [tracks_per_lane, waves_per_simd, use_graph], ...} (an entry of
+// two numbers, from before the launch mode was tuned, reads as use_graph 0).
+struct TuneEntry {
+    int u, w, graph;
+};
+std::vector<std::pair<std::string, TuneEntry>> read_cache(const char *path) {
+    std::vector<std::pair<std::string, TuneEntry>> out;
     std::ifstream f(path);
     if (!f) return out;
     std::stringstream ss;
@@ -1011,23 +1038,23 @@ std::vector<std::pair<std::string, std::pair<int, int>>> read_cache(const char *
         size_t lb = s.find('[', q1);
         size_t rb = s.find(']', lb == std::string::npos ? q1 : lb);
         if (lb == std::string::npos || rb == std::string::npos) break;
-        int u = 0, w = 0;
-        if (std::sscanf(s.c_str() + lb, "[%d , %d]", &u, &w) == 2 ||
-            std::sscanf(s.c_str() + lb, "[%d,%d]", &u, &w) == 2)
-            out.push_back({s.substr(q0 + 1, q1 - q0 - 1), {u, w}});
+        int u = 0, w = 0, gr = 0;
+        const std::string item = s.substr(lb + 1, rb - lb - 1);
+        const int got = std::sscanf(item.c_str(), " %d , %d , %d", &u, &w, &gr);
+        if (got >= 2) out.push_back({s.substr(q0 + 1, q1 - q0 - 1), TuneEntry{u, w, got == 3 ? gr : 0}});
         pos = rb + 1;
     }
     return out;
 }
 
-void write_cache(const char *path, const std::vector<std::pair<std::string, std::pair<int, int>>> &ent) {
+void write_cache(const char *path, const std::vector<std::pair<std::string, TuneEntry>> &ent) {
     std::string tmp = std::string(path) + ".tmp";
     std::ofstream f(tmp);
     if (!f) return;
     f << "{\n";
     for (size_t i = 0; i < ent.size(); ++i)
-        f << "  \"" << ent[i].first << "\": [" << ent[i].second.first << ", " << ent[i].second.second << "]"
-          << (i + 1 < ent.size() ? ",\n" : "\n");
+        f << "  \"" << ent[i].first << "\": [" << ent[i].second.u << ", " << ent[i].second.w << ", "
+          << ent[i].second.graph << "]" << (i + 1 < ent.size() ? ",\n" : "\n");
     f << "}\n";
     f.close();
     std::rename(tmp.c_str(), path);
@@ -1044,7 +1071,9 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
     const std::string key = tune_key(g, b, nb);
     auto cache = path ? read_cache(path) : decltype(read_cache("")){};
     for (auto &e : cache)
-        if (e.first == key && geo_set_launch_config(g, e.second.first, e.second.second) == GEO_OK) return GEO_OK;
+        if (e.first == key && geo_set_launch_config(g, e.second.u, e.second.w) == GEO_OK &&
+            geo_set_batched_graph(g, e.second.graph) == GEO_OK)
+            return GEO_OK;
 
     double *step = nullptr;
     int32_t *hit = nullptr;
@@ -1112,6 +1141,32 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
                 bestU = Us[iu];
                 bestW = Ws[iw];
             }
+    // then, at the best shape, the two kernels as a graph replay against two
+    // launches (two passes, as above)
+    const bool mode0 = g->use_graph;
+    float tmode[2] = {1e30f, 1e30f};
+    g->tracks_per_lane = bestU;
+    g->waves_per_simd = bestW;
+    for (int pass = 0; pass < 2 && rc == GEO_OK; ++pass) {
+        for (int m = 0; m < 2 && rc == GEO_OK; ++m) {
+            g->use_graph = m == 1;
+            constexpr int kBurst = 6;
+            rc = launch_batched(g, b, nb, all, step, hit, stream);
+            (void)hipEventRecord(e0, stream);
+            for (int k = 0; k < kBurst && rc == GEO_OK; ++k) rc = launch_batched(g, b, nb, all, step, hit, stream);
+            (void)hipEventRecord(e1, stream);
+            if (rc) break;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(GEO_ERR_HIP, "autotune timing failed");
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmode[m] = std::min(tmode[m], ms / kBurst);
+        }
+    }
+    const bool bestGraph = rc == GEO_OK ? tmode[1] < tmode[0] : mode0;
+    g->use_graph = bestGraph;
     (void)hipStreamSynchronize(stream);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1122,12 +1177,13 @@ int geo_autotune(geo_geometry *g, const geo_basket *b, int32_t nb, geo_tracks al
     if (rc) return rc;
     if (path) {
         bool found = false;
+        const TuneEntry te{bestU, bestW, bestGraph ? 1 : 0};
         for (auto &e : cache)
             if (e.first == key) {
-                e.second = {bestU, bestW};
+                e.second = te;
                 found = true;
             }
-        if (!found) cache.push_back({key, {bestU, bestW}});
+        if (!found) cache.push_back({key, te});
         write_cache(path, cache);
     }
     return GEO_OK;

@@ -66,7 +66,8 @@ class GeoBasket(C.Structure):
 
 EXPORTS = ("geo_geometry_create", "geo_geometry_destroy", "geo_shape_query",
            "geo_navigate_basket", "geo_navigate_batched", "geo_navigate_backward",
-           "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_set_culling",
+           "geo_autotune", "geo_get_launch_config", "geo_set_launch_config", "geo_get_batched_graph",
+           "geo_set_batched_graph", "geo_set_culling",
            "geo_get_culling", "geo_navigate_batched_census", "geo_navigate_safety",
            "geo_locate", "geo_set_kernel_timing", "geo_batched_kernel_ms", "geo_navigate_backward_noalloc",
            "geo_strerror")
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH):
     lib.geo_autotune.argtypes = [P, C.POINTER(GeoBasket), I32, GeoTracks, P]
     lib.geo_get_launch_config.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
     lib.geo_set_launch_config.argtypes = [P, I32, I32]
+    lib.geo_get_batched_graph.argtypes = [P, C.POINTER(I32)]
+    lib.geo_set_batched_graph.argtypes = [P, I32]
     lib.geo_set_culling.argtypes = [P, I32]
     lib.geo_navigate_safety.argtypes = [P, I32, GeoTracks, P, P, P]
     lib.geo_locate.argtypes = [P, I32, GeoTracks, P, P, P]
@@ -246,6 +249,17 @@ class Geometry:
 
     def set_launch_config(self, tracks_per_lane: int, waves_per_simd: int):
         _check(self._lib.geo_set_launch_config(self._h, int(tracks_per_lane), int(waves_per_simd)))
+
+    @property
+    def batched_graph(self) -> bool:
+        """Whether geo_navigate_batched replays a HIP graph (else two launches)."""
+        v = C.c_int32()
+        _check(self._lib.geo_get_batched_graph(self._h, C.byref(v)))
+        return bool(v.value)
+
+    @batched_graph.setter
+    def batched_graph(self, use_graph: bool):
+        _check(self._lib.geo_set_batched_graph(self._h, 1 if use_graph else 0))
 
     @property
     def culling(self) -> bool:

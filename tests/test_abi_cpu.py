@@ -121,6 +121,9 @@ def test_batched_and_nav_validation_without_device(gv):
     assert lib.geo_navigate_batched(None, None, 0, t, None, None, None) == -1
     assert lib.geo_navigate_backward(None, 0, t, None, None, None, None, None, None, None) == -1
     assert lib.geo_set_launch_config(None, 1, 1) == -1
+    assert lib.geo_set_batched_graph(None, 1) == -1
+    v = C.c_int32()
+    assert lib.geo_get_batched_graph(None, C.byref(v)) == -1
 
 
 def test_binding_rejects_cpu_tensors(gv):

@@ -52,16 +52,24 @@ def batched(gv, g, wl, t):
 
 
 def test_batched_bit_identical_to_per_basket(gv, small):
+    """Every launch shape, with the two kernels as two launches and as a
+    graph replay, equals the per-basket navigator bit for bit."""
     import torch
     g = gv.Geometry(small.volumes)
     t = torch.from_numpy(small.tracks).cuda()
     s0, h0 = per_basket(gv, g, small, t)
-    for U in (1, 2, 4, 8):
-        for Wv in (0, 2, 4, 8):
-            g.set_launch_config(U, Wv)
-            s1, h1 = batched(gv, g, small, t)
-            assert np.array_equal(s1.view(np.int64), s0.view(np.int64)), (U, Wv)
-            assert np.array_equal(h1, h0), (U, Wv)
+    assert not g.batched_graph  # the default: two launches
+    for graph in (False, True):
+        g.batched_graph = graph
+        assert g.batched_graph == graph
+        for U in (1, 2, 4, 8):
+            for Wv in (0, 2, 4, 8):
+                g.set_launch_config(U, Wv)
+                s1, h1 = batched(gv, g, small, t)
+                assert np.array_equal(s1.view(np.int64), s0.view(np.int64)), (graph, U, Wv)
+                assert np.array_equal(h1, h0), (graph, U, Wv)
+    with pytest.raises(gv.GeoError):
+        gv._check(g._lib.geo_set_batched_graph(g.handle, 2))
     g.close()
 
 
@@ -84,11 +92,14 @@ def test_batched_matches_oracle(gv, orc, small):
     g.close()
 
 
-def test_graph_replays_interleaved(gv, small):
-    """Replay the cached graph several times with other device work and host
-    synchronisation in between; every replay equals the first."""
+@pytest.mark.parametrize("graph", [True, False])
+def test_graph_replays_interleaved(gv, small, graph):
+    """Replay the cached graph (or the two launches) several times with other
+    device work and host synchronisation in between; every replay equals
+    the first."""
     import torch
     g = gv.Geometry(small.volumes)
+    g.batched_graph = graph
     t = torch.from_numpy(small.tracks).cuda()
     s0, h0 = batched(gv, g, small, t)
     for rep in range(5):
@@ -210,23 +221,35 @@ def test_autotune_and_cache(gv, small, tmp_path, monkeypatch):
     t = torch.from_numpy(small.tracks).cuda()
     u, w = gv.geo_autotune(g, small.basket_volume, small.basket_offset, small.basket_n, t)
     assert u in (1, 2, 4, 8) and 0 <= w <= 8
+    graph = g.batched_graph
     data = json.loads(path.read_text())
-    assert len(data) == 1 and list(data.values())[0] == [u, w]
+    assert len(data) == 1 and list(data.values())[0] == [u, w, int(graph)]
     g2 = gv.Geometry(small.volumes)
     g2.set_launch_config(1, 1)
+    g2.batched_graph = not graph
     assert gv.geo_autotune(g2, small.basket_volume, small.basket_offset, small.basket_n, t) == (u, w)
+    assert g2.batched_graph == graph
+    # an entry of two numbers (written before the launch mode was tuned)
+    # reads as two launches
+    key = list(data.keys())[0]
+    path.write_text(json.dumps({key: [u, w]}))
+    g2.batched_graph = True
+    assert gv.geo_autotune(g2, small.basket_volume, small.basket_offset, small.basket_n, t) == (u, w)
+    assert not g2.batched_graph
     g.close()
     g2.close()
     assert os.path.exists(path)
 
 
-def test_kernel_timing_events(gv, small):
-    """The graph's timing events around the navigator kernel: a positive
-    duration below the whole call's, the same outputs with them, and a clear
-    error before any timed call."""
+@pytest.mark.parametrize("graph", [False, True])
+def test_kernel_timing_events(gv, small, graph):
+    """The timing events around the navigator kernel (on the stream, or
+    nodes of the graph): a positive duration below the whole call's, the
+    same outputs with them, and a clear error before any timed call."""
     import time
     import torch
     g = gv.Geometry(small.volumes)
+    g.batched_graph = graph
     t = torch.from_numpy(small.tracks).cuda()
     args = (small.basket_volume, small.basket_offset, small.basket_n, t)
     s0, h0 = gv.geo_navigate_batched(g, *args)
