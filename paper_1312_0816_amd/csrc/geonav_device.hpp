@@ -1267,6 +1267,33 @@ __device__ __forceinline__ double daughter_dist_out(const DaughterRec &D, const 
     return any_dist_out<KSET>(D.shape, D.pcon, lx, ly, lz, lux, luy, luz, sid);
 }
 
+// A tile's six track arrays from its first track on: uniform pointers, so
+// that a lane's track, an unsigned index below 1024 off them, is loaded with
+// a scalar base address and a 32-bit vector offset (no 64-bit address per
+// lane and array).
+struct TileTracks {
+    const double *x, *y, *z, *ux, *uy, *uz;
+};
+// element j (< 2^29) of a, its byte offset formed in 32 bits
+template <typename T>
+__device__ __forceinline__ T &at32(T *a, unsigned int j) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(a) + j * (unsigned int)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T &at32(const T *a, unsigned int j) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + j * (unsigned int)sizeof(T));
+}
+__device__ __forceinline__ TileTracks tile_tracks(const TracksDev &t, int64_t base) {
+    TileTracks r;
+    r.x = t.x + base;
+    r.y = t.y + base;
+    r.z = t.z + base;
+    r.ux = t.ux + base;
+    r.uy = t.uy + base;
+    r.uz = t.uz + base;
+    return r;
+}
+
 // A hit slot holds the candidate's index k (-1 for the mother) and the
 // surface that set its step (sid, -1 .. 254) as k * 256 + sid + 1: ordered
 // by k, since each index has one candidate per track, and the adjoint reads
@@ -1326,13 +1353,14 @@ __device__ __forceinline__ void nav_flush(const DaughterRec *__restrict__ dau,
                 uy = lds_load(&S.uy[sl]);
                 uz = lds_load(&S.uz[sl]);
             } else {
-                const int64_t i = base + j;
-                x = t.x[i];
-                y = t.y[i];
-                z = t.z[i];
-                ux = t.ux[i];
-                uy = t.uy[i];
-                uz = t.uz[i];
+                const TileTracks tt = tile_tracks(t, base);
+                const unsigned int ju = (unsigned int)j;
+                x = at32(tt.x, ju);
+                y = at32(tt.y, ju);
+                z = at32(tt.z, ju);
+                ux = at32(tt.ux, ju);
+                uy = at32(tt.uy, ju);
+                uz = at32(tt.uz, ju);
             }
             int sid;
             const double s = daughter_dist_out<HAS_OFFS, KSET>(dau[k], cul[k], offs, k, x, y, z, ux, uy, uz, sid);
@@ -1385,9 +1413,10 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
         const int j = u * 64 + lane;
         const bool act = j < count;
         const unsigned long long amask = __builtin_amdgcn_ballot_w64(act);
-        const int64_t i = base + (act ? j : 0);
-        double x = t.x[i], y = t.y[i], z = t.z[i];
-        double ux = t.ux[i], uy = t.uy[i], uz = t.uz[i];
+        const TileTracks tt = tile_tracks(t, base);
+        const unsigned int ju = act ? (unsigned int)j : 0u;
+        double x = at32(tt.x, ju), y = at32(tt.y, ju), z = at32(tt.z, ju);
+        double ux = at32(tt.ux, ju), uy = at32(tt.uy, ju), uz = at32(tt.uz, ju);
         if (COUNT && lane == 0) atomicAdd(&census[kCensusTracks], (unsigned long long)__popcll(amask));
         int sid;
         const double ms = mother_step<SURF, KSET>(v, x, y, z, ux, uy, uz, sid);
@@ -1464,12 +1493,12 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
                 pend = 0ull;
                 // the track and its test constants are read and formed again
                 // rather than kept live through the flush's evaluations
-                x = t.x[i];
-                y = t.y[i];
-                z = t.z[i];
-                ux = t.ux[i];
-                uy = t.uy[i];
-                uz = t.uz[i];
+                x = at32(tt.x, ju);
+                y = at32(tt.y, ju);
+                z = at32(tt.z, ju);
+                ux = at32(tt.ux, ju);
+                uy = at32(tt.uy, ju);
+                uz = at32(tt.uz, ju);
                 cull_constants(x, y, z, ux, uy, uz, pp, pe, mpx, mpy, mpz, mex, mey, mez);
                 if (!act) pp = __builtin_inf();
             }
@@ -1517,15 +1546,16 @@ __device__ __forceinline__ void nav_write(const NavScratch<U> &S, const TracksDe
     for (int u = 0; u < U; ++u) {
         const int j = u * 64 + lane;
         if (j < count) {
-            const int64_t i = base + j;
+            const unsigned int ju = (unsigned int)j;
             const double s = key_step(lds_load(&S.key[j]));
-            step[i] = s;
-            hit[i] = hit_index(lds_load(&S.hit[j]));
+            at32(step + base, ju) = s;
+            at32(hit + base, ju) = hit_index(lds_load(&S.hit[j]));
             if (HITPT) {
                 const int64_t n = t.n;
-                hitpt[i] = fma(s, t.ux[i], t.x[i]);
-                hitpt[n + i] = fma(s, t.uy[i], t.y[i]);
-                hitpt[2 * n + i] = fma(s, t.uz[i], t.z[i]);
+                const TileTracks tt = tile_tracks(t, base);
+                at32(hitpt + base, ju) = fma(s, at32(tt.ux, ju), at32(tt.x, ju));
+                at32(hitpt + n + base, ju) = fma(s, at32(tt.uy, ju), at32(tt.y, ju));
+                at32(hitpt + 2 * n + base, ju) = fma(s, at32(tt.uz, ju), at32(tt.z, ju));
             }
         }
     }

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KSET == 
         // flush (a wavefront past the basket's end takes part with no tracks)
         __shared__ NavScratch<U> scr[kBlock / 64];
         __shared__ PoolInfo<kBlock / 64> pool;
-        const int wave = threadIdx.x >> 6;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // (uniform)
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         const int64_t left = t.n - base;
         const int count = left <= 0 ? 0 : (left < 64 * U ? (int)left : 64 * U);
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KSET == 
     if constexpr (CULL) {
         // (box, tube and cone only: pooling gains nothing measurable)
         __shared__ NavScratch<U> scr[kBlock / 64];
-        const int wave = threadIdx.x >> 6;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // (uniform)
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         if (base >= t.n) return;
         const int count = t.n - base < 64 * U ? (int)(t.n - base) : 64 * U;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_safety(const VolumeRec *__restri
                                                        double *__restrict__ out) {
     if constexpr (CULL) {
         __shared__ PointScratch<U> scr[kBlock / 64];
-        const int wave = threadIdx.x >> 6;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // (uniform)
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         if (base >= t.n) return;
         const int count = t.n - base < 64 * U ? (int)(t.n - base) : 64 * U;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_locate(const VolumeRec *__restri
                                                        int32_t *__restrict__ out) {
     if constexpr (CULL) {
         __shared__ PointScratch<U> scr[kBlock / 64];
-        const int wave = threadIdx.x >> 6;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // (uniform)
         const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * 64 * U;
         if (base >= t.n) return;
         const int count = t.n - base < 64 * U ? (int)(t.n - base) : 64 * U;
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
     // ints (see below)
     extern __shared__ double s_dyn[];
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int nd = vol->nd;
     const int nj = 3 * nd;
     double *prow = partial ? partial + (size_t)blockIdx.x * nj : nullptr;
