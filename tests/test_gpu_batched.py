@@ -127,6 +127,43 @@ def test_graph_replays_interleaved(gv, small, graph):
     g.close()
 
 
+@pytest.mark.parametrize("shape", [(4, 0), (2, 2)])
+def test_back_to_back_calls_with_different_baskets(gv, small, shape):
+    """Eight calls queued without synchronisation, each on its own basket
+    list (subsets in different orders) and its own outputs, the submission
+    switching between two launches and the graph replay: each call's tile
+    expansion rewrites the handle's tile buffer and (persistent shape) queue
+    cursors, so every call must see its own tiles."""
+    import torch
+    g = gv.Geometry(small.volumes)
+    g.set_launch_config(*shape)
+    t = torch.from_numpy(small.tracks).cuda()
+    s0, h0 = per_basket(gv, g, small, t)
+    nb = len(small.basket_n)
+    idx = np.arange(nb)
+    sels = [idx, idx[::-1], idx[::2], idx[1::3], idx[::-5], np.roll(idx, nb // 3), idx[nb // 2:], idx[:nb // 2][::-1]]
+    graphs = [False, False, True, False, True, True, False, False]
+    n = t.shape[1]
+    outs = []
+    for c, sel in enumerate(sels):
+        g.batched_graph = graphs[c]
+        step = torch.full((n,), -5.0 - c, dtype=torch.float64, device="cuda")
+        hit = torch.full((n,), -5 - c, dtype=torch.int32, device="cuda")
+        gv.geo_navigate_batched(g, small.basket_volume[sel], small.basket_offset[sel], small.basket_n[sel], t,
+                                step, hit)
+        outs.append((sel, step, hit))
+    torch.cuda.synchronize()
+    for c, (sel, step, hit) in enumerate(outs):
+        s, h = step.cpu().numpy(), hit.cpu().numpy()
+        covered = np.zeros(n, bool)
+        for b in sel:
+            covered[small.basket_offset[b]:small.basket_offset[b] + small.basket_n[b]] = True
+        assert np.array_equal(s[covered].view(np.int64), s0[covered].view(np.int64)), c
+        assert np.array_equal(h[covered], h0[covered]), c
+        assert np.all(s[~covered] == -5.0 - c) and np.all(h[~covered] == -5 - c), c
+    g.close()
+
+
 def test_basket_calls_in_a_captured_graph(gv, small):
     """geo_navigate_basket calls captured in one HIP graph (torch.cuda.graph)
     and replayed three times, with output clearing, other device work and
