@@ -459,6 +459,7 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
             {
                 const double rc2 = dr.bound_r * (1.0 + 1e-6) + 1e-6;
                 dr.cull_r2 = rc2 * rc2;
+                dr.cull_r = std::sqrt(dr.cull_r2);
             }
             rc = check_rotation(d.placements[k].rot, what);
             if (rc) return rc;
@@ -473,15 +474,16 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
                 const double tt = dr.tr[0] * dr.tr[0] + dr.tr[1] * dr.tr[1] + dr.tr[2] * dr.tr[2];
                 const double span = 3.0 * mother_r + 2.0 * std::sqrt(tt);
                 const double q = dr.cull_r2 - tt + 64.0 * DBL_EPSILON * span * span;
-                cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], dr.cull_r2, std::sqrt(dr.cull_r2), q});
+                cul.push_back(CullRec{dr.tr[0], dr.tr[1], dr.tr[2], q});
             }
         }
         // pad to whole culling chunks with records that never pass a test
         while ((dau.size() - (size_t)r.first) % kCullChunk != 0) {
             DaughterRec pad;
             std::memset(&pad, 0, sizeof pad);
+            pad.cull_r2 = -HUGE_VAL;  // never passes a test with offsets
             dau.push_back(pad);
-            cul.push_back(CullRec{0.0, 0.0, 0.0, -HUGE_VAL, 0.0, -HUGE_VAL});
+            cul.push_back(CullRec{0.0, 0.0, 0.0, -HUGE_VAL});
         }
     }
     geo_geometry *g = new (std::nothrow) geo_geometry();

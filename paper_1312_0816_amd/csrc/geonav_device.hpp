@@ -81,30 +81,32 @@ struct alignas(16) DaughterRec {
     double rot[9];   // R, row-major
     double tr[3];    // T
     double bound_r;  // radius of a sphere about the local origin holding the shape
-    double cull_r2;  // square of bound_r enlarged by 1e-6 relative + 1e-6 (culling test)
+    // the culling radius (bound_r enlarged by 1e-6 relative + 1e-6) squared
+    // and itself, for the tests with offsets (which form w = p - T
+    // explicitly) and the safety's reach; -infinity and 0 in padding records
+    double cull_r2;
+    double cull_r;
     const PconRec *pcon;  // the polycone's sections (device), or NULL
-    double pad;
     ShapeRec shape;
 };
 static_assert(sizeof(DaughterRec) == 368, "DaughterRec layout");
 
-// Culling record of a daughter, in its own compact array (48 B, so the
+// Culling record of a daughter, in its own compact array (32 B, so the
 // records of a whole volume stay in the scalar cache during the daughter
-// loop): the centre of the bounding sphere in the mother frame (T), the
-// culling radius (bounding radius enlarged by 1e-6 relative + 1e-6) and its
-// square, and the threshold q of the expanded test of the compacted
-// navigator: that test evaluates the squared distance from T to the
-// track's half-line, less |T|^2, as |p|^2 - 2 p.T - b^2 with
-// b = min((p - T).e, 0) and e = d / |d| (1 / |d| to a few ulp); every term
-// is at most (|p| + |T|)^2, so the rounding error is below
-// 16 eps (2 R + 2 |T|)^2 for a track inside the mother (R the mother's
-// bounding radius); q = r2 - |T|^2 + 64 eps (3 R + 2 |T|)^2.
+// loop, and a chunk of four is 128 contiguous bytes, two scalar loads): the
+// centre of the bounding sphere in the mother frame (T) and the threshold q
+// of the expanded test of the compacted navigator: that test evaluates the
+// squared distance from T to the track's half-line, less |T|^2, as
+// |p|^2 - 2 p.T - b^2 with b = min((p - T).e, 0) and e = d / |d| (1 / |d|
+// to a few ulp); every term is at most (|p| + |T|)^2, so the rounding error
+// is below 16 eps (2 R + 2 |T|)^2 for a track inside the mother (R the
+// mother's bounding radius); q = r2 - |T|^2 + 64 eps (3 R + 2 |T|)^2, r2
+// the square of the culling radius. The radius itself and r2 sit in the
+// daughter record.
 struct alignas(16) CullRec {
-    double tx, ty, tz, r2;
-    double r;    // the enlarged radius itself
-    double q;
+    double tx, ty, tz, q;
 };
-static_assert(sizeof(CullRec) == 48, "CullRec layout");
+static_assert(sizeof(CullRec) == 32, "CullRec layout");
 
 struct alignas(16) VolumeRec {
     ShapeRec mother;
@@ -1445,7 +1447,7 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
                 ctx[kk] = Q.tx;
                 cty[kk] = Q.ty;
                 ctz[kk] = Q.tz;
-                clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
+                clim[kk] = HAS_OFFS ? dau[k0 + kk].cull_r2 : Q.q;
                 if (HAS_OFFS) {
                     const int ko = k0 + kk < nd ? k0 + kk : 0;
                     cox[kk] = offs[3 * ko + 0];
@@ -1859,11 +1861,12 @@ __device__ __forceinline__ void point_compact(const VolumeRec &v, const Daughter
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 const CullRec &Q = cul[k0 + kk];
+                const DaughterRec &D = dau[k0 + kk];
                 ctx[kk] = Q.tx;
                 cty[kk] = Q.ty;
                 ctz[kk] = Q.tz;
-                cr[kk] = Q.r;
-                clim[kk] = HAS_OFFS ? Q.r2 : Q.q;
+                cr[kk] = D.cull_r;
+                clim[kk] = HAS_OFFS ? D.cull_r2 : Q.q;
                 if (HAS_OFFS) {
                     const int ko = k0 + kk < nd ? k0 + kk : 0;
                     cox[kk] = offs[3 * ko + 0];
