@@ -314,6 +314,7 @@ struct geo_geometry {
     VolumeRec *d_vols = nullptr;
     DaughterRec *d_dau = nullptr;
     CullRec *d_cull = nullptr;
+    CullRec *d_shift = nullptr;      // a volume's culling records moved by an adjoint call's offsets
     PconRec *d_pcon = nullptr;       // polycone sections of mothers and daughters
     // kinds each volume holds (kSetBasic, kSetSeg, kSetAll) and their union:
     // the navigator kernels are specialised to carry only those
@@ -424,6 +425,7 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
         double mother_r = 0.0;
         int rc = make_shape(d.mother, r.mother, &pc, &mother_r, what);
         if (rc) return rc;
+        r.bound_r = mother_r;
         if (r.mother.kind == kPcon || r.mother.kind == kPcons) {
             pcons.push_back(pc);
             pcon_owner.push_back(iv);
@@ -511,6 +513,10 @@ int geo_geometry_create(const geo_volume_desc *v, int32_t nvol, geo_geometry **o
     if (!cul.empty() && hipMalloc(&g->d_cull, sizeof(CullRec) * cul.size()) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of culling records failed"));
     if (max_nd > 0 &&
+        hipMalloc(&g->d_shift, sizeof(CullRec) * (size_t)((max_nd + kCullChunk - 1) / kCullChunk * kCullChunk)) !=
+            hipSuccess)
+        return cleanup(fail(GEO_ERR_NOMEM, "device allocation of the shifted culling records failed"));
+    if (max_nd > 0 &&
         hipMalloc(&g->d_partial, sizeof(double) * 3 * (size_t)max_nd * kBackwardMaxBlocks) != hipSuccess)
         return cleanup(fail(GEO_ERR_NOMEM, "device allocation of adjoint partials failed"));
     if (hipMalloc(&g->d_cursors, sizeof(unsigned int) * kQueues * kQueueStride) != hipSuccess)
@@ -559,6 +565,7 @@ int geo_geometry_destroy(geo_geometry *g) {
     (void)hipFree(g->d_vols);
     (void)hipFree(g->d_dau);
     (void)hipFree(g->d_cull);
+    (void)hipFree(g->d_shift);
     (void)hipFree(g->d_partial);
     (void)hipFree(g->d_tiles);
     (void)hipFree(g->d_cursors);
@@ -623,7 +630,7 @@ int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, c
     hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
                                    g->d_cull ? g->d_cull + first : nullptr, nd, to_dev(t),
                                    nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, g->d_partial,
-                                   nd > 0 ? g_off : nullptr, g->cull, g->vol_kset[volume], stream);
+                                   nd > 0 ? g_off : nullptr, g->cull, g->vol_kset[volume], g->d_shift, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     return GEO_OK;
 }
@@ -657,7 +664,7 @@ int geo_navigate_backward_noalloc(const geo_geometry *g, int32_t volume, geo_tra
     hipError_t e = launch_backward(g->d_vols + volume, g->d_dau ? g->d_dau + first : nullptr,
                                    g->d_cull ? g->d_cull + first : nullptr, nd, to_dev(t),
                                    nd > 0 ? offsets : nullptr, gstep, ghit, g_o, g_d, part,
-                                   nd > 0 ? g_off : nullptr, g->cull, g->vol_kset[volume], stream);
+                                   nd > 0 ? g_off : nullptr, g->cull, g->vol_kset[volume], nullptr, stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     return GEO_OK;
 }

@@ -113,7 +113,7 @@ struct alignas(16) VolumeRec {
     int32_t nd;     // number of daughters
     int32_t first;  // index of daughter 0 in the daughter and culling tables
     const PconRec *pcon;  // the mother's polycone sections (device), or NULL
-    int32_t pad[2];
+    double bound_r;       // radius of a sphere about the origin holding the mother
 };
 static_assert(sizeof(VolumeRec) == 272, "VolumeRec layout");
 
@@ -1399,12 +1399,22 @@ __device__ __forceinline__ void cull_constants(double x, double y, double z, dou
 //
 // Without FINAL the last flush is left to the caller: the queue's length is
 // returned, its tracks holding slots.
-template <int U, bool HAS_OFFS, bool COUNT, int KSET, bool SURF = true, bool FINAL = true>
+//
+// With SHIFTED (offsets only), the culling tests take their records from
+// `shifted`: the centres moved by this call's offsets and the thresholds of
+// the expanded test for them (k_shift_cull), so that they run as without
+// offsets; the queued pairs still form w = p - T - offset from the
+// unshifted records, as every other form does.
+template <int U, bool HAS_OFFS, bool COUNT, int KSET, bool SURF = true, bool FINAL = true, bool SHIFTED = false>
 __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const DaughterRec *__restrict__ dau,
                                                 const CullRec *__restrict__ cul,
                                                 const double *__restrict__ offs, const TracksDev &t,
                                                 int64_t base, int count, NavScratch<U> &S, int lane,
-                                                unsigned long long *census = nullptr) {
+                                                unsigned long long *census = nullptr,
+                                                const CullRec *__restrict__ shifted = nullptr) {
+    static_assert(!SHIFTED || HAS_OFFS, "shifted culling records go with offsets");
+    constexpr bool EXPLICIT = HAS_OFFS && !SHIFTED;  // tests that form w = p - T - offset
+    const CullRec *__restrict__ tcul = SHIFTED ? shifted : cul;
     int qn = 0;  // queue length (uniform)
     int ns = 0;  // slots in use (uniform)
     const int nd = v.nd;
@@ -1443,12 +1453,12 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
             double cox[kCullChunk], coy[kCullChunk], coz[kCullChunk];
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
-                const CullRec &Q = cul[k0 + kk];
+                const CullRec &Q = tcul[k0 + kk];
                 ctx[kk] = Q.tx;
                 cty[kk] = Q.ty;
                 ctz[kk] = Q.tz;
-                clim[kk] = HAS_OFFS ? dau[k0 + kk].cull_r2 : Q.q;
-                if (HAS_OFFS) {
+                clim[kk] = EXPLICIT ? dau[k0 + kk].cull_r2 : Q.q;
+                if (EXPLICIT) {
                     const int ko = k0 + kk < nd ? k0 + kk : 0;
                     cox[kk] = offs[3 * ko + 0];
                     coy[kk] = offs[3 * ko + 1];
@@ -1460,7 +1470,7 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
 #pragma unroll
             for (int kk = 0; kk < kCullChunk; ++kk) {
                 double b, g;  // w.e and |w|^2 - shift, with w = p - centre
-                if (HAS_OFFS) {
+                if (EXPLICIT) {
                     // the centre moves with the offset: w formed explicitly, shift 0,
                     // limit r2
                     const double wx = x - ctx[kk] - cox[kk];
@@ -1482,7 +1492,7 @@ __device__ __forceinline__ int nav_compact_core(const VolumeRec &v, const Daught
                 // lanes past the tile's end are masked out (the expanded form
                 // excludes them through |p|^2)
                 const unsigned long long pass = __builtin_amdgcn_ballot_w64(f <= lim);
-                cm[kk] = HAS_OFFS ? (pass & amask) : pass;
+                cm[kk] = EXPLICIT ? (pass & amask) : pass;
             }
             if (COUNT && lane == 0)
                 atomicAdd(&census[kCensusCull],

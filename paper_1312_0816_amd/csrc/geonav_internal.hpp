@@ -85,9 +85,13 @@ int backward_blocks(int64_t n);
 constexpr size_t kScratchDoubles = (size_t)kBackwardMaxBlocks * 3 * 64;  // 3 MiB
 hipError_t scratch_partials(double **out);
 
+// shift_buf: room for the volume's culling records (nd rounded up to whole
+// chunks) moved by the offsets, written by a small kernel before the adjoint
+// when culling with offsets; NULL to cull with the offsets applied in every
+// test instead.
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
-                           double *g_off, bool cull, int kset, hipStream_t st);
+                           double *g_off, bool cull, int kset, CullRec *shift_buf, hipStream_t st);
 
 }  // namespace gn

@@ -13,6 +13,8 @@
 //                    of many volumes in one launch, one wavefront per tile;
 //  k_nav_persistent  the same with a machine-sized grid whose wavefronts
 //                    pull tiles from per-XCD queues;
+//  k_shift_cull      a volume's culling records moved by the daughter offsets
+//                    of one adjoint call;
 //  k_nav_backward    adjoint of the navigator (recompute + implicit-function
 //                    gradient of the surface that set the step) with
 //                    per-workgroup partial sums of the offset gradient;
@@ -465,6 +467,36 @@ int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles) {
 }
 
 // ------------------------------------------------------------------ adjoint
+// The volume's culling records moved by this call's daughter offsets, for
+// the adjoint's forward: centre T' = T + offset and the threshold of the
+// expanded test for it, q' = r2 - |T'|^2 + 64 eps (3 R + 2 |T'|)^2 (R the
+// mother's bounding radius), the same bound as the unshifted records'.
+// Padding records are copied (q = -infinity: they never pass). The moved
+// centre differs from T + offset by a rounding, far inside the culling
+// radius's enlargement of 1e-6 relative + 1e-6, so the tests stay
+// conservative for the daughter where the queued pairs place it.
+__global__ __launch_bounds__(kBlock) void k_shift_cull(const VolumeRec *__restrict__ vol,
+                                                       const CullRec *__restrict__ cul,
+                                                       const DaughterRec *__restrict__ dau,
+                                                       const double *__restrict__ offs,
+                                                       CullRec *__restrict__ out) {
+    const int nd = vol->nd;
+    const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
+    const double R = vol->bound_r;
+    for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < ndp; k += (int)(gridDim.x * blockDim.x)) {
+        if (k < nd) {
+            const double tx = cul[k].tx + offs[3 * k + 0];
+            const double ty = cul[k].ty + offs[3 * k + 1];
+            const double tz = cul[k].tz + offs[3 * k + 2];
+            const double tt = tx * tx + ty * ty + tz * tz;
+            const double span = 3.0 * R + 2.0 * fsqrt(tt);
+            out[k] = CullRec{tx, ty, tz, dau[k].cull_r2 - tt + 64.0 * 2.220446049250313e-16 * span * span};
+        } else {
+            out[k] = cul[k];
+        }
+    }
+}
+
 // For each track: recompute the forward step keeping the surface that set it,
 // take that surface's normal n (mother frame) at the hit point and, by the
 // implicit-function theorem on the surface equation,
@@ -474,14 +506,15 @@ int batched_grid(int waves_per_simd, int num_cus, int64_t ntiles) {
 // The offset gradient of the workgroup's tracks is summed per daughter in a
 // fixed lane order into the workgroup's row of `partial`, accumulated over
 // the workgroup's passes in LDS when lds_acc (3 nd doubles; else in the row
-// itself) and written once.
-template <bool HAS_OFFS, bool CULL, int KSET>
+// itself) and written once. With SHIFTED the forward's culling tests read
+// `shifted` (k_shift_cull), the records moved by the offsets.
+template <bool HAS_OFFS, bool CULL, int KSET, bool SHIFTED = false>
 __global__ __launch_bounds__(kBlock) void k_nav_backward(
     const VolumeRec *__restrict__ vol, const DaughterRec *__restrict__ dau,
     const CullRec *__restrict__ cul, TracksDev t, const double *__restrict__ offs,
     const double *__restrict__ gstep,
     const double *__restrict__ ghit, double *__restrict__ g_o, double *__restrict__ g_d,
-    double *__restrict__ partial, bool lds_acc) {
+    double *__restrict__ partial, bool lds_acc, const CullRec *__restrict__ shifted) {
     __shared__ double s_g[3][kBlock];
     __shared__ NavScratch<1> scr[CULL ? kBlock / 64 : 1];
     // [3 nd] doubles of the row's accumulator when lds_acc, then 4 nd + nd + 1
@@ -505,10 +538,15 @@ __global__ __launch_bounds__(kBlock) void k_nav_backward(
             // the forward step and hit by the compacted navigator (per
             // wavefront of 64 tracks)
             const int64_t wbase = base + wave * 64;
-            if (wbase < n)
-                nav_compact_core<1, HAS_OFFS, false, KSET>(*vol, dau, cul, offs, t, wbase,
-                                                           n - wbase < 64 ? (int)(n - wbase) : 64,
-                                                           scr[wave], lane);
+            if (wbase < n) {
+                const int cnt = n - wbase < 64 ? (int)(n - wbase) : 64;
+                if (SHIFTED)
+                    nav_compact_core<1, HAS_OFFS, false, KSET, true, true, SHIFTED>(
+                        *vol, dau, cul, offs, t, wbase, cnt, scr[wave], lane, nullptr, shifted);
+                else
+                    nav_compact_core<1, HAS_OFFS, false, KSET>(*vol, dau, cul, offs, t, wbase, cnt, scr[wave],
+                                                               lane);
+            }
         }
         if (i < n) {
             const double x = t.x[i], y = t.y[i], z = t.z[i];
@@ -671,17 +709,20 @@ template <bool CULL, int KSET>
 static void launch_backward_variant(int nblocks, int nd, const VolumeRec *vol, const DaughterRec *dau,
                                     const CullRec *cul, const TracksDev &t, const double *offs, const double *gstep,
                                     const double *ghit, double *g_o, double *g_d, double *part,
-                                    hipStream_t st) {
+                                    const CullRec *shifted, hipStream_t st) {
     // the offset-gradient sort's counts and runs; the row's accumulator in
     // LDS up to kBackwardLdsAcc daughters (6 KB)
     const bool lds_acc = part && nd <= kBackwardLdsAcc;
     const size_t dyn = (lds_acc ? sizeof(double) * 3 * (size_t)nd : 0) + sizeof(int) * (size_t)(5 * nd + 1);
-    if (offs)
+    if (offs && CULL && shifted)
+        hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET, CULL>), dim3(nblocks), dim3(kBlock), dyn, st, vol, dau,
+                           cul, t, offs, gstep, ghit, g_o, g_d, part, lds_acc, shifted);
+    else if (offs)
         hipLaunchKernelGGL((k_nav_backward<true, CULL, KSET>), dim3(nblocks), dim3(kBlock), dyn, st, vol, dau, cul, t,
-                           offs, gstep, ghit, g_o, g_d, part, lds_acc);
+                           offs, gstep, ghit, g_o, g_d, part, lds_acc, nullptr);
     else
         hipLaunchKernelGGL((k_nav_backward<false, CULL, KSET>), dim3(nblocks), dim3(kBlock), dyn, st, vol, dau, cul, t,
-                           offs, gstep, ghit, g_o, g_d, part, lds_acc);
+                           offs, gstep, ghit, g_o, g_d, part, lds_acc, nullptr);
 }
 
 int backward_blocks(int64_t n) {
@@ -692,16 +733,23 @@ int backward_blocks(int64_t n) {
 hipError_t launch_backward(const VolumeRec *vol, const DaughterRec *dau, const CullRec *cul, int nd,
                            const TracksDev &t, const double *offs, const double *gstep,
                            const double *ghit, double *g_o, double *g_d, double *partial,
-                           double *g_off, bool cull, int kset, hipStream_t st) {
+                           double *g_off, bool cull, int kset, CullRec *shift_buf, hipStream_t st) {
     const int nblocks = backward_blocks(t.n);
     double *part = (g_off && nd > 0) ? partial : nullptr;
     if (t.n > 0 || part) {
+        const CullRec *shifted = nullptr;
+        if (cull && offs && shift_buf && nd > 0 && t.n > 0) {
+            const int ndp = (nd + kCullChunk - 1) / kCullChunk * kCullChunk;
+            hipLaunchKernelGGL(k_shift_cull, dim3((ndp + kBlock - 1) / kBlock), dim3(kBlock), 0, st, vol, cul, dau,
+                               offs, shift_buf);
+            shifted = shift_buf;
+        }
         if (cull)
             GN_KSET(kset, (launch_backward_variant<true, KS>(nblocks, nd, vol, dau, cul, t, offs, gstep, ghit,
-                                                             g_o, g_d, part, st)));
+                                                             g_o, g_d, part, shifted, st)));
         else
             GN_KSET(kset, (launch_backward_variant<false, KS>(nblocks, nd, vol, dau, cul, t, offs, gstep, ghit,
-                                                              g_o, g_d, part, st)));
+                                                              g_o, g_d, part, nullptr, st)));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
