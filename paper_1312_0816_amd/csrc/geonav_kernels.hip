@@ -4,7 +4,9 @@
 //                    streaming, one lane per track, HBM-bound (the polycone
 //                    and the cone segment's Safety are ALU-bound).
 //  k_nav_basket      the simple navigator (section 3, Fig. 1b) over one
-//                    basket; FP64-ALU-bound (every lane walks every daughter).
+//                    basket: culling tests in lockstep queue (track, daughter)
+//                    pairs in LDS, evaluated one pair per lane; bound by VALU
+//                    issue (with culling off, every lane walks every daughter).
 //  k_nav_safety      the navigator's isotropic safety (section 3) per point;
 //  k_nav_locate      the daughter holding each point (localization);
 //  k_build_tiles     expands a host-sorted basket list into tiles of at most
