@@ -199,18 +199,22 @@ int geo_navigate_batched(geo_geometry *g, const geo_basket *baskets, int32_t nb,
  * Tracks whose step is 0 (outside the mother or inside a daughter) or that
  * never reach a boundary contribute 0. At a non-smooth point (an edge, a tie
  * between volumes) the gradient of the surface the forward pass picked is
- * used. Calls on one handle share a partial-sum buffer: they must be
- * stream-ordered (no concurrent backward calls on one handle). */
+ * used. With offsets and culling, a small kernel first writes the volume's
+ * culling records moved by the offsets into a buffer of the handle, which
+ * the forward pass's culling tests read. Calls on one handle share that
+ * buffer and a partial-sum buffer: they must be stream-ordered (no
+ * concurrent backward calls on one handle). */
 int geo_navigate_backward(const geo_geometry *g, int32_t volume, geo_tracks t, const double *offsets,
                           const double *gstep, const double *ghit, double *g_o, double *g_d,
                           double *g_off, hipStream_t stream);
 
 /* geo_navigate_backward for callers that cannot allocate memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid it): the
- * same arguments, kernels and results (bit for bit), but the partial sums of
- * the offset gradient live in a static device buffer of the library (3 MiB,
- * one per GPU, held until the process ends) instead of the handle's, and
- * the call allocates nothing. The buffer holds 2048 * 3 * 64 doubles: any
+ * same arguments and results (bit for bit), but the partial sums of the
+ * offset gradient live in a static device buffer of the library (3 MiB, one
+ * per GPU, held until the process ends) instead of the handle's, the
+ * culling tests apply the offsets themselves (no shifted records are
+ * written into the handle), and the call allocates nothing. The buffer holds 2048 * 3 * 64 doubles: any
  * track count with up to 64 daughters; with more, a call whose partial sums
  * (min(ceil(n / 256), 2048) rows of 3 * ndaughters) do not fit fails with
  * GEO_ERR_INVALID_ARG before launching anything. Every call on one GPU shares

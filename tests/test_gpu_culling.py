@@ -57,14 +57,19 @@ def test_batched_culling_bit_identical(gv):
     g.close()
 
 
-def test_backward_culling_bit_identical(gv):
+@pytest.mark.parametrize("shift", [0.0, 5.0])
+def test_backward_culling_bit_identical(gv, shift):
+    """The adjoint with culling on and off, with zero offsets and with
+    offsets of up to 5 in each coordinate (the culled forward then tests
+    the culling records moved by the offsets)."""
     import torch
     vol, tr, tgt = W.adjoint_c4(n=200000)
     g = gv.Geometry([vol])
     o = torch.from_numpy(np.ascontiguousarray(tr[:3])).cuda()
     d = torch.from_numpy(np.ascontiguousarray(tr[3:])).cuda()
     gh = torch.from_numpy(np.ascontiguousarray(tgt)).cuda()
-    offs = torch.zeros((vol.nd, 3), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(11)
+    offs = torch.from_numpy(rng.uniform(-shift, shift, (vol.nd, 3))).cuda()
     out = {}
     for cull in (True, False):
         g.culling = cull
