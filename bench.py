@@ -294,7 +294,9 @@ def basket_scan(gv, W, dev):
     """The paper's benchmark protocol on its toy detector: P baskets of N
     consecutive particles from a random start in a 2^20-track pool, N x P =
     2^20 fixed; runtime per particle for one launch per basket and for all
-    baskets in one batched launch (N x P = 2^20)."""
+    baskets in one batched launch (N x P = 2^20), in pool order (neighbouring
+    baskets are joined into full wavefronts) and in a random order (each
+    basket tiled on its own)."""
     import torch
     vol = W.paper_toy_detector()
     pool = W.paper_toy_tracks(n=1 << 21)
@@ -316,6 +318,13 @@ def basket_scan(gv, W, dev):
         # buffers grows it to this basket count
         ms_b = _time_ms(lambda: gv._check(lib.geo_navigate_batched(g.handle, barr, nb, tr, sp, hp, hs)),
                         reps=10, warm=20)
+        # the same baskets in a random order: no two neighbours in the list
+        # follow one another in the pool, so none is joined to the next and
+        # every basket's last wavefront runs part empty
+        perm = np.random.default_rng(1502 + N).permutation(P)
+        barr_s, nb_s = gv._baskets(np.zeros(P, np.int32), offs[perm], np.full(P, N))
+        ms_s = _time_ms(lambda: gv._check(lib.geo_navigate_batched(g.handle, barr_s, nb_s, tr, sp, hp, hs)),
+                        reps=10, warm=20)
         plain = [(gv.GeoTracks(tr.x + 8 * o, tr.y + 8 * o, tr.z + 8 * o, tr.ux + 8 * o, tr.uy + 8 * o,
                                tr.uz + 8 * o, N),
                   gv.C.c_void_p(step.data_ptr() + 8 * o), gv.C.c_void_p(hit.data_ptr() + 4 * o))
@@ -328,6 +337,7 @@ def basket_scan(gv, W, dev):
         ms_p = _time_ms(run_plain, reps=1 if P > 1024 else 3, warm=1 if P <= 4096 else 0)
         out[str(N)] = {"baskets": P,
                        "batched_ns_per_particle": ms_b * 1e6 / SCAN_TOTAL,
+                       "batched_shuffled_ns_per_particle": ms_s * 1e6 / SCAN_TOTAL,
                        "per_basket_launches_ns_per_particle": ms_p * 1e6 / SCAN_TOTAL}
     g.close()
     return out

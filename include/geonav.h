@@ -179,7 +179,10 @@ int geo_locate(const geo_geometry *g, int32_t volume, geo_tracks t, const double
  * indexing into the shared pool `all`; step and hit are indexed like the
  * pool (entry offset + j for track j of a basket); pool entries not covered
  * by any basket are left untouched. Results are bit-identical to
- * geo_navigate_basket on each basket with offsets = NULL.
+ * geo_navigate_basket on each basket with offsets = NULL. Baskets of one
+ * volume given one after another whose tracks follow one another in the
+ * pool are navigated as one (their tiles fill whole wavefronts across the
+ * basket boundaries); that changes no output.
  * The handle keeps per-call state (tile buffer, graph, a ring of pinned
  * staging buffers): calls on one handle must come from one host thread at a
  * time and be ordered on the device (the same stream, or streams the caller

@@ -781,6 +781,20 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
     for (int i = 0; i < nb; ++i)
         if (b[i].n > 0) s[cnt[g->max_nd - g->h_vols[b[i].volume].nd]++] = BasketRec{b[i].volume, 0, b[i].offset, b[i].n};
     if (ns == 0) return GEO_OK;
+    // baskets of one volume that follow one another in this order and whose
+    // tracks follow one another in the pool are joined, so that their tiles
+    // fill whole wavefronts across the basket boundaries (results are per
+    // track, so the outputs are the same)
+    int nm = 0;
+    for (int i = 0; i < ns; ++i) {
+        BasketRec &last = s[nm > 0 ? nm - 1 : 0];
+        if (nm > 0 && last.volume == s[i].volume && last.offset + last.n == s[i].offset)
+            last.n += s[i].n;
+        else
+            s[nm++] = s[i];
+    }
+    ns = nm;
+    s.resize((size_t)ns);
     int64_t ntiles = 0;
     for (const BasketRec &r : s) ntiles += (r.n + tile_n - 1) / tile_n;
     if (ntiles > 0x7fffffff) return fail(GEO_ERR_INVALID_ARG, "too many tiles");

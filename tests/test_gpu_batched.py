@@ -164,6 +164,48 @@ def test_back_to_back_calls_with_different_baskets(gv, small, shape):
     g.close()
 
 
+def test_contiguous_baskets_joined(gv, small):
+    """Each basket cut into contiguous pieces of random sizes: given in
+    order, the pieces of a basket are joined back before tiling; shuffled,
+    they are not. Both equal the per-basket navigator bit for bit, as does
+    a single-volume pool cut into 16-track baskets (the paper's scan at its
+    smallest basket size)."""
+    import torch
+    g = gv.Geometry(small.volumes)
+    t = torch.from_numpy(small.tracks).cuda()
+    s0, h0 = per_basket(gv, g, small, t)
+    rng = np.random.default_rng(17)
+    vol, off, cnt = [], [], []
+    for b in range(len(small.basket_n)):
+        o, m = int(small.basket_offset[b]), int(small.basket_n[b])
+        cuts = np.sort(rng.choice(np.arange(1, m), size=min(m - 1, 3), replace=False)) if m > 1 else []
+        edges = [0, *[int(c) for c in cuts], m]
+        for a, e in zip(edges[:-1], edges[1:]):
+            vol.append(int(small.basket_volume[b]))
+            off.append(o + a)
+            cnt.append(e - a)
+    vol, off, cnt = np.array(vol, np.int32), np.array(off, np.int64), np.array(cnt, np.int64)
+    for order in (np.arange(len(vol)), rng.permutation(len(vol))):
+        s, h = gv.geo_navigate_batched(g, vol[order], off[order], cnt[order], t)
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy().view(np.int64), s0.view(np.int64))
+        assert np.array_equal(h.cpu().numpy(), h0)
+    g.close()
+    # one volume, 16-track baskets back to back
+    vol1 = small.volumes[int(np.argmax([v.nd for v in small.volumes]))]
+    g1 = gv.Geometry([vol1])
+    n = 16 * 1000 + 7
+    tr = torch.from_numpy(W.tracks_in_mother(np.random.default_rng(18), vol1, n)).cuda()
+    offs = np.arange(0, n, 16, dtype=np.int64)
+    cnts = np.minimum(16, n - offs)
+    s1, h1 = gv.geo_navigate_batched(g1, np.zeros(len(offs), np.int32), offs, cnts, tr)
+    s2, h2 = gv.geo_navigate_basket(g1, 0, tr)
+    torch.cuda.synchronize()
+    assert np.array_equal(s1.cpu().numpy().view(np.int64), s2.cpu().numpy().view(np.int64))
+    assert np.array_equal(h1.cpu().numpy(), h2.cpu().numpy())
+    g1.close()
+
+
 def test_basket_calls_in_a_captured_graph(gv, small):
     """geo_navigate_basket calls captured in one HIP graph (torch.cuda.graph)
     and replayed three times, with output clearing, other device work and
