@@ -360,6 +360,7 @@ struct geo_geometry {
     bool ktime_recorded = false;
     hipEvent_t kt_before = nullptr, kt_after = nullptr;
     std::vector<BasketRec> sorted;   // reused host scratch
+    std::vector<BasketRec> joined, sort_tmp;
     std::vector<int> sort_count;
 };
 
@@ -764,37 +765,40 @@ int launch_batched(geo_geometry *g, const geo_basket *b, int32_t nb, const geo_t
                    int32_t *hit, hipStream_t stream, unsigned long long *census = nullptr) {
     const int U = g->tracks_per_lane;
     const int tile_n = 64 * U;
+    // Baskets of one volume that follow one another in the list and whose
+    // tracks follow one another in the pool are joined, so that their tiles
+    // fill whole wavefronts across the basket boundaries (results are per
+    // track, so the outputs are the same): once in the order given (which
+    // takes a list of many small consecutive baskets down to a few before
+    // the sort), and again in the sorted order.
+    auto join = [](const BasketRec &r, std::vector<BasketRec> &out) {
+        BasketRec *last = out.empty() ? nullptr : &out.back();
+        if (last && last->volume == r.volume && last->offset + last->n == r.offset)
+            last->n += r.n;
+        else
+            out.push_back(r);
+    };
+    std::vector<BasketRec> &in = g->joined;
+    in.clear();
+    in.reserve((size_t)nb);
+    for (int i = 0; i < nb; ++i)
+        if (b[i].n > 0) join(BasketRec{b[i].volume, 0, b[i].offset, b[i].n}, in);
+    if (in.empty()) return GEO_OK;
     // cost-sorted basket list (per-track cost ~ daughters + mother): a
     // stable counting sort on the daughter count, descending (O(nb), which
     // matters for tens of thousands of small baskets)
     std::vector<BasketRec> &s = g->sorted;
     std::vector<int> &cnt = g->sort_count;
     cnt.assign((size_t)g->max_nd + 2, 0);
-    int ns = 0;
-    for (int i = 0; i < nb; ++i)
-        if (b[i].n > 0) {
-            ++cnt[g->max_nd - g->h_vols[b[i].volume].nd + 1];
-            ++ns;
-        }
+    for (const BasketRec &r : in) ++cnt[g->max_nd - g->h_vols[r.volume].nd + 1];
     for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
-    s.resize((size_t)ns);
-    for (int i = 0; i < nb; ++i)
-        if (b[i].n > 0) s[cnt[g->max_nd - g->h_vols[b[i].volume].nd]++] = BasketRec{b[i].volume, 0, b[i].offset, b[i].n};
-    if (ns == 0) return GEO_OK;
-    // baskets of one volume that follow one another in this order and whose
-    // tracks follow one another in the pool are joined, so that their tiles
-    // fill whole wavefronts across the basket boundaries (results are per
-    // track, so the outputs are the same)
-    int nm = 0;
-    for (int i = 0; i < ns; ++i) {
-        BasketRec &last = s[nm > 0 ? nm - 1 : 0];
-        if (nm > 0 && last.volume == s[i].volume && last.offset + last.n == s[i].offset)
-            last.n += s[i].n;
-        else
-            s[nm++] = s[i];
-    }
-    ns = nm;
-    s.resize((size_t)ns);
+    std::vector<BasketRec> &tmp = g->sort_tmp;
+    tmp.resize(in.size());
+    for (const BasketRec &r : in) tmp[cnt[g->max_nd - g->h_vols[r.volume].nd]++] = r;
+    s.clear();
+    s.reserve(tmp.size());
+    for (const BasketRec &r : tmp) join(r, s);
+    const int ns = (int)s.size();
     int64_t ntiles = 0;
     for (const BasketRec &r : s) ntiles += (r.n + tile_n - 1) / tile_n;
     if (ntiles > 0x7fffffff) return fail(GEO_ERR_INVALID_ARG, "too many tiles");
