@@ -60,7 +60,8 @@ static_assert(sizeof(ShapeRec) == 240, "ShapeRec layout");
 // present when bit j of hole_mask is set: not both inner radii 0).
 constexpr int kPconMax = 8;
 // The daughter and culling tables hold each volume's records padded to a
-// multiple of kCullChunk; padding records have r2 = q = -infinity, so that
+// multiple of kCullChunk; padding records have q (culling record) and
+// cull_r2 (daughter record) = -infinity, so that
 // no culling test passes them.
 constexpr int kCullChunk = 4;
 struct alignas(16) PconRec {
