@@ -167,9 +167,9 @@ def test_back_to_back_calls_with_different_baskets(gv, small, shape):
 def test_contiguous_baskets_joined(gv, small):
     """Each basket cut into contiguous pieces of random sizes: given in
     order, the pieces of a basket are joined back before tiling; shuffled,
-    they are not. Both equal the per-basket navigator bit for bit, as does
-    a single-volume pool cut into 16-track baskets (the paper's scan at its
-    smallest basket size)."""
+    only pieces that happen to meet again after the sort are. Both equal
+    the per-basket navigator bit for bit, as does a single-volume pool cut
+    into 16-track baskets (the paper's scan at its smallest basket size)."""
     import torch
     g = gv.Geometry(small.volumes)
     t = torch.from_numpy(small.tracks).cuda()
