@@ -238,8 +238,10 @@ def test_tangent_to_culling_spheres_in_a_large_mother(gv, orc):
 def test_the_largest_volume(gv, orc):
     """A volume with the most daughters the library accepts (1024 boxes on a
     16 x 16 x 4 grid): basket and batched navigation with culling on and
-    off, safety and localization on and off, the adjoint on and off (its
-    offset-gradient sort holds 1024 bins), and the oracle on a sample."""
+    off, safety and localization on and off, the adjoint on and off with
+    daughter offsets up to 1 in each coordinate (its offset-gradient sort
+    holds 1024 bins; the culled forward tests 1024 shifted culling
+    records), and the oracle on a sample."""
     import torch
     n_d = gv.GEO_MAX_DAUGHTERS
     ii = np.arange(n_d)
@@ -257,7 +259,7 @@ def test_the_largest_volume(gv, orc):
     p = torch.from_numpy(np.ascontiguousarray(tr[:3])).cuda()
     d = torch.from_numpy(np.ascontiguousarray(tr[3:])).cuda()
     gh = torch.from_numpy(rng.normal(size=(3, tr.shape[1]))).cuda()
-    offs = torch.zeros((n_d, 3), dtype=torch.float64, device="cuda")
+    offs = torch.from_numpy(rng.uniform(-1.0, 1.0, (n_d, 3))).cuda()
     out = {}
     for cull in (True, False):
         g.culling = cull
